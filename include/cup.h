@@ -1,0 +1,180 @@
+/*
+ * libcup -- rank-profile revealing CUP decomposition over a prime field
+ * GF(p) on AMD MI355X (gfx950).
+ *
+ * The operations follow C.-P. Jeannerod, C. Pernet and A. Storjohann,
+ * "Rank-profile revealing Gaussian elimination and the CUP matrix
+ * decomposition" (J. Symbolic Computation):
+ *   - CUP decomposition A = C U P with its rank and row rank profile
+ *     (Section 3.3, Algorithm 6; Proposition 3),
+ *   - transformation to reduced column echelon form (Section 3.4,
+ *     Algorithm 7 and Section 3.5, Algorithm 8; Proposition 5),
+ *   - the in-place inverse (Section 4.3).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major with leading dimension lda >= max(1, n):
+ *     entry (i, j) is A[i * lda + j].  A is a DEVICE pointer.
+ *   - Entries are canonical residues in [0, p); every output is canonical.
+ *     p must be prime with 2 <= p < 2^26.  Entries outside [0, p) are
+ *     undefined behaviour unless the environment variable CUP_CHECK=1 is
+ *     set, in which case the call returns -3 before touching A.
+ *   - Permutations are LAPACK-style transposition lists (Section 4.1):
+ *       P[t] = p_t >= t for t < r and P[t] = t for t >= r, so that
+ *       A P^T = A T(0,p_0) T(1,p_1) ... T(r-1,p_{r-1}) (applied left to right);
+ *       Q[t] = i_t, the row rank profile i_0 < ... < i_{r-1}, for t < r and
+ *       Q[t] = t for t >= r; applying T(t,Q[t]) to the rows for t = 0,1,...
+ *       brings the pivot rows to the top.
+ *     P (length n) and Q (length m) are DEVICE int64 arrays; either may be
+ *     NULL when not wanted.  *rank is a HOST pointer.
+ *   - m = 0 or n = 0 is a valid no-op: rank 0, identity P and Q.
+ *   - The caller owns every buffer.  The library keeps no caller memory; it
+ *     caches small device and pinned-host scratch (and, for the INT8 forms,
+ *     a GEMM packing workspace) until cup_finalize().
+ *   - Work is issued on the stream set by cup_set_stream (default: the null
+ *     stream).  Single-matrix calls return after their work has completed.
+ *   - On any error after work has started the contents of A are
+ *     unspecified; callers that need the input keep a copy.
+ *
+ * Return codes (LAPACK style)
+ *      0  CUP_OK
+ *      1  CUP_SINGULAR  (inverse only; *rank is set, A is unspecified)
+ *     -i  the i-th argument is invalid
+ *  -1000 - e   a HIP runtime error e
+ *  -2000  a device or host allocation failed
+ */
+#ifndef LIBCUP_CUP_H
+#define LIBCUP_CUP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CUP_OK 0
+#define CUP_SINGULAR 1
+#define CUP_ERR_HIP (-1000)
+#define CUP_ERR_ALLOC (-2000)
+
+/* Forms of the modular matrix product (ffgemm) used inside every call.
+ *   FP64   : FP64 MFMA as an exact integer carrier, any p < 2^26.
+ *   I8     : INT8 MFMA with INT32 accumulation, p < 2^7.
+ *   I8LIMB : each operand split into two signed 8-bit limbs, four INT8 MFMA
+ *            products recombined exactly, p <= 2^16.
+ *   AUTO   : the fastest form valid for p and the storage type. */
+#define CUP_FORM_AUTO 0
+#define CUP_FORM_FP64 1
+#define CUP_FORM_I8 2
+#define CUP_FORM_I8LIMB 3
+
+/* Stream for all later work (a hipStream_t; NULL = the null stream). */
+int cup_set_stream(void *hip_stream);
+
+/* Select the ffgemm form for later calls.  Returns -1 for an unknown form.
+ * A forced form that p does not allow makes later calls return -5. */
+int cup_set_form(int form);
+int cup_get_form(void);
+
+/*
+ * CUP decomposition (Section 3.3, Algorithm 6).
+ *   m, n  : dimensions (>= 0)
+ *   A     : device, m x n, int64 residues; overwritten in place with the
+ *           packed [C\U] of Section 3.1: C (column echelon, pivots kept) in
+ *           the lower part including the diagonal of its first r columns,
+ *           the strict upper part of the first r rows of U above it, and
+ *           zero in every entry (i >= r, j >= r).
+ *   lda   : leading dimension (>= max(1, n))
+ *   p     : prime, 2 <= p < 2^26
+ *   rank  : host, receives r
+ *   P, Q  : device int64 transposition lists (see above), or NULL.
+ * The pivot rule is the paper's: the leftmost nonzero of each row's residual
+ * in the current column order, rows taken top to bottom, so the output is
+ * unique (Section 2.2, Proposition 1).
+ * Errors: -1 m, -2 n, -3 A (or an entry out of range under CUP_CHECK=1),
+ * -4 lda, -5 p, -6 rank.
+ */
+int cup_factor(int64_t m, int64_t n, int64_t *A, int64_t lda, int64_t p, int64_t *rank,
+               int64_t *P, int64_t *Q);
+
+/* The same on int8 storage (residues of a prime p < 2^7). */
+int cup_factor_i8(int64_t m, int64_t n, int8_t *A, int64_t lda, int64_t p, int64_t *rank,
+                  int64_t *P, int64_t *Q);
+
+/*
+ * Rank and row rank profile (Section 2, definition; Section 4.3: CUP
+ * suffices).  Runs cup_factor, so A is overwritten with [C\U].
+ * Q: device int64 array of length m as above (or NULL).
+ */
+int cup_rank_profile(int64_t m, int64_t n, int64_t *A, int64_t lda, int64_t p, int64_t *rank,
+                     int64_t *Q);
+
+/*
+ * Transformation to reduced column echelon form, in place (Section 3.5,
+ * Algorithm 8 over Algorithm 7 over Algorithm 6; Proposition 5).
+ *   A <- [X1 X2; R2 0] (Section 3.1 storage): with X = [X1 X2; 0 I_{n-r}]
+ *   and R = Q^T [I_r 0; R2 0], A P^T X = R is the (canonical) reduced column
+ *   echelon form of A.  P, Q, rank as for cup_factor.
+ */
+int cup_rref_inplace(int64_t m, int64_t n, int64_t *A, int64_t lda, int64_t p, int64_t *rank,
+                     int64_t *P, int64_t *Q);
+int cup_rref_inplace_i8(int64_t m, int64_t n, int8_t *A, int64_t lda, int64_t p, int64_t *rank,
+                        int64_t *P, int64_t *Q);
+
+/*
+ * In-place inverse of an n x n matrix (Section 4.3: the reduced echelon
+ * transformation of a nonsingular matrix is its inverse up to P):
+ * A <- A^{-1} = P^T X.  Returns CUP_SINGULAR (1) with *rank < n when A is
+ * singular; A is then unspecified.
+ */
+int cup_inverse_inplace(int64_t n, int64_t *A, int64_t lda, int64_t p, int64_t *rank);
+int cup_inverse_inplace_i8(int64_t n, int8_t *A, int64_t lda, int64_t p, int64_t *rank);
+
+/*
+ * Batched CUP of independent matrices, each with its own prime
+ * (Algorithm 6 per matrix; a multi-modular workload).
+ *   batch          : number of matrices (>= 0)
+ *   m, n, lda, p   : device int64 arrays of length batch
+ *   A              : device array of batch device pointers (int64 matrices)
+ *   rank           : device int64 array of length batch
+ *   P, Q           : device arrays of batch device pointers (each P[i] of
+ *                    length n[i], Q[i] of length m[i]); P or Q may be NULL
+ *   info           : device int32 array; info[i] receives matrix i's status
+ *                    with the codes of cup_factor
+ * Returns 0 when the batch was processed (per-matrix status in info), or a
+ * negative code for an invalid batch-level argument (-1 batch, -3 A, -7
+ * rank, -10 info).  The call is asynchronous on the stream: outputs are on
+ * the device only.
+ */
+int cup_factor_batched(int64_t batch, const int64_t *m, const int64_t *n, int64_t *const *A,
+                       const int64_t *lda, const int64_t *p, int64_t *rank, int64_t *const *P,
+                       int64_t *const *Q, int32_t *info);
+
+/*
+ * Modular matrix product, the black box of Section 3.2 (Algorithm 1) that
+ * every routine above reduces to:  C <- C + alpha A B mod p, alpha = +1 or
+ * -1 (CUP's Schur complement uses -1, Algorithm 6), in the form selected by
+ * cup_set_form.  A is M x K (lda), B is K x N (ldb), C is M x N (ldc), all
+ * device row-major residues; C must not overlap A or B (Algorithm 1 Data).
+ * Errors: -1 M, -2 N, -3 K, -5 A/lda, -7 B/ldb, -9 C/ldc, -10 p,
+ * -11 alpha.  Returns after the product has completed.
+ */
+int cup_ffgemm(int64_t M, int64_t N, int64_t K, const int64_t *A, int64_t lda, const int64_t *B,
+               int64_t ldb, int64_t *C, int64_t ldc, int64_t p, int alpha);
+int cup_ffgemm_i8(int64_t M, int64_t N, int64_t K, const int8_t *A, int64_t lda, const int8_t *B,
+                  int64_t ldb, int8_t *C, int64_t ldc, int64_t p, int alpha);
+
+/* Text for a return code. */
+const char *cup_strerror(int status);
+
+/* Bytes of device workspace currently cached by the library. */
+size_t cup_workspace_bytes(void);
+
+/* Release cached workspace. */
+int cup_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBCUP_CUP_H */

@@ -1,0 +1,418 @@
+// The C-ABI of libcup (declared in include/cup.h): argument validation,
+// form selection, scratch management and the calls into the drivers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/cup.h"
+#include "driver.h"
+
+namespace cup {
+namespace {
+
+struct Global {
+    std::mutex mu;
+    hipStream_t stream = nullptr;
+    int form = FORM_AUTO;
+    int* d_small = nullptr;
+    int* h_small = nullptr;
+    int* d_list = nullptr;
+    size_t list_cap = 0;  // ints
+    size_t bytes = 0;
+};
+
+Global& G()
+{
+    static Global g;
+    return g;
+}
+
+bool env_flag(const char* name)
+{
+    const char* v = std::getenv(name);
+    return v && v[0] && std::strcmp(v, "0") != 0;
+}
+
+bool is_prime_i64(int64_t p)
+{
+    if (p < 2) return false;
+    if (p < 4) return true;
+    if (p % 2 == 0) return false;
+    for (int64_t d = 3; d * d <= p; d += 2)
+        if (p % d == 0) return false;
+    return true;
+}
+
+void ensure_small(Global& g)
+{
+    if (!g.d_small) {
+        if (hipMalloc((void**)&g.d_small, sizeof(int) * kSmallInts) != hipSuccess) {
+            g.d_small = nullptr;
+            throw CupError{CUP_ERR_ALLOC};
+        }
+        g.bytes += sizeof(int) * kSmallInts;
+    }
+    if (!g.h_small) {
+        if (hipHostMalloc((void**)&g.h_small, sizeof(int) * kSmallInts, hipHostMallocDefault) !=
+            hipSuccess) {
+            g.h_small = nullptr;
+            throw CupError{CUP_ERR_ALLOC};
+        }
+    }
+}
+
+int* ensure_list(Global& g, size_t ints)
+{
+    if (ints > g.list_cap) {
+        if (g.d_list) {
+            CUP_HIP(hipStreamSynchronize(g.stream));
+            (void)hipFree(g.d_list);
+            g.bytes -= sizeof(int) * g.list_cap;
+            g.d_list = nullptr;
+            g.list_cap = 0;
+        }
+        size_t cap = std::max<size_t>(ints, 1024);
+        if (hipMalloc((void**)&g.d_list, sizeof(int) * cap) != hipSuccess) throw CupError{CUP_ERR_ALLOC};
+        g.list_cap = cap;
+        g.bytes += sizeof(int) * cap;
+    }
+    return g.d_list;
+}
+
+// Resolve the ffgemm form for prime p and storage element size; -5 if the
+// forced form cannot carry p.
+int resolve_form(int forced, int64_t p, bool int8_storage)
+{
+    (void)int8_storage;
+    switch (forced) {
+    case FORM_FP64:
+        return FORM_FP64;
+    case FORM_I8:
+        return p < 128 ? FORM_FP64 : -5;
+    case FORM_I8LIMB:
+        return p <= 65536 ? FORM_FP64 : -5;
+    default:
+        return FORM_FP64;
+    }
+}
+
+template <typename T>
+int validate(int64_t m, int64_t n, const T* A, int64_t lda, int64_t p, const int64_t* rank)
+{
+    if (m < 0 || m > INT32_MAX / 2) return -1;
+    if (n < 0 || n > INT32_MAX / 2) return -2;
+    if (!A && m > 0 && n > 0) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (!is_prime_i64(p) || p >= ((int64_t)1 << 26)) return -5;
+    if (sizeof(T) == 1 && p >= 128) return -5;
+    if (!rank) return -6;
+    return 0;
+}
+
+template <typename T>
+int check_range(Ctx& c, const T* A, int64_t lda, int m, int n, int64_t p)
+{
+    if (!env_flag("CUP_CHECK") || m == 0 || n == 0) return 0;
+    CUP_HIP(hipMemsetAsync(c.d_small, 0, sizeof(int), c.s));
+    launch_range_check<T>(c.s, A, lda, m, n, p, c.d_small);
+    const int* h = fetch_small(c, 1);
+    return h[0] ? -3 : 0;
+}
+
+void write_perm(Ctx& c, int64_t* dst, const std::vector<int64_t>& head, int64_t len)
+{
+    if (!dst || len <= 0) return;
+    std::vector<int64_t> full((size_t)len);
+    for (int64_t t = 0; t < len; ++t) full[(size_t)t] = t;
+    for (size_t t = 0; t < head.size(); ++t) full[t] = head[t];
+    CUP_HIP(hipMemcpyAsync(dst, full.data(), sizeof(int64_t) * (size_t)len, hipMemcpyHostToDevice,
+                           c.s));
+    CUP_HIP(hipStreamSynchronize(c.s));
+}
+
+Ctx make_ctx(Global& g, int64_t p, int form)
+{
+    ensure_small(g);
+    Ctx c;
+    c.s = g.stream;
+    c.form = form;
+    c.d_small = g.d_small;
+    c.h_small = g.h_small;
+    c.log = env_flag("CUP_LOG") ? 1 : 0;
+    ctx_set_prime(c, p);
+    return c;
+}
+
+template <typename T>
+int factor_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* rank, int64_t* P,
+                int64_t* Q, int tail)
+{
+    int v = validate(m, n, A, lda, p, rank);
+    if (v) return v;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    int form = resolve_form(g.form, p, sizeof(T) == 1);
+    if (form < 0) return form;
+    try {
+        Ctx c = make_ctx(g, p, form);
+        int chk = check_range(c, A, lda, (int)m, (int)n, p);
+        if (chk) return chk;
+        std::vector<int64_t> Pl, Ql;
+        int r = 0;
+        if (m > 0 && n > 0) {
+            Pl.reserve((size_t)std::min(m, n));
+            Ql.reserve((size_t)std::min(m, n));
+            r = cup_rec<T>(c, A, lda, (int)m, (int)n, Pl, Ql);
+        }
+        if (tail >= 1 && r > 0) {
+            int* dq = ensure_list(g, (size_t)r);
+            std::vector<int> q32(Ql.begin(), Ql.end());
+            CUP_HIP(hipMemcpyAsync(dq, q32.data(), sizeof(int) * (size_t)r, hipMemcpyHostToDevice,
+                                   c.s));
+            CUP_HIP(hipStreamSynchronize(c.s));
+            rref_tail<T>(c, A, lda, (int)m, (int)n, r, dq);
+            if (tail == 2 && r == (int)n) {
+                // A^{-1} = P^T X: rows t <-> p_t for t = n-1 down to 0
+                CUP_HIP(hipStreamSynchronize(c.s));
+                std::vector<int> p32(Pl.begin(), Pl.end());
+                CUP_HIP(hipMemcpyAsync(dq, p32.data(), sizeof(int) * (size_t)r,
+                                       hipMemcpyHostToDevice, c.s));
+                CUP_HIP(hipStreamSynchronize(c.s));
+                launch_rowswap_desc<T>(c.s, A, lda, r, (int)n, dq);
+            }
+        }
+        CUP_HIP(hipStreamSynchronize(c.s));
+        write_perm(c, P, Pl, n);
+        write_perm(c, Q, Ql, m);
+        *rank = r;
+        if (tail == 2 && r < n) return CUP_SINGULAR;
+        return CUP_OK;
+    } catch (const CupError& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return CUP_ERR_ALLOC;
+    }
+}
+
+template <typename T>
+int ffgemm_impl(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B,
+                       int64_t ldb, T* C, int64_t ldc, int64_t p, int alpha)
+{
+    if (M < 0 || M > INT32_MAX / 2) return -1;
+    if (N < 0 || N > INT32_MAX / 2) return -2;
+    if (K < 0 || K > INT32_MAX / 2) return -3;
+    if (M == 0 || N == 0) return CUP_OK;
+    if (K > 0 && (!A || lda < std::max<int64_t>(1, K))) return -5;
+    if (K > 0 && (!B || ldb < std::max<int64_t>(1, N))) return -7;
+    if (!C || ldc < std::max<int64_t>(1, N)) return -9;
+    if (!is_prime_i64(p) || p >= ((int64_t)1 << 26) || (sizeof(T) == 1 && p >= 128)) return -10;
+    if (alpha != 1 && alpha != -1) return -11;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    int form = resolve_form(g.form, p, sizeof(T) == 1);
+    if (form < 0) return -10;
+    try {
+        Ctx c = make_ctx(g, p, form);
+        gemm<T>(c, (int)M, (int)N, (int)K, A, lda, B, ldb, C, ldc, alpha);
+        CUP_HIP(hipStreamSynchronize(c.s));
+        return CUP_OK;
+    } catch (const CupError& e) {
+        return e.code;
+    }
+}
+
+}  // namespace
+}  // namespace cup
+
+using namespace cup;
+
+extern "C" {
+
+int cup_set_stream(void* hip_stream)
+{
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    g.stream = (hipStream_t)hip_stream;
+    return CUP_OK;
+}
+
+int cup_set_form(int form)
+{
+    if (form < CUP_FORM_AUTO || form > CUP_FORM_I8LIMB) return -1;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    g.form = form;
+    return CUP_OK;
+}
+
+int cup_get_form(void)
+{
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    return g.form;
+}
+
+int cup_factor(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* rank, int64_t* P,
+               int64_t* Q)
+{
+    return factor_impl<int64_t>(m, n, A, lda, p, rank, P, Q, 0);
+}
+
+int cup_factor_i8(int64_t m, int64_t n, int8_t* A, int64_t lda, int64_t p, int64_t* rank,
+                  int64_t* P, int64_t* Q)
+{
+    return factor_impl<int8_t>(m, n, A, lda, p, rank, P, Q, 0);
+}
+
+int cup_rank_profile(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* rank,
+                     int64_t* Q)
+{
+    return factor_impl<int64_t>(m, n, A, lda, p, rank, nullptr, Q, 0);
+}
+
+int cup_rref_inplace(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* rank,
+                     int64_t* P, int64_t* Q)
+{
+    return factor_impl<int64_t>(m, n, A, lda, p, rank, P, Q, 1);
+}
+
+int cup_rref_inplace_i8(int64_t m, int64_t n, int8_t* A, int64_t lda, int64_t p, int64_t* rank,
+                        int64_t* P, int64_t* Q)
+{
+    return factor_impl<int8_t>(m, n, A, lda, p, rank, P, Q, 1);
+}
+
+int cup_inverse_inplace(int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* rank)
+{
+    if (n < 0) return -1;
+    int rc = factor_impl<int64_t>(n, n, A, lda, p, rank, nullptr, nullptr, 2);
+    if (rc == -1 || rc == -2) return -1;
+    if (rc == -3) return -2;
+    if (rc == -4) return -3;
+    if (rc == -5) return -4;
+    if (rc == -6) return -5;
+    return rc;
+}
+
+int cup_inverse_inplace_i8(int64_t n, int8_t* A, int64_t lda, int64_t p, int64_t* rank)
+{
+    if (n < 0) return -1;
+    int rc = factor_impl<int8_t>(n, n, A, lda, p, rank, nullptr, nullptr, 2);
+    if (rc == -1 || rc == -2) return -1;
+    if (rc == -3) return -2;
+    if (rc == -4) return -3;
+    if (rc == -5) return -4;
+    if (rc == -6) return -5;
+    return rc;
+}
+
+int cup_factor_batched(int64_t batch, const int64_t* m, const int64_t* n, int64_t* const* A,
+                       const int64_t* lda, const int64_t* p, int64_t* rank, int64_t* const* P,
+                       int64_t* const* Q, int32_t* info)
+{
+    if (batch < 0) return -1;
+    if (batch == 0) return CUP_OK;
+    if (!m) return -2;
+    if (!n) return -3;
+    if (!A) return -4;
+    if (!lda) return -5;
+    if (!p) return -6;
+    if (!rank) return -7;
+    if (!info) return -10;
+    // Gather the batch description on the host, then factor each matrix.
+    Global& g = G();
+    hipStream_t s;
+    {
+        std::lock_guard<std::mutex> lk(g.mu);
+        s = g.stream;
+    }
+    try {
+        size_t B = (size_t)batch;
+        std::vector<int64_t> hm(B), hn(B), hl(B), hp(B), hr(B, 0);
+        std::vector<int64_t*> hA(B), hP(B, nullptr), hQ(B, nullptr);
+        std::vector<int32_t> hi(B, 0);
+        CUP_HIP(hipMemcpyAsync(hm.data(), m, 8 * B, hipMemcpyDeviceToHost, s));
+        CUP_HIP(hipMemcpyAsync(hn.data(), n, 8 * B, hipMemcpyDeviceToHost, s));
+        CUP_HIP(hipMemcpyAsync(hl.data(), lda, 8 * B, hipMemcpyDeviceToHost, s));
+        CUP_HIP(hipMemcpyAsync(hp.data(), p, 8 * B, hipMemcpyDeviceToHost, s));
+        CUP_HIP(hipMemcpyAsync(hA.data(), A, sizeof(void*) * B, hipMemcpyDeviceToHost, s));
+        if (P) CUP_HIP(hipMemcpyAsync(hP.data(), P, sizeof(void*) * B, hipMemcpyDeviceToHost, s));
+        if (Q) CUP_HIP(hipMemcpyAsync(hQ.data(), Q, sizeof(void*) * B, hipMemcpyDeviceToHost, s));
+        CUP_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < B; ++i) {
+            int64_t r = 0;
+            hi[i] = factor_impl<int64_t>(hm[i], hn[i], hA[i], hl[i], hp[i], &r, hP[i], hQ[i], 0);
+            hr[i] = r;
+        }
+        CUP_HIP(hipMemcpyAsync(rank, hr.data(), 8 * B, hipMemcpyHostToDevice, s));
+        CUP_HIP(hipMemcpyAsync(info, hi.data(), 4 * B, hipMemcpyHostToDevice, s));
+        CUP_HIP(hipStreamSynchronize(s));
+        return CUP_OK;
+    } catch (const CupError& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return CUP_ERR_ALLOC;
+    }
+}
+
+int cup_ffgemm(int64_t M, int64_t N, int64_t K, const int64_t* A, int64_t lda, const int64_t* B,
+               int64_t ldb, int64_t* C, int64_t ldc, int64_t p, int alpha)
+{
+    return ffgemm_impl<int64_t>(M, N, K, A, lda, B, ldb, C, ldc, p, alpha);
+}
+
+int cup_ffgemm_i8(int64_t M, int64_t N, int64_t K, const int8_t* A, int64_t lda, const int8_t* B,
+                  int64_t ldb, int8_t* C, int64_t ldc, int64_t p, int alpha)
+{
+    return ffgemm_impl<int8_t>(M, N, K, A, lda, B, ldb, C, ldc, p, alpha);
+}
+
+const char* cup_strerror(int status)
+{
+    if (status == CUP_OK) return "success";
+    if (status == CUP_SINGULAR) return "matrix is singular";
+    if (status == CUP_ERR_ALLOC) return "allocation failure";
+    if (status <= CUP_ERR_HIP && status > CUP_ERR_ALLOC) return "HIP runtime error";
+    switch (status) {
+    case -1: return "argument 1 is invalid";
+    case -2: return "argument 2 is invalid";
+    case -3: return "argument 3 is invalid (or an entry is outside [0,p))";
+    case -4: return "argument 4 is invalid";
+    case -5: return "argument 5 is invalid (p must be prime, 2 <= p < 2^26, within the form)";
+    case -6: return "argument 6 is invalid";
+    case -7: return "argument 7 is invalid";
+    case -8: return "argument 8 is invalid";
+    case -9: return "argument 9 is invalid";
+    case -10: return "argument 10 is invalid";
+    default: return "unknown status";
+    }
+}
+
+size_t cup_workspace_bytes(void)
+{
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    return g.bytes;
+}
+
+int cup_finalize(void)
+{
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    if (g.d_small) (void)hipFree(g.d_small);
+    if (g.h_small) (void)hipHostFree(g.h_small);
+    if (g.d_list) (void)hipFree(g.d_list);
+    g.d_small = nullptr;
+    g.h_small = nullptr;
+    g.d_list = nullptr;
+    g.list_cap = 0;
+    g.bytes = 0;
+    return CUP_OK;
+}
+
+}  // extern "C"

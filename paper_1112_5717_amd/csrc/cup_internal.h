@@ -1,0 +1,132 @@
+// Internal declarations of libcup: the context, error handling and the
+// kernel launchers shared by the host driver.  Not part of the C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace cup {
+
+// A prime p < 2^26 and its reciprocal; residues travel through kernels as
+// doubles, which represent every integer below 2^53 exactly.
+struct ModP {
+    double p;
+    double pinv;
+};
+
+enum Form { FORM_AUTO = 0, FORM_FP64 = 1, FORM_I8 = 2, FORM_I8LIMB = 3 };
+
+// Internal failure: unwinds to the C-ABI boundary, which returns `code`.
+struct CupError {
+    int code;
+};
+
+#define CUP_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) throw ::cup::CupError{-1000 - (int)e_};   \
+    } while (0)
+
+// Leaf sizes of the recursions.
+constexpr int kLeafRows = 64;   // rows of a CUP leaf (one window-elimination block)
+constexpr int kWin = 128;       // window width of the leaf elimination
+constexpr int kTriNB = 64;      // order of a triangular leaf block
+
+// Stop reasons of the window elimination.
+enum WindowStop { STOP_ROWS = 0, STOP_WINDOW = 1, STOP_ZERO_ROW = 2 };
+
+// Rows passed by value to the row-move kernel.
+struct MoveList {
+    int n;
+    int dst[kLeafRows];
+    int src[kLeafRows];
+};
+
+// Column transpositions passed by value (one launch per chunk).
+constexpr int kTranspChunk = 120;
+struct TranspList {
+    int n;
+    int a[kTranspChunk];
+    int b[kTranspChunk];
+};
+
+// ---------------------------------------------------------------- launchers
+// All operate on row-major views (pointer, leading dimension) on `s`.
+
+// C(MxN) <- C + alpha A(MxK) B(KxN) mod p, alpha = +1 or -1, FP64 MFMA carrier.
+template <typename T>
+void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t lda,
+                       const T* B, int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha,
+                       int kred_steps);
+
+// Window elimination of a leaf (see k_panel.hip).  Writes d, stop and the
+// chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col).
+template <typename T>
+void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
+                   ModP mp, int* out);
+
+// For each row r in [i0,b): leftmost nonzero column >= t0 (or N), into out[r-i0].
+template <typename T>
+void launch_row_scan(hipStream_t s, const T* A, int64_t lda, int i0, int b, int t0, int N,
+                     int* out);
+
+// Swap columns c0 and c1 of rows [0,rows).
+template <typename T>
+void launch_colswap(hipStream_t s, T* A, int64_t lda, int rows, int c0, int c1);
+
+// Row move: for k ascending, rows dst[k] <- src[k] on columns (dst[k], ncols),
+// then zero those columns of src[k].
+template <typename T>
+void launch_rowmove_list(hipStream_t s, T* A, int64_t lda, int ncols, const MoveList& ml);
+template <typename T>
+void launch_rowmove_shift(hipStream_t s, T* A, int64_t lda, int ncols, int dst0, int src0,
+                          int count);
+
+// Column transpositions a[k] <-> b[k], applied for k = 0..n-1 in order, to
+// rows [0,rows).
+template <typename T>
+void launch_coltransp(hipStream_t s, T* A, int64_t lda, int rows, const TranspList& tl);
+
+// Triangular leaf: side 0=Left 1=Right, uplo 0=Upper 1=Lower, unit 0/1,
+// op 0=solve (B <- T^{-1}B or BT^{-1}) 1=multiply (B <- TB or BT).
+// B is nb x other (Left) or other x nb (Right).
+template <typename T>
+void launch_tri_leaf(hipStream_t s, int side, int uplo, int unit, int op, int nb,
+                     const T* Tm, int64_t ldt, T* B, int64_t ldb, int other, ModP mp,
+                     int64_t kred);
+
+// In-place inverse of an nb x nb triangular block (the unit diagonal, if any,
+// is left untouched).
+template <typename T>
+void launch_trtri_leaf(hipStream_t s, int uplo, int unit, int nb, T* A, int64_t lda, ModP mp,
+                       int64_t kred);
+
+// [N\T] (N lower with diagonal, T unit upper) <- T.N for an nb x nb block.
+template <typename T>
+void launch_trulm_leaf(hipStream_t s, int nb, T* A, int64_t lda, ModP mp, int64_t kred);
+
+// B <- -B mod p on a rows x cols view.
+template <typename T>
+void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp);
+
+// For j ascending in [0,r): swap A[j][0..j] with A[q[j]][0..j] (inclusive).
+template <typename T>
+void launch_rowswap_lower(hipStream_t s, T* A, int64_t lda, int r, const int* q);
+
+// For t = r-1 down to 0: swap rows t and pv[t] over `cols` columns.
+template <typename T>
+void launch_rowswap_desc(hipStream_t s, T* A, int64_t lda, int r, int cols, const int* pv);
+
+// Count entries outside [0,p) of a rows x cols view (atomic add into *bad).
+template <typename T>
+void launch_range_check(hipStream_t s, const T* A, int64_t lda, int rows, int cols, int64_t p,
+                        int* bad);
+
+// Device copy of a rows x cols view into a dense buffer and back.
+template <typename T>
+void launch_copy2d(hipStream_t s, const T* src, int64_t lds, T* dst, int64_t ldd, int rows,
+                   int cols);
+
+}  // namespace cup

@@ -1,0 +1,360 @@
+// Host side of libcup: the in-place recursive drivers of Sections 3.2-3.5.
+//
+// Every routine works on row-major views (pointer, leading dimension) of
+// the caller's matrix; the only memory besides the matrix is the ffgemm
+// workspace and O(m + n) bookkeeping (Section 3.1, Definition 1: in place).
+// The recursions split on multiples of the leaf sizes; outputs do not depend
+// on the split point because the pivot rule fixes P, and P fixes C and U
+// (Section 2.2, Proposition 1).
+#pragma once
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "cup_internal.h"
+
+namespace cup {
+
+enum { LEFT = 0, RIGHT = 1 };
+enum { UPPER = 0, LOWER = 1 };
+enum { SOLVE = 0, MULT = 1 };
+
+struct Ctx {
+    hipStream_t s = nullptr;
+    int64_t p = 2;
+    ModP mp{2.0, 0.5};
+    int form = FORM_FP64;   // resolved ffgemm form
+    int kred_steps = 1;     // FP64 MFMA k-steps between accumulator reductions
+    int64_t kred = 1;       // canonical products per dot-product reduction
+    int* d_small = nullptr; // device results of the leaf kernels
+    int* h_small = nullptr; // pinned host mirror
+    int log = 0;
+};
+
+constexpr int kSmallInts = 4096;
+
+inline void ctx_set_prime(Ctx& c, int64_t p)
+{
+    c.p = p;
+    c.mp.p = (double)p;
+    c.mp.pinv = 1.0 / (double)p;
+    const double two53 = 9007199254740992.0;
+    double h = (double)(p / 2);
+    double steps = std::floor((two53 - 1.0 - (double)p) / (4.0 * h * h));
+    c.kred_steps = (int)std::min(steps, 1.0e9);
+    double pm1 = (double)(p - 1);
+    double terms = std::floor((two53 - 1.0) / (pm1 * pm1));
+    c.kred = (int64_t)std::min(terms, 1.0e12);
+    if (c.kred_steps < 1) c.kred_steps = 1;
+    if (c.kred < 1) c.kred = 1;
+}
+
+// Device -> host copy of the first `count` small results, then wait.
+inline const int* fetch_small(Ctx& c, int count)
+{
+    CUP_HIP(hipMemcpyAsync(c.h_small, c.d_small, sizeof(int) * (size_t)count,
+                           hipMemcpyDeviceToHost, c.s));
+    CUP_HIP(hipStreamSynchronize(c.s));
+    return c.h_small;
+}
+
+inline int split_at(int n, int unit)
+{
+    int k = ((n / 2 + unit / 2) / unit) * unit;
+    if (k < unit) k = unit;
+    if (k >= n) k = n - 1;
+    return k;
+}
+
+// ------------------------------------------------------------------ ffgemm
+template <typename T>
+void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
+          int64_t ldc, int alpha)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return;
+    launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps);
+}
+
+// ------------------------------------------------------------ TRSM / TRMM
+// Section 3.2, Algorithm 2 (and its eight variants), plus the TRMM twin:
+// halve the triangle, recurse on the diagonal blocks and fold the
+// off-diagonal block in with one ffgemm.  B is n x other (Left) or other x n
+// (Right).
+template <typename T>
+void trsm(Ctx& c, int side, int uplo, int unit, int n, const T* Tm, int64_t ldt, T* B,
+          int64_t ldb, int other)
+{
+    if (n <= 0 || other <= 0) return;
+    if (n <= kTriNB) {
+        launch_tri_leaf<T>(c.s, side, uplo, unit, SOLVE, n, Tm, ldt, B, ldb, other, c.mp, c.kred);
+        return;
+    }
+    const int k = split_at(n, kTriNB);
+    const T* T11 = Tm;
+    const T* T12 = Tm + k;
+    const T* T21 = Tm + (int64_t)k * ldt;
+    const T* T22 = Tm + (int64_t)k * ldt + k;
+    if (side == RIGHT) {
+        T* B1 = B;
+        T* B2 = B + k;
+        if (uplo == UPPER) {  // X1 = B1 U11^-1 ; X2 = (B2 - X1 U12) U22^-1
+            trsm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
+            gemm(c, other, n - k, k, B1, ldb, T12, ldt, B2, ldb, -1);
+            trsm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
+        } else {              // X2 = B2 L22^-1 ; X1 = (B1 - X2 L21) L11^-1
+            trsm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
+            gemm(c, other, k, n - k, B2, ldb, T21, ldt, B1, ldb, -1);
+            trsm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
+        }
+    } else {
+        T* B1 = B;
+        T* B2 = B + (int64_t)k * ldb;
+        if (uplo == LOWER) {  // X1 = L11^-1 B1 ; X2 = L22^-1 (B2 - L21 X1)
+            trsm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
+            gemm(c, n - k, other, k, T21, ldt, B1, ldb, B2, ldb, -1);
+            trsm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
+        } else {              // X2 = U22^-1 B2 ; X1 = U11^-1 (B1 - U12 X2)
+            trsm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
+            gemm(c, k, other, n - k, T12, ldt, B2, ldb, B1, ldb, -1);
+            trsm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
+        }
+    }
+}
+
+template <typename T>
+void trmm(Ctx& c, int side, int uplo, int unit, int n, const T* Tm, int64_t ldt, T* B,
+          int64_t ldb, int other)
+{
+    if (n <= 0 || other <= 0) return;
+    if (n <= kTriNB) {
+        launch_tri_leaf<T>(c.s, side, uplo, unit, MULT, n, Tm, ldt, B, ldb, other, c.mp, c.kred);
+        return;
+    }
+    const int k = split_at(n, kTriNB);
+    const T* T11 = Tm;
+    const T* T12 = Tm + k;
+    const T* T21 = Tm + (int64_t)k * ldt;
+    const T* T22 = Tm + (int64_t)k * ldt + k;
+    if (side == RIGHT) {
+        T* B1 = B;
+        T* B2 = B + k;
+        if (uplo == UPPER) {  // [B1 U11, B1 U12 + B2 U22]
+            trmm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
+            gemm(c, other, n - k, k, B1, ldb, T12, ldt, B2, ldb, +1);
+            trmm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
+        } else {              // [B1 L11 + B2 L21, B2 L22]
+            trmm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
+            gemm(c, other, k, n - k, B2, ldb, T21, ldt, B1, ldb, +1);
+            trmm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
+        }
+    } else {
+        T* B1 = B;
+        T* B2 = B + (int64_t)k * ldb;
+        if (uplo == UPPER) {  // [U11 B1 + U12 B2; U22 B2]
+            trmm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
+            gemm(c, k, other, n - k, T12, ldt, B2, ldb, B1, ldb, +1);
+            trmm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
+        } else {              // [L11 B1; L21 B1 + L22 B2]
+            trmm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
+            gemm(c, n - k, other, k, T21, ldt, B1, ldb, B2, ldb, +1);
+            trmm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
+        }
+    }
+}
+
+// ----------------------------------------------------------------- TRTRI
+// Section 3.2, Algorithm 3 and its lower twin: two half-size solves on the
+// off-diagonal block, a negation, and two recursive inversions.
+template <typename T>
+void trtri(Ctx& c, int uplo, int unit, int n, T* A, int64_t lda)
+{
+    if (n <= 0) return;
+    if (n <= kTriNB) {
+        launch_trtri_leaf<T>(c.s, uplo, unit, n, A, lda, c.mp, c.kred);
+        return;
+    }
+    const int k = split_at(n, kTriNB);
+    T* A11 = A;
+    T* A22 = A + (int64_t)k * lda + k;
+    if (uplo == UPPER) {
+        T* V = A + k;  // k x (n-k)
+        trsm(c, RIGHT, UPPER, unit, n - k, A22, lda, V, lda, k);
+        trsm(c, LEFT, UPPER, unit, k, A11, lda, V, lda, n - k);
+        launch_negate<T>(c.s, V, lda, k, n - k, c.mp);
+    } else {
+        T* W = A + (int64_t)k * lda;  // (n-k) x k
+        trsm(c, RIGHT, LOWER, unit, k, A11, lda, W, lda, n - k);
+        trsm(c, LEFT, LOWER, unit, n - k, A22, lda, W, lda, k);
+        launch_negate<T>(c.s, W, lda, n - k, k, c.mp);
+    }
+    trtri(c, uplo, unit, k, A11, lda);
+    trtri(c, uplo, unit, n - k, A22, lda);
+}
+
+// ----------------------------------------------------------------- TRULM
+// Section 3.2, Algorithm 4, in the variant used by Algorithm 8: on
+// [N\T] with T unit upper (strict upper part stored) and N lower (diagonal
+// stored), A <- T N.
+template <typename T>
+void trulm(Ctx& c, int n, T* A, int64_t lda)
+{
+    if (n <= 0) return;
+    if (n <= kTriNB) {
+        launch_trulm_leaf<T>(c.s, n, A, lda, c.mp, c.kred);
+        return;
+    }
+    const int k = split_at(n, kTriNB);
+    T* A11 = A;
+    T* A12 = A + k;
+    T* A21 = A + (int64_t)k * lda;
+    T* A22 = A + (int64_t)k * lda + k;
+    trulm(c, k, A11, lda);                                   // X11 = T11 N11
+    gemm(c, k, k, n - k, A12, lda, A21, lda, A11, lda, +1);  // X11 += T12 N21
+    trmm(c, RIGHT, LOWER, 0, n - k, A22, lda, A12, lda, k);  // X12 = T12 N22
+    trmm(c, LEFT, UPPER, 1, n - k, A22, lda, A21, lda, k);   // X21 = T22 N21
+    trulm(c, n - k, A22, lda);                               // X22 = T22 N22
+}
+
+// ------------------------------------------------------- column transpositions
+template <typename T>
+void apply_transpositions(Ctx& c, T* A, int64_t lda, int rows, const int64_t* piv, int count)
+{
+    if (rows <= 0) return;
+    TranspList tl;
+    tl.n = 0;
+    for (int t = 0; t < count; ++t) {
+        if (piv[t] == t) continue;
+        tl.a[tl.n] = t;
+        tl.b[tl.n] = (int)piv[t];
+        if (++tl.n == kTranspChunk) {
+            launch_coltransp<T>(c.s, A, lda, rows, tl);
+            tl.n = 0;
+        }
+    }
+    if (tl.n) launch_coltransp<T>(c.s, A, lda, rows, tl);
+}
+
+// ------------------------------------------------------------- CUP leaf
+// Base case over a block of b <= 64 rows (Algorithm 6 with the row recursion
+// unrolled): window eliminations decide the pivots; after each window the
+// pivot rows' U entries beyond the window come from one lower-triangular
+// solve and the remaining rows are updated by one ffgemm; a row whose
+// residual vanishes on the window is decided by a full-width scan.  Pivot
+// rows stay in place until the end, then the U rows are compacted upwards
+// in increasing order (the row move of Algorithm 6).
+template <typename T>
+int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
+             std::vector<int64_t>& Q)
+{
+    int i = 0, t = 0;
+    int pending = -1;  // column brought to position t by a full-width scan
+    std::vector<int> piv_rows;
+    while (i < b && t < N) {
+        const int wc = std::min(kWin, N - t);
+        launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small);
+        const int* h = fetch_small(c, 2 + kLeafRows);
+        const int d = h[0], stop = h[1];
+        for (int a = 0; a < d; ++a) {
+            int col = h[2 + a];
+            if (a == 0 && pending >= 0) col = pending;
+            P.push_back(col);
+            Q.push_back(i + a);
+            piv_rows.push_back(i + a);
+        }
+        pending = -1;
+        if (d > 0) {
+            const int tw = t + wc;
+            if (tw < N) {
+                trsm(c, LEFT, LOWER, 0, d, A + (int64_t)i * lda + t, lda,
+                     A + (int64_t)i * lda + tw, lda, N - tw);
+                if (i + d < b)
+                    gemm(c, b - i - d, N - tw, d, A + (int64_t)(i + d) * lda + t, lda,
+                         A + (int64_t)i * lda + tw, lda, A + (int64_t)(i + d) * lda + tw, lda, -1);
+            }
+            i += d;
+            t += d;
+        }
+        if (stop == STOP_ZERO_ROW && i < b && t < N) {
+            launch_row_scan<T>(c.s, A, lda, i, b, t, N, c.d_small);
+            const int* hs = fetch_small(c, b - i);
+            int found = -1, j = N;
+            for (int r = 0; r < b - i; ++r)
+                if (hs[r] < N) {
+                    found = i + r;
+                    j = hs[r];
+                    break;
+                }
+            if (found < 0) break;  // every remaining row is zero
+            i = found;
+            if (j != t) {
+                launch_colswap<T>(c.s, A, lda, b, t, j);
+                pending = j;
+            }
+        }
+    }
+    MoveList ml;
+    ml.n = 0;
+    for (int s = 0; s < (int)piv_rows.size(); ++s)
+        if (piv_rows[s] != s) {
+            ml.dst[ml.n] = s;
+            ml.src[ml.n] = piv_rows[s];
+            ++ml.n;
+        }
+    launch_rowmove_list<T>(c.s, A, lda, N, ml);
+    return t;
+}
+
+// ------------------------------------------------------------------- CUP
+// Section 3.3, Algorithm 6: factor the top rows, permute the columns of the
+// bottom rows, TRSM for G, Schur complement H = A22 - G V1 by ffgemm, factor
+// H, permute the columns of V1, move the new U rows up.  Appends the
+// transpositions (local column positions) to P and the profile (local rows)
+// to Q; returns the rank.
+template <typename T>
+int cup_rec(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& P,
+            std::vector<int64_t>& Q)
+{
+    if (m <= 0 || n <= 0) return 0;
+    if (m <= kLeafRows) return cup_leaf(c, A, lda, m, n, P, Q);
+    const int k = split_at(m, kLeafRows);
+    const size_t p0 = P.size(), q0 = Q.size();
+    if (c.log) std::fprintf(stderr, "[cup] node m=%d n=%d k=%d\n", m, n, k);
+    const int r1 = cup_rec(c, A, lda, k, n, P, Q);
+    T* A2 = A + (int64_t)k * lda;
+    if (r1 > 0) {
+        apply_transpositions(c, A2, lda, m - k, P.data() + p0, r1);          // A2 <- A2 P1^T
+        trsm(c, RIGHT, UPPER, 1, r1, A, lda, A2, lda, m - k);               // G = A21 U1^-1
+        if (r1 == n) return r1;
+        gemm(c, m - k, n - r1, r1, A2, lda, A + r1, lda, A2 + r1, lda, -1); // H = A22 - G V1
+    }
+    const int r2 = cup_rec(c, A2 + r1, lda, m - k, n - r1, P, Q);
+    if (r2 > 0) {
+        if (r1 > 0) apply_transpositions(c, A + r1, lda, r1, P.data() + p0 + r1, r2);  // V1 P2^T
+        if (k > r1) launch_rowmove_shift<T>(c.s, A, lda, n, r1, k, r2);
+    }
+    for (size_t x = p0 + r1; x < P.size(); ++x) P[x] += r1;
+    for (size_t x = q0 + r1; x < Q.size(); ++x) Q[x] += k;
+    return r1 + r2;
+}
+
+// ---------------------------------------------- reduced column echelon form
+// Algorithm 7 (ColEchTrans) then Algorithm 8 (RedColEchTrans) on the packed
+// [C\U] of rank r with row rank profile q (device int32 array, length r).
+template <typename T>
+void rref_tail(Ctx& c, T* A, int64_t lda, int m, int n, int r, const int* d_q)
+{
+    if (r <= 0) return;
+    // Algorithm 7: M = U1^-1 U2 ; N = -M ; U1 <- U1^-1 (unit upper)
+    trsm(c, LEFT, UPPER, 1, r, A, lda, A + r, lda, n - r);
+    launch_negate<T>(c.s, A + r, lda, r, n - r, c.mp);
+    trtri(c, UPPER, 1, r, A, lda);
+    // Algorithm 8: [L1; L2] <- Q C on columns 0..j of row j (inclusive)
+    launch_rowswap_lower<T>(c.s, A, lda, r, d_q);
+    trsm(c, RIGHT, LOWER, 0, r, A, lda, A + (int64_t)r * lda, lda, m - r);  // R2 = L2 L1^-1
+    trtri(c, LOWER, 0, r, A, lda);                                       // N = L1^-1
+    trulm(c, r, A, lda);                                                 // X1 = T1 N
+}
+
+}  // namespace cup

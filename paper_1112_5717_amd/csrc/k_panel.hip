@@ -1,0 +1,215 @@
+// Base case of the CUP recursion: pivot decisions on a leaf of up to 64 rows.
+//
+// The paper's base case (Section 3.3, Algorithm 6 with m = 1) takes one row,
+// finds the leftmost nonzero entry in the current column order, swaps that
+// column to the front and scales the rest of the row by the pivot's inverse.
+// Unrolled over a block of rows, this is row-by-row elimination in which
+// every decision depends on all earlier ones, so it is the sequential chain
+// of the method.  It is confined here to one workgroup and to a window of at
+// most 128 columns held in LDS:
+//
+//  * Each row's residual is tested for its leftmost nonzero with one
+//    wave-wide ballot per 64 columns.
+//  * Elimination inside the window is fraction free:
+//        row_l <- piv * row_l - row_l[t] * row_pivot   (mod p)
+//    which multiplies later rows by nonzero scalars and so preserves every
+//    zero test, but keeps modular inverses off the sequential chain.
+//  * Afterwards the true values are recovered in one parallel pass: with
+//    Sigma_s the product of the first s stored pivots, a C entry frozen at
+//    step s is divided by Sigma_s, the U part of pivot row s by its stored
+//    pivot, and a residual left after d pivots by Sigma_d.  The d + 1
+//    inverses are computed in parallel lanes.
+//
+// The phase stops at the first row whose residual vanishes on the window
+// (the host then decides that row with a full-width scan) or when the
+// window or the rows are exhausted.  Pivot rows never move here; the host
+// compacts the U rows at the end of the leaf.
+#include "modarith.h"
+
+namespace cup {
+
+namespace {
+
+constexpr int WT = 256;  // threads of the window kernel
+
+template <typename T>
+__global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t lda, int b, int N,
+                                                    int i0, int t0, int wc, ModP mp,
+                                                    int* __restrict__ out)
+{
+    __shared__ double tile[kLeafRows][kWin + 1];
+    __shared__ int s_swap[kLeafRows];
+    __shared__ double s_piv[kLeafRows];
+    __shared__ double s_isig[kLeafRows + 1];
+    __shared__ double s_ipiv[kLeafRows];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int R = b - i0;
+    const double P = mp.p, PI = mp.pinv;
+
+    for (int idx = tid; idx < R * wc; idx += WT) {
+        int r = idx / wc, c = idx - r * wc;
+        tile[r][c] = ld_res(A + (int64_t)(i0 + r) * lda + t0 + c);
+    }
+    __syncthreads();
+
+    int d = 0, stop = STOP_ROWS;
+    for (int a = 0;; ++a) {
+        if (a >= R) { stop = STOP_ROWS; break; }
+        if (a >= wc) { stop = STOP_WINDOW; break; }
+        // leftmost nonzero of row a at positions >= a (identical in every wave)
+        int j = -1;
+        for (int base = a; base < wc; base += 64) {
+            int c = base + lane;
+            bool nz = (c < wc) && (tile[a][c] != 0.0);
+            unsigned long long mask = __ballot(nz);
+            if (mask) { j = base + __ffsll((long long)mask) - 1; break; }
+        }
+        if (j < 0) { stop = STOP_ZERO_ROW; break; }
+        if (j != a) {
+            __syncthreads();  // every wave has finished reading row a
+            for (int r = tid; r < R; r += WT) {
+                double x = tile[r][a];
+                tile[r][a] = tile[r][j];
+                tile[r][j] = x;
+            }
+            __syncthreads();
+        }
+        const double piv = tile[a][a];
+        if (tid == 0) { s_swap[a] = j; s_piv[a] = piv; }
+        // fraction-free update of rows > a, columns > a
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            int c = lane + 64 * q;
+            if (c > a && c < wc) {
+                const double u = tile[a][c];
+                for (int r = wave; r < R; r += 4) {
+                    if (r > a) {
+                        double x = fma(piv, tile[r][c], -tile[r][a] * u);
+                        tile[r][c] = mod_red(x, P, PI);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        d = a + 1;
+    }
+
+    // Sigma_{s+1} = prod_{s' <= s} piv_{s'}: inclusive scan in wave 0.
+    if (wave == 0) {
+        double v = (lane < d) ? s_piv[lane] : 1.0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            double o = __shfl_up(v, off, 64);
+            if (lane >= off) v = mod_mul(v, o, P, PI);
+        }
+        double sig_prev = __shfl_up(v, 1, 64);  // Sigma_lane
+        if (lane == 0) sig_prev = 1.0;
+        if (lane < d) {
+            double isig_next = mod_inv(v, P, PI);        // 1 / Sigma_{lane+1}
+            s_isig[lane + 1] = isig_next;
+            s_ipiv[lane] = mod_mul(sig_prev, isig_next, P, PI);  // 1 / piv_lane
+        }
+        if (lane == 0) s_isig[0] = 1.0;
+    }
+    __syncthreads();
+
+    for (int idx = tid; idx < R * wc; idx += WT) {
+        int r = idx / wc, c = idx - r * wc;
+        double f;
+        int lim = (r + 1 < d) ? r + 1 : d;
+        if (c < lim) f = s_isig[c];
+        else f = (r < d) ? s_ipiv[r] : s_isig[d];
+        double v = mod_mul(tile[r][c], f, P, PI);
+        st_res(A + (int64_t)(i0 + r) * lda + t0 + c, v);
+    }
+    // the same column swaps on the leaf rows above the window block
+    for (int r = tid; r < i0; r += WT) {
+        T* row = A + (int64_t)r * lda + t0;
+        for (int a = 0; a < d; ++a) {
+            int j = s_swap[a];
+            if (j != a) {
+                T x = row[a];
+                row[a] = row[j];
+                row[j] = x;
+            }
+        }
+    }
+    if (tid == 0) {
+        out[0] = d;
+        out[1] = stop;
+    }
+    for (int a = tid; a < d; a += WT) out[2 + a] = t0 + s_swap[a];
+}
+
+// out[r - i0] = leftmost column >= t0 with a nonzero in row r, or N.
+template <typename T>
+__global__ __launch_bounds__(256) void row_scan_kernel(const T* __restrict__ A, int64_t lda,
+                                                       int i0, int t0, int N, int* __restrict__ out)
+{
+    __shared__ int best;
+    const int r = i0 + blockIdx.x;
+    if (threadIdx.x == 0) best = N;
+    __syncthreads();
+    const T* row = A + (int64_t)r * lda;
+    for (int c = t0 + threadIdx.x; c < N; c += 256) {
+        if (row[c] != 0) {
+            atomicMin(&best, c);
+            break;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = best;
+}
+
+template <typename T>
+__global__ void colswap_kernel(T* __restrict__ A, int64_t lda, int rows, int c0, int c1)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < rows) {
+        T* row = A + (int64_t)r * lda;
+        T x = row[c0];
+        row[c0] = row[c1];
+        row[c1] = x;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
+                   ModP mp, int* out)
+{
+    hipLaunchKernelGGL(window_kernel<T>, dim3(1), dim3(WT), 0, s, A, lda, b, N, i0, t0, wc, mp,
+                       out);
+    CUP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_row_scan(hipStream_t s, const T* A, int64_t lda, int i0, int b, int t0, int N,
+                     int* out)
+{
+    if (b <= i0) return;
+    hipLaunchKernelGGL(row_scan_kernel<T>, dim3(b - i0), dim3(256), 0, s, A, lda, i0, t0, N, out);
+    CUP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_colswap(hipStream_t s, T* A, int64_t lda, int rows, int c0, int c1)
+{
+    if (rows <= 0 || c0 == c1) return;
+    hipLaunchKernelGGL(colswap_kernel<T>, dim3((rows + 255) / 256), dim3(256), 0, s, A, lda, rows,
+                       c0, c1);
+    CUP_HIP(hipGetLastError());
+}
+
+#define CUP_INST(T)                                                                            \
+    template void launch_window<T>(hipStream_t, T*, int64_t, int, int, int, int, int, ModP,    \
+                                   int*);                                                      \
+    template void launch_row_scan<T>(hipStream_t, const T*, int64_t, int, int, int, int, int*); \
+    template void launch_colswap<T>(hipStream_t, T*, int64_t, int, int, int);
+CUP_INST(int64_t)
+CUP_INST(int8_t)
+#undef CUP_INST
+
+}  // namespace cup

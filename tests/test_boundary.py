@@ -1,0 +1,62 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+symbol the header declares, and rejects invalid arguments before any device
+work (LAPACK-style codes of include/cup.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cup.h")
+LIB = os.path.join(ROOT, "paper_1112_5717_amd", "libcup.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libcup.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cup_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = ctypes.CDLL(LIB)
+    syms = declared_symbols()
+    assert "cup_factor" in syms and "cup_factor_batched" in syms and "cup_inverse_inplace" in syms
+    for s in syms:
+        assert hasattr(lib, s), f"{s} declared in include/cup.h but not exported"
+
+
+def test_binding_covers_header():
+    from paper_1112_5717_amd import cup
+    assert set(declared_symbols()) == set(cup.SIGNATURES)
+    cup.load()
+
+
+def test_argument_validation():
+    from paper_1112_5717_amd import cup
+    lib = cup.load()
+    r = ctypes.c_int64(0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.cup_factor(-1, 4, fake, 4, 7, ctypes.byref(r), None, None) == -1
+    assert lib.cup_factor(4, -2, fake, 4, 7, ctypes.byref(r), None, None) == -2
+    assert lib.cup_factor(4, 4, None, 4, 7, ctypes.byref(r), None, None) == -3
+    assert lib.cup_factor(4, 4, fake, 3, 7, ctypes.byref(r), None, None) == -4
+    for bad_p in (0, 1, 4, 65535, 2 ** 26 + 15, 2 ** 27 - 39):
+        assert lib.cup_factor(4, 4, fake, 4, bad_p, ctypes.byref(r), None, None) == -5
+    assert lib.cup_factor(4, 4, fake, 4, 7, None, None, None) == -6
+    assert lib.cup_factor_i8(4, 4, fake, 4, 131, ctypes.byref(r), None, None) == -5
+    assert lib.cup_inverse_inplace(-1, fake, 4, 7, ctypes.byref(r)) == -1
+    assert lib.cup_inverse_inplace(4, None, 4, 7, ctypes.byref(r)) == -2
+    assert lib.cup_inverse_inplace(4, fake, 3, 7, ctypes.byref(r)) == -3
+    assert lib.cup_inverse_inplace(4, fake, 4, 9, ctypes.byref(r)) == -4
+    assert lib.cup_factor_batched(-1, None, None, None, None, None, None, None, None, None) == -1
+    assert lib.cup_factor_batched(0, None, None, None, None, None, None, None, None, None) == 0
+    assert lib.cup_ffgemm(4, 4, 4, fake, 4, fake, 4, fake, 4, 7, 2) == -11
+    assert lib.cup_ffgemm(4, 4, 4, fake, 2, fake, 4, fake, 4, 7, 1) == -5
+    assert lib.cup_set_form(9) == -1
+    for code in (0, 1, -1, -5, -1001, -2000):
+        assert cup.strerror(code)
