@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the CUP decomposition over GF(65521) on one MI355X.
+
+Workload (one step): the in-place CUP decomposition (Algorithm 6 of
+Jeannerod, Pernet and Storjohann) of an 8192 x 8192 matrix of uniform
+residues modulo 65521 (seed 2; full rank with high probability), with its
+rank, row rank profile and transposition list.  Each step factors its own
+pre-staged copy of the input, so inputs are resident in HBM when the timed
+region starts and nothing is skipped.
+
+Metric: CUP field operations per second with the paper's count for
+classical matrix products, F = 2mnr - (m+n) r^2 + 2/3 r^3 (Section 4.2).
+
+Besides the headline form, the same steps run in the plain FP64-carrier
+form, and once on the rank-6000 variant X(8192x6000) Y(6000x8192) mod p
+(seed 20).  Every timed result is checked against the CPU oracle's SHA-256
+digest when tests/golden/full_size_hashes.json has it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("CUP field ops/s (2mnr-class count) + % MFMA peak, INT8 vs FP64-carrier form, "
+          "bit-exact")
+PEAK = {"fp64": (78.6, "TFLOP/s"), "i8": (5000.0, "TOP/s"), "i8limb": (5000.0, "TOP/s")}
+P16 = 65521
+
+
+def field_ops(m: int, n: int, r: int) -> float:
+    """Section 4.2: 2mnr - (m+n) r^2 + 2/3 r^3 field operations."""
+    return 2.0 * m * n * r - (m + n) * r * r + 2.0 * r ** 3 / 3.0
+
+
+def digest(packed, r, P, Q) -> str:
+    import numpy as np
+    h = hashlib.sha256()
+    for a in (packed, P, Q):
+        h.update(np.ascontiguousarray(a, dtype=np.int64).tobytes())
+    h.update(np.int64(r).tobytes())
+    return h.hexdigest()
+
+
+def golden():
+    path = os.path.join(ROOT, "tests", "golden", "full_size_hashes.json")
+    return json.load(open(path)) if os.path.exists(path) else {}
+
+
+def run_form(cup, torch, A0, p, form, steps, warmup, profile):
+    """Time `steps` CUP calls of form `form` on fresh copies of A0."""
+    cup.cup_set_form(form)
+    copies = [A0.clone() for _ in range(steps + warmup)]
+    torch.cuda.synchronize()
+    for i in range(warmup):
+        cup.cup_factor(copies[i], p)
+    torch.cuda.synchronize()
+    if profile:
+        cup.cup_profile(True)
+    t0 = time.perf_counter()
+    out = None
+    for i in range(warmup, warmup + steps):
+        out = cup.cup_factor(copies[i], p)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stats = None
+    if profile:
+        stats = cup.cup_profile_read()
+        cup.cup_profile(False)
+    r, P, Q = out
+    res = copies[-1]
+    dg = digest(res.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy())
+    del copies
+    return {"seconds": dt, "rank": r, "digest": dg, "stats": stats}
+
+
+def cpu_baseline(A_host, p, rows):
+    """The oracle, as it stands, on the first `rows` rows of the same matrix."""
+    import oracle
+    sample = A_host[:rows].copy()
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    _, r, _, _ = oracle.cup(sample, p)
+    dt = time.perf_counter() - t0
+    F = field_ops(rows, A_host.shape[1], r)
+    return {"value": F / dt, "unit": "field ops/s", "cores": threads, "kind": "oracle",
+            "sample": f"CUP of the first {rows} rows ({rows}x{A_host.shape[1]}, rank {r}) of the "
+                      f"same GF({p}) matrix; {F:.3e} field ops in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--form", default="auto", choices=["auto", "fp64", "i8limb"])
+    ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the decomposition's exchange pattern is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1112_5717_amd import cup, inputs
+
+    cup.load()
+    n = args.n
+    gold = golden()
+    print(f"[bench] generating {n}x{n} uniform residues mod {P16} (seed 2)", file=sys.stderr, flush=True)
+    A_host = inputs.uniform((n, n), P16, seed=2)
+    A0 = torch.from_numpy(A_host).cuda()
+
+    main_form = args.form
+    print(f"[bench] timing form={main_form} steps={args.steps} warmup={args.warmup}", file=sys.stderr,
+          flush=True)
+    res = run_form(cup, torch, A0, P16, main_form, args.steps, args.warmup, profile=True)
+    r = res["rank"]
+    F = field_ops(n, n, r)
+    value = F / res["seconds"]
+    resolved = "fp64" if main_form in ("auto", "fp64") else main_form
+    gkey = f"cup_{n}_uniform_p{P16}_seed2"
+    parity = ("oracle digest match" if gold.get(gkey, {}).get("digest") == res["digest"]
+              else ("ORACLE DIGEST MISMATCH" if gkey in gold else "no oracle digest at this size"))
+
+    st = res["stats"]["ffgemm"]
+    peak, unit = PEAK[resolved]
+    mult = 4.0 if resolved == "i8limb" else 1.0
+    achieved = (mult * st["flops"] / (st["ms"] * 1e-3) / 1e12) if st["ms"] > 0 else 0.0
+    roofline = {
+        "bound": "mfma", "kernel": f"ffgemm ({resolved})",
+        "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+        "frac": round(achieved / peak, 4),
+        "traffic": None,
+        "launches_per_step": st["launches"] / args.steps,
+        "avg_launch_ms": st["ms"] / max(1.0, st["launches"]),
+        "ops_per_launch": mult * st["flops"] / max(1.0, st["launches"]),
+        "kernel_ms_per_step": st["ms"] / args.steps,
+    }
+    win = res["stats"]["window"]
+    extra = {"window_kernel": {"launches_per_step": win["launches"] / args.steps,
+                               "kernel_ms_per_step": win["ms"] / args.steps}}
+
+    forms = {resolved: {"ms_per_step": res["seconds"] * 1e3, "field_ops_per_s": value,
+                        "parity": parity}}
+    if not args.no_variants:
+        print("[bench] rank-6000 variant (seed 20)", file=sys.stderr, flush=True)
+        B0 = torch.from_numpy(inputs.low_rank(n, n, min(6000, n), P16, seed=20, device="cuda")).cuda()
+        rv = run_form(cup, torch, B0, P16, main_form, max(1, args.steps // 2), 1, profile=False)
+        gk = f"cup_{n}_rank6000_p{P16}_seed20"
+        extra["rank6000"] = {
+            "rank": rv["rank"], "ms_per_step": rv["seconds"] * 1e3,
+            "field_ops_per_s": field_ops(n, n, rv["rank"]) / rv["seconds"],
+            "parity": ("oracle digest match" if gold.get(gk, {}).get("digest") == rv["digest"]
+                       else ("ORACLE DIGEST MISMATCH" if gk in gold else "no oracle digest")),
+        }
+        del B0
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] CPU oracle on {args.cpu_rows} rows", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(A_host, P16, args.cpu_rows)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "field ops/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["seconds"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if resolved == "fp64" else "i8", "data": "synthetic",
+        "config": {"workload": f"CUP over GF({P16}), {n}x{n} uniform residues (seed 2), "
+                               f"full rank; packed [C\\U], P, Q in place",
+                   "m": n, "n": n, "p": P16, "rank": r, "form": resolved,
+                   "field_ops_per_step": F, "parity": parity},
+        "roofline": roofline, "cpu_baseline": cpu, "forms": forms, **extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

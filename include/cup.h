@@ -167,6 +167,19 @@ int cup_ffgemm_i8(int64_t M, int64_t N, int64_t K, const int8_t *A, int64_t lda,
 /* Text for a return code. */
 const char *cup_strerror(int status);
 
+/*
+ * Kernel timing for measurement.  cup_profile(1) resets and starts timing
+ * every ffgemm launch and every leaf-window launch with a pair of HIP events
+ * on the launch stream (no extra synchronisation); cup_profile(0) stops.
+ * cup_profile_read fills stats[8] = {ffgemm launches, ffgemm kernel ms,
+ * ffgemm algorithmic operations (2MNK per launch), ffgemm algorithmic bytes
+ * ((MK + KN + 2MN) x element size per launch), then the same four figures
+ * for the window kernel (operations 0, bytes = one read and one write of
+ * its tile)}.  Returns -1 if stats is NULL.
+ */
+int cup_profile(int enable);
+int cup_profile_read(double *stats);
+
 /* Bytes of device workspace currently cached by the library. */
 size_t cup_workspace_bytes(void);
 

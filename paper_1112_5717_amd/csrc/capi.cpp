@@ -24,6 +24,8 @@ struct Global {
     int* d_list = nullptr;
     size_t list_cap = 0;  // ints
     size_t bytes = 0;
+    Profiler prof;
+    Workspace ws;
 };
 
 Global& G()
@@ -144,6 +146,8 @@ Ctx make_ctx(Global& g, int64_t p, int form)
     c.d_small = g.d_small;
     c.h_small = g.h_small;
     c.log = env_flag("CUP_LOG") ? 1 : 0;
+    c.prof = &g.prof;
+    c.ws = &g.ws;
     ctx_set_prime(c, p);
     return c;
 }
@@ -187,6 +191,7 @@ int factor_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* ran
             }
         }
         CUP_HIP(hipStreamSynchronize(c.s));
+        if (g.prof.on) g.prof.collect();
         write_perm(c, P, Pl, n);
         write_perm(c, Q, Ql, m);
         *rank = r;
@@ -220,6 +225,7 @@ int ffgemm_impl(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const 
         Ctx c = make_ctx(g, p, form);
         gemm<T>(c, (int)M, (int)N, (int)K, A, lda, B, ldb, C, ldc, alpha);
         CUP_HIP(hipStreamSynchronize(c.s));
+        if (g.prof.on) g.prof.collect();
         return CUP_OK;
     } catch (const CupError& e) {
         return e.code;
@@ -393,11 +399,34 @@ const char* cup_strerror(int status)
     }
 }
 
+int cup_profile(int enable)
+{
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    if (enable) g.prof.reset();
+    g.prof.on = enable != 0;
+    return CUP_OK;
+}
+
+int cup_profile_read(double* stats)
+{
+    if (!stats) return -1;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    for (int k = 0; k < 2; ++k) {
+        stats[4 * k + 0] = g.prof.launches[k];
+        stats[4 * k + 1] = g.prof.ms[k];
+        stats[4 * k + 2] = g.prof.flops[k];
+        stats[4 * k + 3] = g.prof.bytes[k];
+    }
+    return CUP_OK;
+}
+
 size_t cup_workspace_bytes(void)
 {
     Global& g = G();
     std::lock_guard<std::mutex> lk(g.mu);
-    return g.bytes;
+    return g.bytes + g.ws.bytes;
 }
 
 int cup_finalize(void)
@@ -407,6 +436,8 @@ int cup_finalize(void)
     if (g.d_small) (void)hipFree(g.d_small);
     if (g.h_small) (void)hipHostFree(g.h_small);
     if (g.d_list) (void)hipFree(g.d_list);
+    if (g.ws.tri) (void)hipFree(g.ws.tri);
+    g.ws = Workspace{};
     g.d_small = nullptr;
     g.h_small = nullptr;
     g.d_list = nullptr;

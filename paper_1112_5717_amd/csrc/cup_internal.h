@@ -89,19 +89,18 @@ void launch_rowmove_shift(hipStream_t s, T* A, int64_t lda, int ncols, int dst0,
 template <typename T>
 void launch_coltransp(hipStream_t s, T* A, int64_t lda, int rows, const TranspList& tl);
 
-// Triangular leaf: side 0=Left 1=Right, uplo 0=Upper 1=Lower, unit 0/1,
-// op 0=solve (B <- T^{-1}B or BT^{-1}) 1=multiply (B <- TB or BT).
-// B is nb x other (Left) or other x nb (Right).
+// Diagonal blocks of a triangle of order n (uplo 0=Upper 1=Lower, unit 0/1):
+// mode 0 writes W[b] = T_bb^{-1}, mode 1 writes W[b] = T_bb (each a dense
+// 64 x 64 block of doubles, identity-padded), mode 2 inverts the single
+// block of order n <= 64 in place.
 template <typename T>
-void launch_tri_leaf(hipStream_t s, int side, int uplo, int unit, int op, int nb,
-                     const T* Tm, int64_t ldt, T* B, int64_t ldb, int other, ModP mp,
-                     int64_t kred);
+void launch_diag_prep(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, int mode,
+                      double* W, ModP mp);
 
-// In-place inverse of an nb x nb triangular block (the unit diagonal, if any,
-// is left untouched).
+// B <- B W (side 1: B is other x nb) or W B (side 0: B is nb x other).
 template <typename T>
-void launch_trtri_leaf(hipStream_t s, int uplo, int unit, int nb, T* A, int64_t lda, ModP mp,
-                       int64_t kred);
+void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, int64_t ldb,
+                      int other, ModP mp);
 
 // [N\T] (N lower with diagonal, T unit upper) <- T.N for an nb x nb block.
 template <typename T>

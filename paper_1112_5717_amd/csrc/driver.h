@@ -21,8 +21,72 @@ enum { LEFT = 0, RIGHT = 1 };
 enum { UPPER = 0, LOWER = 1 };
 enum { SOLVE = 0, MULT = 1 };
 
+// Kernel timing with HIP events (enabled by cup_profile): every ffgemm and
+// leaf-window launch is bracketed by two events on the launch stream; the
+// elapsed times are summed after the call has synchronised.
+struct ProfRec {
+    int kind;            // 0 ffgemm, 1 window
+    double flops;        // algorithmic operations of the launch
+    double bytes;        // algorithmic bytes of the launch
+    hipEvent_t a, b;
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<ProfRec> recs;
+    double launches[2] = {0, 0}, ms[2] = {0, 0}, flops[2] = {0, 0}, bytes[2] = {0, 0};
+
+    void reset()
+    {
+        launches[0] = launches[1] = ms[0] = ms[1] = 0;
+        flops[0] = flops[1] = bytes[0] = bytes[1] = 0;
+    }
+    hipEvent_t next()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            CUP_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void begin(hipStream_t s, int kind, double f, double by)
+    {
+        ProfRec r{kind, f, by, next(), next()};
+        CUP_HIP(hipEventRecord(r.a, s));
+        recs.push_back(r);
+    }
+    void end(hipStream_t s) { CUP_HIP(hipEventRecord(recs.back().b, s)); }
+    // after the stream has synchronised
+    void collect()
+    {
+        for (auto& r : recs) {
+            float t = 0.f;
+            CUP_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            launches[r.kind] += 1;
+            ms[r.kind] += t;
+            flops[r.kind] += r.flops;
+            bytes[r.kind] += r.bytes;
+        }
+        recs.clear();
+        used = 0;
+    }
+};
+
+// Device scratch owned by the library (grown on demand, freed by
+// cup_finalize): the dense 64 x 64 diagonal blocks of the triangular leaves.
+struct Workspace {
+    double* tri = nullptr;
+    size_t tri_cap = 0;  // doubles
+    size_t bytes = 0;
+};
+
 struct Ctx {
     hipStream_t s = nullptr;
+    Profiler* prof = nullptr;
+    Workspace* ws = nullptr;
     int64_t p = 2;
     ModP mp{2.0, 0.5};
     int form = FORM_FP64;   // resolved ffgemm form
@@ -60,6 +124,29 @@ inline const int* fetch_small(Ctx& c, int count)
     return c.h_small;
 }
 
+inline double* tri_workspace(Ctx& c, int n)
+{
+    const size_t need = (size_t)((n + kTriNB - 1) / kTriNB) * kTriNB * kTriNB;
+    Workspace& w = *c.ws;
+    if (need > w.tri_cap) {
+        if (w.tri) {
+            CUP_HIP(hipStreamSynchronize(c.s));
+            CUP_HIP(hipFree(w.tri));
+            w.bytes -= w.tri_cap * sizeof(double);
+            w.tri = nullptr;
+            w.tri_cap = 0;
+        }
+        size_t cap = std::max(need, (size_t)64 * kTriNB * kTriNB);
+        if (hipMalloc((void**)&w.tri, cap * sizeof(double)) != hipSuccess) {
+            w.tri = nullptr;
+            throw CupError{-2000};
+        }
+        w.tri_cap = cap;
+        w.bytes += cap * sizeof(double);
+    }
+    return w.tri;
+}
+
 inline int split_at(int n, int unit)
 {
     int k = ((n / 2 + unit / 2) / unit) * unit;
@@ -74,53 +161,87 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
           int64_t ldc, int alpha)
 {
     if (M <= 0 || N <= 0 || K <= 0) return;
+    const bool prof = c.prof && c.prof->on;
+    if (prof)
+        c.prof->begin(c.s, 0, 2.0 * M * N * K,
+                      ((double)M * K + (double)K * N + 2.0 * M * N) * sizeof(T));
     launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps);
+    if (prof) c.prof->end(c.s);
 }
 
 // ------------------------------------------------------------ TRSM / TRMM
 // Section 3.2, Algorithm 2 (and its eight variants), plus the TRMM twin:
 // halve the triangle, recurse on the diagonal blocks and fold the
 // off-diagonal block in with one ffgemm.  B is n x other (Left) or other x n
-// (Right).
+// (Right).  The leaves multiply by the precomputed inverse (solve) or copy
+// (multiply) of their 64 x 64 diagonal block, W[offset / 64].
+template <typename T>
+void tri_rec(Ctx& c, int op, int side, int uplo, int n, const T* Tm, int64_t ldt, T* B,
+             int64_t ldb, int other, const double* W)
+{
+    if (n <= kTriNB) {
+        launch_tri_apply<T>(c.s, side, n, W, B, ldb, other, c.mp);
+        return;
+    }
+    const int k = split_at(n, kTriNB);
+    const T* T12 = Tm + k;
+    const T* T21 = Tm + (int64_t)k * ldt;
+    const T* T22 = Tm + (int64_t)k * ldt + k;
+    const double* W2 = W + (size_t)(k / kTriNB) * kTriNB * kTriNB;
+    const int sg = (op == SOLVE) ? -1 : +1;
+    if (side == RIGHT) {
+        T* B1 = B;
+        T* B2 = B + k;
+        if ((uplo == UPPER) == (op == SOLVE)) {
+            // solve upper: X1 = B1 U11^-1 ; X2 = (B2 - X1 U12) U22^-1
+            // multiply lower: [B1 L11 + B2 L21, B2 L22]
+            const T* Toff = (uplo == UPPER) ? T12 : T21;
+            if (op == SOLVE) {
+                tri_rec(c, op, side, uplo, k, Tm, ldt, B1, ldb, other, W);
+                gemm(c, other, n - k, k, B1, ldb, Toff, ldt, B2, ldb, sg);
+                tri_rec(c, op, side, uplo, n - k, T22, ldt, B2, ldb, other, W2);
+            } else {
+                tri_rec(c, op, side, uplo, k, Tm, ldt, B1, ldb, other, W);
+                gemm(c, other, k, n - k, B2, ldb, Toff, ldt, B1, ldb, sg);
+                tri_rec(c, op, side, uplo, n - k, T22, ldt, B2, ldb, other, W2);
+            }
+        } else {
+            // solve lower: X2 = B2 L22^-1 ; X1 = (B1 - X2 L21) L11^-1
+            // multiply upper: [B1 U11, B1 U12 + B2 U22]
+            tri_rec(c, op, side, uplo, n - k, T22, ldt, B2, ldb, other, W2);
+            if (op == SOLVE) gemm(c, other, k, n - k, B2, ldb, T21, ldt, B1, ldb, sg);
+            else gemm(c, other, n - k, k, B1, ldb, T12, ldt, B2, ldb, sg);
+            tri_rec(c, op, side, uplo, k, Tm, ldt, B1, ldb, other, W);
+        }
+    } else {
+        T* B1 = B;
+        T* B2 = B + (int64_t)k * ldb;
+        if ((uplo == LOWER) == (op == SOLVE)) {
+            // solve lower: X1 = L11^-1 B1 ; X2 = L22^-1 (B2 - L21 X1)
+            // multiply upper: [U11 B1 + U12 B2; U22 B2]
+            tri_rec(c, op, side, uplo, k, Tm, ldt, B1, ldb, other, W);
+            if (op == SOLVE) gemm(c, n - k, other, k, T21, ldt, B1, ldb, B2, ldb, sg);
+            else gemm(c, k, other, n - k, T12, ldt, B2, ldb, B1, ldb, sg);
+            tri_rec(c, op, side, uplo, n - k, T22, ldt, B2, ldb, other, W2);
+        } else {
+            // solve upper: X2 = U22^-1 B2 ; X1 = U11^-1 (B1 - U12 X2)
+            // multiply lower: [L11 B1; L21 B1 + L22 B2]
+            tri_rec(c, op, side, uplo, n - k, T22, ldt, B2, ldb, other, W2);
+            if (op == SOLVE) gemm(c, k, other, n - k, T12, ldt, B2, ldb, B1, ldb, sg);
+            else gemm(c, n - k, other, k, T21, ldt, B1, ldb, B2, ldb, sg);
+            tri_rec(c, op, side, uplo, k, Tm, ldt, B1, ldb, other, W);
+        }
+    }
+}
+
 template <typename T>
 void trsm(Ctx& c, int side, int uplo, int unit, int n, const T* Tm, int64_t ldt, T* B,
           int64_t ldb, int other)
 {
     if (n <= 0 || other <= 0) return;
-    if (n <= kTriNB) {
-        launch_tri_leaf<T>(c.s, side, uplo, unit, SOLVE, n, Tm, ldt, B, ldb, other, c.mp, c.kred);
-        return;
-    }
-    const int k = split_at(n, kTriNB);
-    const T* T11 = Tm;
-    const T* T12 = Tm + k;
-    const T* T21 = Tm + (int64_t)k * ldt;
-    const T* T22 = Tm + (int64_t)k * ldt + k;
-    if (side == RIGHT) {
-        T* B1 = B;
-        T* B2 = B + k;
-        if (uplo == UPPER) {  // X1 = B1 U11^-1 ; X2 = (B2 - X1 U12) U22^-1
-            trsm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
-            gemm(c, other, n - k, k, B1, ldb, T12, ldt, B2, ldb, -1);
-            trsm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
-        } else {              // X2 = B2 L22^-1 ; X1 = (B1 - X2 L21) L11^-1
-            trsm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
-            gemm(c, other, k, n - k, B2, ldb, T21, ldt, B1, ldb, -1);
-            trsm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
-        }
-    } else {
-        T* B1 = B;
-        T* B2 = B + (int64_t)k * ldb;
-        if (uplo == LOWER) {  // X1 = L11^-1 B1 ; X2 = L22^-1 (B2 - L21 X1)
-            trsm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
-            gemm(c, n - k, other, k, T21, ldt, B1, ldb, B2, ldb, -1);
-            trsm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
-        } else {              // X2 = U22^-1 B2 ; X1 = U11^-1 (B1 - U12 X2)
-            trsm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
-            gemm(c, k, other, n - k, T12, ldt, B2, ldb, B1, ldb, -1);
-            trsm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
-        }
-    }
+    double* W = tri_workspace(c, n);
+    launch_diag_prep<T>(c.s, const_cast<T*>(Tm), ldt, n, uplo, unit, 0, W, c.mp);
+    tri_rec(c, SOLVE, side, uplo, n, Tm, ldt, B, ldb, other, W);
 }
 
 template <typename T>
@@ -128,40 +249,9 @@ void trmm(Ctx& c, int side, int uplo, int unit, int n, const T* Tm, int64_t ldt,
           int64_t ldb, int other)
 {
     if (n <= 0 || other <= 0) return;
-    if (n <= kTriNB) {
-        launch_tri_leaf<T>(c.s, side, uplo, unit, MULT, n, Tm, ldt, B, ldb, other, c.mp, c.kred);
-        return;
-    }
-    const int k = split_at(n, kTriNB);
-    const T* T11 = Tm;
-    const T* T12 = Tm + k;
-    const T* T21 = Tm + (int64_t)k * ldt;
-    const T* T22 = Tm + (int64_t)k * ldt + k;
-    if (side == RIGHT) {
-        T* B1 = B;
-        T* B2 = B + k;
-        if (uplo == UPPER) {  // [B1 U11, B1 U12 + B2 U22]
-            trmm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
-            gemm(c, other, n - k, k, B1, ldb, T12, ldt, B2, ldb, +1);
-            trmm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
-        } else {              // [B1 L11 + B2 L21, B2 L22]
-            trmm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
-            gemm(c, other, k, n - k, B2, ldb, T21, ldt, B1, ldb, +1);
-            trmm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
-        }
-    } else {
-        T* B1 = B;
-        T* B2 = B + (int64_t)k * ldb;
-        if (uplo == UPPER) {  // [U11 B1 + U12 B2; U22 B2]
-            trmm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
-            gemm(c, k, other, n - k, T12, ldt, B2, ldb, B1, ldb, +1);
-            trmm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
-        } else {              // [L11 B1; L21 B1 + L22 B2]
-            trmm(c, side, uplo, unit, n - k, T22, ldt, B2, ldb, other);
-            gemm(c, n - k, other, k, T21, ldt, B1, ldb, B2, ldb, +1);
-            trmm(c, side, uplo, unit, k, T11, ldt, B1, ldb, other);
-        }
-    }
+    double* W = tri_workspace(c, n);
+    launch_diag_prep<T>(c.s, const_cast<T*>(Tm), ldt, n, uplo, unit, 1, W, c.mp);
+    tri_rec(c, MULT, side, uplo, n, Tm, ldt, B, ldb, other, W);
 }
 
 // ----------------------------------------------------------------- TRTRI
@@ -172,7 +262,7 @@ void trtri(Ctx& c, int uplo, int unit, int n, T* A, int64_t lda)
 {
     if (n <= 0) return;
     if (n <= kTriNB) {
-        launch_trtri_leaf<T>(c.s, uplo, unit, n, A, lda, c.mp, c.kred);
+        launch_diag_prep<T>(c.s, A, lda, n, uplo, unit, 2, nullptr, c.mp);
         return;
     }
     const int k = split_at(n, kTriNB);
@@ -253,7 +343,10 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
     std::vector<int> piv_rows;
     while (i < b && t < N) {
         const int wc = std::min(kWin, N - t);
+        const bool prof = c.prof && c.prof->on;
+        if (prof) c.prof->begin(c.s, 1, 0.0, 2.0 * (b - i) * wc * sizeof(T));
         launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small);
+        if (prof) c.prof->end(c.s);
         const int* h = fetch_small(c, 2 + kLeafRows);
         const int d = h[0], stop = h[1];
         for (int a = 0; a < d; ++a) {

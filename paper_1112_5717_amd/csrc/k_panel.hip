@@ -13,7 +13,10 @@
 //  * Elimination inside the window is fraction free:
 //        row_l <- piv * row_l - row_l[t] * row_pivot   (mod p)
 //    which multiplies later rows by nonzero scalars and so preserves every
-//    zero test, but keeps modular inverses off the sequential chain.
+//    zero test, but keeps modular inverses off the sequential chain.  The
+//    tile lives in registers; residues stay in (-p, p) between steps, so
+//    each update is two products and one rounding reduction, and every
+//    product stays below 2 p^2 < 2^53.
 //  * Afterwards the true values are recovered in one parallel pass: with
 //    Sigma_s the product of the first s stored pivots, a C entry frozen at
 //    step s is divided by Sigma_s, the U part of pivot row s by its stored
@@ -32,81 +35,127 @@ namespace {
 
 constexpr int WT = 256;  // threads of the window kernel
 
+// Residue in (-p, p): x - rint(x / p) p, exact for |x| < 2^53.  Zero iff
+// x = 0 mod p.
+__device__ __forceinline__ double red_c(double x, double p, double pinv)
+{
+    return fma(-rint(x * pinv), p, x);
+}
+
+// Register-resident tile: thread (wave w, lane l) holds rows w + 4k
+// (k = 0..15) of columns l and l + 64.  The pivot row and the multiplier
+// column of each step are exchanged through LDS buffers alternating with
+// the step's parity, so one barrier per pivot suffices.
 template <typename T>
 __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t lda, int b, int N,
                                                     int i0, int t0, int wc, ModP mp,
                                                     int* __restrict__ out)
 {
-    __shared__ double tile[kLeafRows][kWin + 1];
+    __shared__ double rowbuf[2][kWin];
+    __shared__ double colbuf[2][kLeafRows];
+    __shared__ int s_j[2];
     __shared__ int s_swap[kLeafRows];
     __shared__ double s_piv[kLeafRows];
     __shared__ double s_isig[kLeafRows + 1];
     __shared__ double s_ipiv[kLeafRows];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int R = b - i0;
     const double P = mp.p, PI = mp.pinv;
 
-    for (int idx = tid; idx < R * wc; idx += WT) {
-        int r = idx / wc, c = idx - r * wc;
-        tile[r][c] = ld_res(A + (int64_t)(i0 + r) * lda + t0 + c);
-    }
-    __syncthreads();
+    double v[2][16];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int r = w + 4 * k, c = lane + 64 * q;
+            v[q][k] = (r < R && c < wc) ? ld_res(A + (int64_t)(i0 + r) * lda + t0 + c) : 0.0;
+        }
 
     int d = 0, stop = STOP_ROWS;
     for (int a = 0;; ++a) {
         if (a >= R) { stop = STOP_ROWS; break; }
         if (a >= wc) { stop = STOP_WINDOW; break; }
-        // leftmost nonzero of row a at positions >= a (identical in every wave)
-        int j = -1;
-        for (int base = a; base < wc; base += 64) {
-            int c = base + lane;
-            bool nz = (c < wc) && (tile[a][c] != 0.0);
-            unsigned long long mask = __ballot(nz);
-            if (mask) { j = base + __ffsll((long long)mask) - 1; break; }
+        const int par = a & 1, qa = a >> 6, la = a & 63;
+        if (w == (a & 3)) {
+            // this wave owns row a: publish it and find its leftmost nonzero
+            const int ka = a >> 2;
+            double x0 = 0.0, x1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                x0 = (k == ka) ? v[0][k] : x0;
+                x1 = (k == ka) ? v[1][k] : x1;
+            }
+            const unsigned long long m0 = __ballot(lane >= a && lane < wc && x0 != 0.0);
+            const unsigned long long m1 = __ballot(lane + 64 >= a && lane + 64 < wc && x1 != 0.0);
+            rowbuf[par][lane] = x0;
+            rowbuf[par][lane + 64] = x1;
+            if (lane == 0)
+                s_j[par] = m0 ? __ffsll((long long)m0) - 1 : (m1 ? 64 + __ffsll((long long)m1) - 1 : -1);
         }
+        if (lane == la) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) colbuf[par][w + 4 * k] = qa ? v[1][k] : v[0][k];
+        }
+        __syncthreads();
+        const int j = s_j[par];
         if (j < 0) { stop = STOP_ZERO_ROW; break; }
         if (j != a) {
-            __syncthreads();  // every wave has finished reading row a
-            for (int r = tid; r < R; r += WT) {
-                double x = tile[r][a];
-                tile[r][a] = tile[r][j];
-                tile[r][j] = x;
+            // swap columns a and j: both live in the same lanes of every wave
+            const int qj = j >> 6, lj = j & 63;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const double ca = qa ? v[1][k] : v[0][k];
+                const double cj = qj ? v[1][k] : v[0][k];
+                const double from_j = __shfl(cj, lj, 64);
+                const double from_a = __shfl(ca, la, 64);
+                if (lane == la) { if (qa) v[1][k] = from_j; else v[0][k] = from_j; }
+                if (lane == lj) { if (qj) v[1][k] = from_a; else v[0][k] = from_a; }
+            }
+            if (lane == la) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) colbuf[par][w + 4 * k] = qa ? v[1][k] : v[0][k];
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double x = rowbuf[par][a];
+                rowbuf[par][a] = rowbuf[par][j];
+                rowbuf[par][j] = x;
             }
             __syncthreads();
         }
-        const double piv = tile[a][a];
-        if (tid == 0) { s_swap[a] = j; s_piv[a] = piv; }
+        const double piv = rowbuf[par][a];
+        if (tid == 0) {
+            s_swap[a] = j;
+            s_piv[a] = mod_red(piv, P, PI);
+        }
         // fraction-free update of rows > a, columns > a
+        const double u0 = rowbuf[par][lane], u1 = rowbuf[par][lane + 64];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            int c = lane + 64 * q;
-            if (c > a && c < wc) {
-                const double u = tile[a][c];
-                for (int r = wave; r < R; r += 4) {
-                    if (r > a) {
-                        double x = fma(piv, tile[r][c], -tile[r][a] * u);
-                        tile[r][c] = mod_red(x, P, PI);
-                    }
-                }
+        for (int k = 0; k < 16; ++k) {
+            const int r = w + 4 * k;
+            if (r > a && r < R) {
+                const double mlt = colbuf[par][r];
+                if (lane > a) v[0][k] = red_c(fma(piv, v[0][k], -mlt * u0), P, PI);
+                if (lane + 64 > a) v[1][k] = red_c(fma(piv, v[1][k], -mlt * u1), P, PI);
             }
         }
-        __syncthreads();
         d = a + 1;
     }
+    __syncthreads();
 
     // Sigma_{s+1} = prod_{s' <= s} piv_{s'}: inclusive scan in wave 0.
-    if (wave == 0) {
-        double v = (lane < d) ? s_piv[lane] : 1.0;
+    if (w == 0) {
+        double x = (lane < d) ? s_piv[lane] : 1.0;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            double o = __shfl_up(v, off, 64);
-            if (lane >= off) v = mod_mul(v, o, P, PI);
+            double o = __shfl_up(x, off, 64);
+            if (lane >= off) x = mod_mul(x, o, P, PI);
         }
-        double sig_prev = __shfl_up(v, 1, 64);  // Sigma_lane
+        double sig_prev = __shfl_up(x, 1, 64);  // Sigma_lane
         if (lane == 0) sig_prev = 1.0;
         if (lane < d) {
-            double isig_next = mod_inv(v, P, PI);        // 1 / Sigma_{lane+1}
+            double isig_next = mod_inv(x, P, PI);  // 1 / Sigma_{lane+1}
             s_isig[lane + 1] = isig_next;
             s_ipiv[lane] = mod_mul(sig_prev, isig_next, P, PI);  // 1 / piv_lane
         }
@@ -114,15 +163,17 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     }
     __syncthreads();
 
-    for (int idx = tid; idx < R * wc; idx += WT) {
-        int r = idx / wc, c = idx - r * wc;
-        double f;
-        int lim = (r + 1 < d) ? r + 1 : d;
-        if (c < lim) f = s_isig[c];
-        else f = (r < d) ? s_ipiv[r] : s_isig[d];
-        double v = mod_mul(tile[r][c], f, P, PI);
-        st_res(A + (int64_t)(i0 + r) * lda + t0 + c, v);
-    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int r = w + 4 * k, c = lane + 64 * q;
+            if (r < R && c < wc) {
+                const int lim = (r + 1 < d) ? r + 1 : d;
+                const double f = (c < lim) ? s_isig[c] : ((r < d) ? s_ipiv[r] : s_isig[d]);
+                st_res(A + (int64_t)(i0 + r) * lda + t0 + c, mod_mul(v[q][k], f, P, PI));
+            }
+        }
     // the same column swaps on the leaf rows above the window block
     for (int r = tid; r < i0; r += WT) {
         T* row = A + (int64_t)r * lda + t0;

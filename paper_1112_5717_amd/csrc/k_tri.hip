@@ -1,14 +1,23 @@
 // Leaves of the triangular routines of Section 3.2 (TRSM, TRMM, TRTRI,
-// TRULM) on blocks of order <= 64, staged in LDS.
+// TRULM) on diagonal blocks of order <= 64.
 //
-// A triangular solve or multiply treats each row (right side, B T^{-1} or
-// B T) or each column (left side, T^{-1} B or T B) of B independently, so
-// one thread owns one vector.  With Mt(i,s) = T[s][i] on the right and
-// T[i][s] on the left, both sides become y = Mt x with Mt effectively lower
-// or upper triangular; solves run in the dependency order, multiplies in
-// the order that lets y overwrite x.  Dot products accumulate exact integer
-// products in FP64 and are reduced mod p every `kred` terms (a bound the
-// host derives from p).
+// A triangular solve B T^{-1} (or T^{-1} B) on a 64-column (64-row) block is
+// a product with the block's inverse, and a triangular multiply is a product
+// with the block itself.  So the solve/multiply leaves are two steps:
+//
+//  * diag_prep: one workgroup per diagonal block of the whole triangle
+//    builds the dense 64 x 64 matrix W = T_bb^{-1} (solve) or W = T_bb
+//    (multiply), padded with the identity, into a workspace.  The inverse
+//    is computed column-parallel (thread j solves T x = e_j) with the
+//    column held in registers and the loops fully unrolled.
+//  * tri_apply: B <- B W (right) or W B (left) for one leaf, every output
+//    an independent 64-term dot product; rows (columns) of B are staged in
+//    LDS so the product can overwrite them in place.
+//
+// Dot products of canonical residues are exact in FP64 while their sum stays
+// below 2^53: 64 terms suffice for p < 2^23.5; for larger p (below 2^26) the
+// partial sum is reduced after every term (the BIG instantiations), since a
+// reduced sum plus one product stays below p + p^2 < 2^53.
 #include "modarith.h"
 
 namespace cup {
@@ -16,192 +25,201 @@ namespace cup {
 namespace {
 
 constexpr int NB = kTriNB;
-constexpr int VT = 128;  // vectors (threads) per workgroup
 
-// Sum_{s in [s0,s1)} Mt[i][s] x[s] mod p with delayed reduction.
-__device__ __forceinline__ double dot_red(const double* mt_row, const double* x, int xstride,
-                                          int s0, int s1, double P, double PI, int64_t kred)
+template <bool BIG>
+__device__ __forceinline__ void maybe_reduce(double& acc, int s, double P, double PI)
 {
-    double acc = 0.0;
-    int64_t cnt = 0;
-    for (int s = s0; s < s1; ++s) {
-        acc = fma(mt_row[s], x[s * xstride], acc);
-        if (++cnt == kred) {
-            acc = mod_red(acc, P, PI);
-            cnt = 0;
-        }
-    }
-    return mod_red(acc, P, PI);
+    (void)s;
+    if (BIG) acc = mod_red(acc, P, PI);
 }
 
-// side: 0 Left, 1 Right.  uplo: 0 Upper, 1 Lower.  op: 0 solve, 1 multiply.
+// Load the triangle of block b (order nb <= 64, at A + o*lda + o) into
+// M[64][65] with zeros outside the triangle, the unit diagonal if `unit`,
+// and identity padding beyond nb.
 template <typename T>
-__global__ __launch_bounds__(VT) void tri_leaf_kernel(int side, int uplo, int unit, int op, int nb,
-                                                      const T* __restrict__ Tm, int64_t ldt,
-                                                      T* __restrict__ B, int64_t ldb, int other,
-                                                      ModP mp, int64_t kred)
+__device__ void load_triangle(double (*M)[NB + 1], const T* A, int64_t lda, int o, int nb,
+                              int uplo, int unit)
 {
-    __shared__ double Mt[NB][NB + 1];
-    __shared__ double dinv[NB];
-    __shared__ double X[NB][VT + 1];  // X[i][v]: element i of vector v
-
-    const int tid = threadIdx.x;
-    const double P = mp.p, PI = mp.pinv;
-    const int v0 = blockIdx.x * VT;
-    const int nv = min(VT, other - v0);
-
-    // Mt(i,s) = T[i][s] (Left) or T[s][i] (Right), restricted to the triangle
-    const bool upper_eff = (side == 0) ? (uplo == 0) : (uplo == 1);
-    for (int idx = tid; idx < nb * nb; idx += VT) {
-        int i = idx / nb, s = idx - i * nb;
-        int tr = (side == 0) ? i : s, tc = (side == 0) ? s : i;
-        bool in = upper_eff ? (s >= i) : (s <= i);
-        double v = in ? ld_res(Tm + (int64_t)tr * ldt + tc) : 0.0;
-        if (s == i && unit) v = 1.0;
-        Mt[i][s] = v;
-    }
-    // vectors: rows of B (Right) or columns of B (Left)
-    if (side == 1) {
-        for (int idx = tid; idx < nv * nb; idx += VT) {
-            int v = idx / nb, i = idx - v * nb;
-            X[i][v] = ld_res(B + (int64_t)(v0 + v) * ldb + i);
-        }
-    } else {
-        for (int idx = tid; idx < nv * nb; idx += VT) {
-            int i = idx / nv, v = idx - i * nv;
-            X[i][v] = ld_res(B + (int64_t)i * ldb + v0 + v);
-        }
-    }
-    __syncthreads();
-    if (op == 0 && !unit)
-        for (int i = tid; i < nb; i += VT) dinv[i] = mod_inv(Mt[i][i], P, PI);
-    __syncthreads();
-
-    if (tid < nv) {
-        double* x = &X[0][tid];
-        const int xs = VT + 1;
-        if (op == 0) {
-            if (!upper_eff) {
-                for (int i = 0; i < nb; ++i) {
-                    double s = dot_red(Mt[i], x, xs, 0, i, P, PI, kred);
-                    double r = x[i * xs] - s;
-                    r = (r < 0.0) ? r + P : r;
-                    x[i * xs] = unit ? r : mod_mul(r, dinv[i], P, PI);
-                }
-            } else {
-                for (int i = nb - 1; i >= 0; --i) {
-                    double s = dot_red(Mt[i], x, xs, i + 1, nb, P, PI, kred);
-                    double r = x[i * xs] - s;
-                    r = (r < 0.0) ? r + P : r;
-                    x[i * xs] = unit ? r : mod_mul(r, dinv[i], P, PI);
-                }
-            }
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+        int i = idx >> 6, s = idx & 63;
+        double v;
+        if (i >= nb || s >= nb) {
+            v = (i == s) ? 1.0 : 0.0;
         } else {
-            if (!upper_eff) {
-                for (int i = nb - 1; i >= 0; --i) x[i * xs] = dot_red(Mt[i], x, xs, 0, i + 1, P, PI, kred);
-            } else {
-                for (int i = 0; i < nb; ++i) x[i * xs] = dot_red(Mt[i], x, xs, i, nb, P, PI, kred);
-            }
+            bool in = (uplo == 0) ? (s >= i) : (s <= i);
+            v = in ? ld_res(A + (int64_t)(o + i) * lda + o + s) : 0.0;
+            if (i == s && unit) v = 1.0;
         }
-    }
-    __syncthreads();
-    if (side == 1) {
-        for (int idx = tid; idx < nv * nb; idx += VT) {
-            int v = idx / nb, i = idx - v * nb;
-            st_res(B + (int64_t)(v0 + v) * ldb + i, X[i][v]);
-        }
-    } else {
-        for (int idx = tid; idx < nv * nb; idx += VT) {
-            int i = idx / nv, v = idx - i * nv;
-            st_res(B + (int64_t)i * ldb + v0 + v, X[i][v]);
-        }
-    }
-}
-
-// In-place inverse of a triangular block: column j of T^{-1} solves T x = e_j.
-template <typename T>
-__global__ __launch_bounds__(NB) void trtri_leaf_kernel(int uplo, int unit, int nb, T* __restrict__ A,
-                                                        int64_t lda, ModP mp, int64_t kred)
-{
-    __shared__ double M[NB][NB + 1];
-    __shared__ double X[NB][NB + 1];
-    __shared__ double dinv[NB];
-    const int tid = threadIdx.x;
-    const double P = mp.p, PI = mp.pinv;
-    for (int idx = tid; idx < nb * nb; idx += NB) {
-        int i = idx / nb, s = idx - i * nb;
-        bool in = (uplo == 0) ? (s >= i) : (s <= i);
-        double v = in ? ld_res(A + (int64_t)i * lda + s) : 0.0;
-        if (s == i && unit) v = 1.0;
         M[i][s] = v;
     }
-    __syncthreads();
-    if (tid < nb) dinv[tid] = unit ? 1.0 : mod_inv(M[tid][tid], P, PI);
-    __syncthreads();
-    if (tid < nb) {
-        const int j = tid;
-        double* x = &X[0][j];
-        const int xs = NB + 1;
-        for (int i = 0; i < nb; ++i) x[i * xs] = (i == j) ? 1.0 : 0.0;
-        if (uplo == 1) {
-            for (int i = j; i < nb; ++i) {
-                double s = dot_red(M[i], x, xs, j, i, P, PI, kred);
-                double r = x[i * xs] - s;
-                r = (r < 0.0) ? r + P : r;
-                x[i * xs] = mod_mul(r, dinv[i], P, PI);
+}
+
+// Column j of the inverse of the triangle in M: solves M x = e_j.
+template <bool BIG>
+__device__ __forceinline__ void inverse_column(const double (*M)[NB + 1], const double* dinv,
+                                               int uplo, int j, double* x, double P, double PI)
+{
+#pragma unroll
+    for (int i = 0; i < NB; ++i) x[i] = 0.0;
+    if (uplo == 1) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < i; ++s) {
+                acc = fma(M[i][s], x[s], acc);
+                maybe_reduce<BIG>(acc, s, P, PI);
             }
-        } else {
-            for (int i = j; i >= 0; --i) {
-                double s = dot_red(M[i], x, xs, i + 1, j + 1, P, PI, kred);
-                double r = x[i * xs] - s;
-                r = (r < 0.0) ? r + P : r;
-                x[i * xs] = mod_mul(r, dinv[i], P, PI);
-            }
+            double r = ((i == j) ? 1.0 : 0.0) - mod_red(acc, P, PI);
+            r = (r < 0.0) ? r + P : r;
+            x[i] = mod_mul(r, dinv[i], P, PI);
         }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nb * nb; idx += NB) {
-        int i = idx / nb, s = idx - i * nb;
-        bool write = (uplo == 0) ? (unit ? s > i : s >= i) : (unit ? s < i : s <= i);
-        if (write) st_res(A + (int64_t)i * lda + s, X[i][s]);
+    } else {
+#pragma unroll
+        for (int i = NB - 1; i >= 0; --i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int s = i + 1; s < NB; ++s) {
+                acc = fma(M[i][s], x[s], acc);
+                maybe_reduce<BIG>(acc, s, P, PI);
+            }
+            double r = ((i == j) ? 1.0 : 0.0) - mod_red(acc, P, PI);
+            r = (r < 0.0) ? r + P : r;
+            x[i] = mod_mul(r, dinv[i], P, PI);
+        }
     }
 }
 
-// [N\T] <- T N with T unit upper (strict upper part stored) and N lower
-// (diagonal stored): X[i][j] = sum_{s >= max(i,j)} T[i][s] N[s][j].
-template <typename T>
-__global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ A, int64_t lda,
-                                                        ModP mp, int64_t kred)
+// mode 0: W[b] = T_bb^{-1}; mode 1: W[b] = T_bb; mode 2: T_bb <- T_bb^{-1} in
+// place (the unit diagonal, if any, is left untouched).  One block of 64
+// threads per diagonal block.
+template <typename T, bool BIG>
+__global__ __launch_bounds__(NB) void diag_prep_kernel(T* __restrict__ A, int64_t lda, int n, int uplo,
+                                                       int unit, int mode, double* __restrict__ W,
+                                                       ModP mp)
 {
-    __shared__ double Tu[NB][NB + 1];
-    __shared__ double Nl[NB][NB + 1];
-    __shared__ double X[NB][NB + 1];
+    __shared__ double M[NB][NB + 1];
+    __shared__ double dinv[NB];
+    const int b = blockIdx.x, o = b * NB, nb = min(NB, n - o), j = threadIdx.x;
+    const double P = mp.p, PI = mp.pinv;
+    load_triangle(M, A, lda, o, nb, uplo, unit);
+    __syncthreads();
+    if (mode == 1) {
+        double* Wb = W + (size_t)b * NB * NB;
+        for (int i = 0; i < NB; ++i) Wb[i * NB + j] = M[i][j];
+        return;
+    }
+    dinv[j] = (unit || j >= nb) ? 1.0 : mod_inv(M[j][j], P, PI);
+    __syncthreads();
+    double x[NB];
+    inverse_column<BIG>(M, dinv, uplo, j, x, P, PI);
+    if (mode == 0) {
+        double* Wb = W + (size_t)b * NB * NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) Wb[i * NB + j] = x[i];
+    } else if (j < nb) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            bool write = (uplo == 0) ? (unit ? j > i : j >= i) : (unit ? j < i : j <= i);
+            if (i < nb && write) st_res(A + (int64_t)(o + i) * lda + o + j, x[i]);
+        }
+    }
+}
+
+// B <- B W (side 1, B is rows x nb) or W B (side 0, B is nb x cols), W dense
+// 64 x 64 (identity beyond nb).  Each workgroup owns 64 rows (right) or 64
+// columns (left) of B.
+template <typename T, bool BIG>
+__global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const double* __restrict__ W,
+                                                        T* __restrict__ B, int64_t ldb, int other,
+                                                        ModP mp)
+{
+    __shared__ double Ws[NB][NB + 1];
+    __shared__ double Bs[NB][NB + 1];
     const int tid = threadIdx.x;
     const double P = mp.p, PI = mp.pinv;
-    for (int idx = tid; idx < nb * nb; idx += NB) {
-        int i = idx / nb, s = idx - i * nb;
-        double v = ld_res(A + (int64_t)i * lda + s);
-        Tu[i][s] = (s > i) ? v : (s == i ? 1.0 : 0.0);
-        Nl[i][s] = (s <= i) ? v : 0.0;
-    }
-    __syncthreads();
-    if (tid < nb) {
-        const int j = tid;
-        for (int i = 0; i < nb; ++i) {
-            int s0 = i > j ? i : j;
-            double acc = 0.0;
-            int64_t cnt = 0;
-            for (int s = s0; s < nb; ++s) {
-                acc = fma(Tu[i][s], Nl[s][j], acc);
-                if (++cnt == kred) { acc = mod_red(acc, P, PI); cnt = 0; }
-            }
-            X[i][j] = mod_red(acc, P, PI);
+    const int v0 = blockIdx.x * NB;
+    const int nv = min(NB, other - v0);
+    for (int idx = tid; idx < NB * NB; idx += 256) Ws[idx >> 6][idx & 63] = W[idx];
+    // Bs[v][i]: element i of vector v (row of B on the right, column on the left)
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        int a = idx >> 6, c = idx & 63;
+        double val = 0.0;
+        if (side == 1) {  // a = vector (row), c = element
+            if (a < nv && c < nb) val = ld_res(B + (int64_t)(v0 + a) * ldb + c);
+            Bs[a][c] = val;
+        } else {          // a = element (row of B), c = vector (column)
+            if (a < nb && c < nv) val = ld_res(B + (int64_t)a * ldb + v0 + c);
+            Bs[c][a] = val;
         }
     }
     __syncthreads();
-    for (int idx = tid; idx < nb * nb; idx += NB) {
-        int i = idx / nb, s = idx - i * nb;
-        st_res(A + (int64_t)i * lda + s, X[i][s]);
+    // thread: vector v = tid & 63, outputs e = (tid >> 6) * 16 .. +16
+    const int v = tid & 63, e0 = (tid >> 6) * 16;
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+#pragma unroll 4
+    for (int s = 0; s < NB; ++s) {
+        const double bv = Bs[v][s];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            // right: out[v][e] = sum_s B[v][s] W[s][e]; left: out[e][v] = sum_s W[e][s] B[s][v]
+            const double w = (side == 1) ? Ws[s][e0 + q] : Ws[e0 + q][s];
+            acc[q] = fma(bv, w, acc[q]);
+        }
+        if (BIG) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = mod_red(acc[q], P, PI);
+        }
+    }
+    if (v < nv) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = e0 + q;
+            if (e < nb) {
+                T* dst = (side == 1) ? B + (int64_t)(v0 + v) * ldb + e : B + (int64_t)e * ldb + v0 + v;
+                st_res(dst, mod_red(acc[q], P, PI));
+            }
+        }
+    }
+}
+
+// [N\T] <- T N on an nb x nb block (nb <= 64): T unit upper (strict upper
+// part stored), N lower with its diagonal.  Thread j holds column j of N.
+template <typename T, bool BIG>
+__global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ A, int64_t lda, ModP mp)
+{
+    __shared__ double Tu[NB][NB + 1];
+    const int j = threadIdx.x;
+    const double P = mp.p, PI = mp.pinv;
+    for (int idx = j; idx < NB * NB; idx += NB) {
+        int i = idx >> 6, s = idx & 63;
+        double v = 0.0;
+        if (i < nb && s < nb) v = (s > i) ? ld_res(A + (int64_t)i * lda + s) : (s == i ? 1.0 : 0.0);
+        Tu[i][s] = v;
+    }
+    double ncol[NB];
+#pragma unroll
+    for (int s = 0; s < NB; ++s)
+        ncol[s] = (j < nb && s < nb && s >= j) ? ld_res(A + (int64_t)s * lda + j) : 0.0;
+    __syncthreads();
+    double x[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int s = i; s < NB; ++s) {
+            acc = fma(Tu[i][s], ncol[s], acc);
+            maybe_reduce<BIG>(acc, s, P, PI);
+        }
+        x[i] = mod_red(acc, P, PI);
+    }
+    __syncthreads();  // every read of the block is done before it is overwritten
+    if (j < nb) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            if (i < nb) st_res(A + (int64_t)i * lda + j, x[i]);
     }
 }
 
@@ -217,33 +235,49 @@ __global__ void negate_kernel(T* __restrict__ B, int64_t ldb, int rows, int cols
     }
 }
 
+inline bool big_prime(const ModP& mp) { return mp.p > 11863283.0; }  // 64 (p-1)^2 >= 2^53
+
 }  // namespace
 
 template <typename T>
-void launch_tri_leaf(hipStream_t s, int side, int uplo, int unit, int op, int nb, const T* Tm,
-                     int64_t ldt, T* B, int64_t ldb, int other, ModP mp, int64_t kred)
+void launch_diag_prep(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, int mode,
+                      double* W, ModP mp)
 {
-    if (nb <= 0 || other <= 0) return;
-    hipLaunchKernelGGL(tri_leaf_kernel<T>, dim3((other + VT - 1) / VT), dim3(VT), 0, s, side, uplo,
-                       unit, op, nb, Tm, ldt, B, ldb, other, mp, kred);
+    if (n <= 0) return;
+    const int nblk = (mode == 2) ? 1 : (n + NB - 1) / NB;
+    if (big_prime(mp))
+        hipLaunchKernelGGL((diag_prep_kernel<T, true>), dim3(nblk), dim3(NB), 0, s, A, lda, n, uplo,
+                           unit, mode, W, mp);
+    else
+        hipLaunchKernelGGL((diag_prep_kernel<T, false>), dim3(nblk), dim3(NB), 0, s, A, lda, n, uplo,
+                           unit, mode, W, mp);
     CUP_HIP(hipGetLastError());
 }
 
 template <typename T>
-void launch_trtri_leaf(hipStream_t s, int uplo, int unit, int nb, T* A, int64_t lda, ModP mp,
-                       int64_t kred)
+void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, int64_t ldb, int other,
+                      ModP mp)
 {
-    if (nb <= 0) return;
-    hipLaunchKernelGGL(trtri_leaf_kernel<T>, dim3(1), dim3(NB), 0, s, uplo, unit, nb, A, lda, mp,
-                       kred);
+    if (nb <= 0 || other <= 0) return;
+    dim3 grid((other + NB - 1) / NB);
+    if (big_prime(mp))
+        hipLaunchKernelGGL((tri_apply_kernel<T, true>), grid, dim3(256), 0, s, side, nb, W, B, ldb,
+                           other, mp);
+    else
+        hipLaunchKernelGGL((tri_apply_kernel<T, false>), grid, dim3(256), 0, s, side, nb, W, B, ldb,
+                           other, mp);
     CUP_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_trulm_leaf(hipStream_t s, int nb, T* A, int64_t lda, ModP mp, int64_t kred)
 {
+    (void)kred;
     if (nb <= 0) return;
-    hipLaunchKernelGGL(trulm_leaf_kernel<T>, dim3(1), dim3(NB), 0, s, nb, A, lda, mp, kred);
+    if (big_prime(mp))
+        hipLaunchKernelGGL((trulm_leaf_kernel<T, true>), dim3(1), dim3(NB), 0, s, nb, A, lda, mp);
+    else
+        hipLaunchKernelGGL((trulm_leaf_kernel<T, false>), dim3(1), dim3(NB), 0, s, nb, A, lda, mp);
     CUP_HIP(hipGetLastError());
 }
 
@@ -251,16 +285,20 @@ template <typename T>
 void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp)
 {
     if (rows <= 0 || cols <= 0) return;
-    hipLaunchKernelGGL(negate_kernel<T>, dim3((cols + 255) / 256, rows), dim3(256), 0, s, B, ldb,
-                       rows, cols, mp.p);
-    CUP_HIP(hipGetLastError());
+    for (int r0 = 0; r0 < rows; r0 += 65535) {
+        int rr = std::min(65535, rows - r0);
+        hipLaunchKernelGGL(negate_kernel<T>, dim3((cols + 255) / 256, rr), dim3(256), 0, s,
+                           B + (int64_t)r0 * ldb, ldb, rr, cols, mp.p);
+        CUP_HIP(hipGetLastError());
+    }
 }
 
-#define CUP_INST(T)                                                                           \
-    template void launch_tri_leaf<T>(hipStream_t, int, int, int, int, int, const T*, int64_t, \
-                                     T*, int64_t, int, ModP, int64_t);                        \
-    template void launch_trtri_leaf<T>(hipStream_t, int, int, int, T*, int64_t, ModP, int64_t); \
-    template void launch_trulm_leaf<T>(hipStream_t, int, T*, int64_t, ModP, int64_t);         \
+#define CUP_INST(T)                                                                             \
+    template void launch_diag_prep<T>(hipStream_t, T*, int64_t, int, int, int, int, double*,    \
+                                      ModP);                                                    \
+    template void launch_tri_apply<T>(hipStream_t, int, int, const double*, T*, int64_t, int,   \
+                                      ModP);                                                    \
+    template void launch_trulm_leaf<T>(hipStream_t, int, T*, int64_t, ModP, int64_t);           \
     template void launch_negate<T>(hipStream_t, T*, int64_t, int, int, ModP);
 CUP_INST(int64_t)
 CUP_INST(int8_t)

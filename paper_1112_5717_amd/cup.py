@@ -40,6 +40,8 @@ SIGNATURES = {
     "cup_ffgemm_i8": (ctypes.c_int, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _I64,
                                      ctypes.c_int]),
     "cup_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "cup_profile": (ctypes.c_int, [ctypes.c_int]),
+    "cup_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double)]),
     "cup_workspace_bytes": (ctypes.c_size_t, []),
     "cup_finalize": (ctypes.c_int, []),
 }
@@ -211,6 +213,19 @@ def cup_ffgemm(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, p: int, alpha:
     rc = getattr(load(), name)(M, N, K, pa, lda, pb, ldb, pc, ldc, int(p), int(alpha))
     if rc < 0:
         raise CupError(rc, name)
+
+
+def cup_profile(enable: bool) -> None:
+    load().cup_profile(1 if enable else 0)
+
+
+def cup_profile_read() -> dict:
+    """Kernel timing collected since cup_profile(True)."""
+    buf = (ctypes.c_double * 8)()
+    load().cup_profile_read(buf)
+    v = list(buf)
+    keys = ("launches", "ms", "flops", "bytes")
+    return {"ffgemm": dict(zip(keys, v[0:4])), "window": dict(zip(keys, v[4:8]))}
 
 
 def cup_workspace_bytes() -> int:
