@@ -107,7 +107,7 @@ inline void ctx_set_prime(Ctx& c, int64_t p)
     const double two53 = 9007199254740992.0;
     double h = (double)(p / 2);
     double steps = std::floor((two53 - 1.0 - (double)p) / (4.0 * h * h));
-    c.kred_steps = (int)std::min(steps, 1.0e9);
+    c.kred_steps = (int)std::min(steps, (double)(1 << 28));
     double pm1 = (double)(p - 1);
     double terms = std::floor((two53 - 1.0) / (pm1 * pm1));
     c.kred = (int64_t)std::min(terms, 1.0e12);

@@ -5,9 +5,10 @@
 // triangular routines) is an exact integer contraction.  Operands are
 // loaded in centred form (|x| <= p/2) and accumulated in FP64 MFMA
 // registers; every partial sum is an integer of magnitude below 2^53, so the
-// FP64 datapath is an exact integer carrier.  The accumulators are reduced
-// mod p every `kred_steps` MFMA k-steps (4 products per lane-element each),
-// a bound the host derives from p: p + 4 kred_steps (p/2)^2 < 2^53.
+// FP64 datapath is an exact integer carrier.  The kernel reduces mod p only
+// in its epilogue: the host splits K into chunks of at most kmax terms with
+// kmax (p/2)^2 < 2^53 - p (over two million terms for p = 65521, 512 for
+// p < 2^23), one launch per chunk.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup (4 wave64s, 64 x 64
 // each as 4 x 4 blocks of v_mfma_f64_16x16x4f64), K tiles of 16 staged
@@ -21,21 +22,23 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int PADM = 16;  // row stride 144 doubles: k-rows land 32 banks apart
+constexpr int PADM = 16;  // row stride 144 doubles: adjacent k-rows 16 double-banks apart
 
-template <typename T>
-__device__ __forceinline__ double ld_centred(const T* a, double half, double p)
+// The residue as a 32-bit integer (int64 storage: its low word).
+__device__ __forceinline__ int ld_raw(const int64_t* a) { return *reinterpret_cast<const int*>(a); }
+__device__ __forceinline__ int ld_raw(const int8_t* a) { return (int)*a; }
+
+__device__ __forceinline__ double centre(double v, double half, double p)
 {
-    double v = ld_res(a);
     return v > half ? v - p : v;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void ffgemm_f64_kernel(int M, int N, int K,
+__global__ __launch_bounds__(256, 2) void ffgemm_f64_kernel(int M, int N, int K,
                                                          const T* __restrict__ A, int64_t lda,
                                                          const T* __restrict__ B, int64_t ldb,
                                                          T* __restrict__ C, int64_t ldc, ModP mp,
-                                                         int alpha, int kred_steps)
+                                                         int alpha)
 {
     __shared__ double As[2][BK][BM + PADM];
     __shared__ double Bs[2][BK][BN + PADM];
@@ -55,39 +58,59 @@ __global__ __launch_bounds__(256) void ffgemm_f64_kernel(int M, int N, int K,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    double ra[8], rb[8];
+    // Rows beyond M and columns beyond N read a clamped (valid) address: they
+    // only feed outputs that are never stored.  K is zero-padded.
     const int ac = tid & 15, ar = tid >> 4;    // A tile: 16 k-columns x 128 rows
     const int bc = tid & 127, br = tid >> 7;   // B tile: 16 k-rows x 128 columns
+    const T* pa[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pa[i] = A + (int64_t)min(m0 + ar + 16 * i, M - 1) * lda + ac;
+    const T* pb = B + (int64_t)br * ldb + min(n0 + bc, N - 1);
+    const int64_t ldb2 = 2 * ldb;
+    // raw residues of the next tile; converted to centred doubles only when
+    // they are written to LDS, after the MFMAs of the current tile
+    int ra[8], rb[8];
 
-    auto load = [&](int k0) {
+    auto load_full = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ra[i] = ld_raw(pa[i] + k0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) rb[i] = ld_raw(pb + (int64_t)k0 * ldb + i * ldb2);
+    };
+    auto load_tail = [&](int k0) {
+        // out-of-range k reads a valid address and is zeroed
+        const bool ka = k0 + ac < K;
+        const int ka_off = ka ? k0 : K - 1 - ac;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            int gm = m0 + ar + 16 * i, gk = k0 + ac;
-            ra[i] = (gm < M && gk < K) ? ld_centred(A + (int64_t)gm * lda + gk, half, P) : 0.0;
+            int x = ld_raw(pa[i] + ka_off);
+            ra[i] = ka ? x : 0;
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            int gk = k0 + br + 2 * i, gn = n0 + bc;
-            rb[i] = (gk < K && gn < N) ? ld_centred(B + (int64_t)gk * ldb + gn, half, P) : 0.0;
+            const bool kb = k0 + br + 2 * i < K;
+            const int64_t off = kb ? (int64_t)k0 * ldb + i * ldb2 : (int64_t)(K - 1 - br) * ldb;
+            int x = ld_raw(pb + off);
+            rb[i] = kb ? x : 0;
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) As[buf][ac][ar + 16 * i] = ra[i];
+        for (int i = 0; i < 8; ++i) As[buf][ac][ar + 16 * i] = centre((double)ra[i], half, P);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) Bs[buf][br + 2 * i][bc] = rb[i];
+        for (int i = 0; i < 8; ++i) Bs[buf][br + 2 * i][bc] = centre((double)rb[i], half, P);
     };
 
     const int ntiles = (K + BK - 1) / BK;
-    int since = 0;
-    if (ntiles > 0) {
-        load(0);
-        store(0);
-    }
+    const int nfull = K / BK;
+    if (nfull > 0) load_full(0);
+    else load_tail(0);
+    store(0);
     __syncthreads();
     for (int kt = 0; kt < ntiles; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < ntiles) load((kt + 1) * BK);
+        if (kt + 1 < nfull) load_full((kt + 1) * BK);
+        else if (kt + 1 < ntiles) load_tail((kt + 1) * BK);
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             double a[4], b[4];
@@ -101,30 +124,25 @@ __global__ __launch_bounds__(256) void ffgemm_f64_kernel(int M, int N, int K,
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-            if (++since == kred_steps) {
-                since = 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) acc[i][j][e] = mod_red(acc[i][j][e], P, PI);
-            }
         }
         if (kt + 1 < ntiles) store(buf ^ 1);
         __syncthreads();
     }
 
     // Epilogue: in each 16x16 block, lane l holds column l%16 of rows
-    // l/16 + 4e, e = 0..3 (the v_mfma_f64_16x16x4f64 result layout).
+    // l/16 + 4e, e = 0..3 (the v_mfma_f64_16x16x4f64 result layout).  One
+    // block at a time, so the C loads of all 64 outputs are not hoisted
+    // together.
+    const int gn0 = n0 + wn + (lane & 15);
+    const int gm0 = m0 + wm + (lane >> 4);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+            const int gn = gn0 + j * 16;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                int gm = m0 + wm + i * 16 + (lane >> 4) + 4 * e;
-                int gn = n0 + wn + j * 16 + (lane & 15);
+                const int gm = gm0 + i * 16 + 4 * e;
                 if (gm < M && gn < N) {
                     T* cp = C + (int64_t)gm * ldc + gn;
                     double s = mod_red(acc[i][j][e], P, PI);
@@ -135,6 +153,8 @@ __global__ __launch_bounds__(256) void ffgemm_f64_kernel(int M, int N, int K,
                     st_res(cp, r);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
+        }
 }
 
 }  // namespace
@@ -145,9 +165,14 @@ void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t l
 {
     if (M <= 0 || N <= 0 || K <= 0) return;
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-    hipLaunchKernelGGL(ffgemm_f64_kernel<T>, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
-                       ldc, mp, alpha, kred_steps);
-    CUP_HIP(hipGetLastError());
+    // products per lane-element before the sum could reach 2^53 (>= 4)
+    const int64_t kmax = std::max<int64_t>(4, std::min<int64_t>(4 * (int64_t)kred_steps, K));
+    for (int64_t k0 = 0; k0 < K; k0 += kmax) {
+        const int kc = (int)std::min<int64_t>(kmax, K - k0);
+        hipLaunchKernelGGL(ffgemm_f64_kernel<T>, grid, dim3(256), 0, s, M, N, kc, A + k0, lda,
+                           B + k0 * ldb, ldb, C, ldc, mp, alpha);
+        CUP_HIP(hipGetLastError());
+    }
 }
 
 template void launch_ffgemm_f64<int64_t>(hipStream_t, int, int, int, const int64_t*, int64_t,

@@ -26,13 +26,6 @@ namespace {
 
 constexpr int NB = kTriNB;
 
-template <bool BIG>
-__device__ __forceinline__ void maybe_reduce(double& acc, int s, double P, double PI)
-{
-    (void)s;
-    if (BIG) acc = mod_red(acc, P, PI);
-}
-
 // Load the triangle of block b (order nb <= 64, at A + o*lda + o) into
 // M[64][65] with zeros outside the triangle, the unit diagonal if `unit`,
 // and identity padding beyond nb.
@@ -54,8 +47,9 @@ __device__ void load_triangle(double (*M)[NB + 1], const T* A, int64_t lda, int 
     }
 }
 
-// Column j of the inverse of the triangle in M: solves M x = e_j.
-template <bool BIG>
+// Column j of the inverse of the triangle in M: solves M x = e_j, with the
+// column in registers and the loops unrolled (sums of up to 64 products
+// stay exact: p < 2^23.5).
 __device__ __forceinline__ void inverse_column(const double (*M)[NB + 1], const double* dinv,
                                                int uplo, int j, double* x, double P, double PI)
 {
@@ -66,10 +60,7 @@ __device__ __forceinline__ void inverse_column(const double (*M)[NB + 1], const 
         for (int i = 0; i < NB; ++i) {
             double acc = 0.0;
 #pragma unroll
-            for (int s = 0; s < i; ++s) {
-                acc = fma(M[i][s], x[s], acc);
-                maybe_reduce<BIG>(acc, s, P, PI);
-            }
+            for (int s = 0; s < i; ++s) acc = fma(M[i][s], x[s], acc);
             double r = ((i == j) ? 1.0 : 0.0) - mod_red(acc, P, PI);
             r = (r < 0.0) ? r + P : r;
             x[i] = mod_mul(r, dinv[i], P, PI);
@@ -79,14 +70,28 @@ __device__ __forceinline__ void inverse_column(const double (*M)[NB + 1], const 
         for (int i = NB - 1; i >= 0; --i) {
             double acc = 0.0;
 #pragma unroll
-            for (int s = i + 1; s < NB; ++s) {
-                acc = fma(M[i][s], x[s], acc);
-                maybe_reduce<BIG>(acc, s, P, PI);
-            }
+            for (int s = i + 1; s < NB; ++s) acc = fma(M[i][s], x[s], acc);
             double r = ((i == j) ? 1.0 : 0.0) - mod_red(acc, P, PI);
             r = (r < 0.0) ? r + P : r;
             x[i] = mod_mul(r, dinv[i], P, PI);
         }
+    }
+}
+
+// The same for p >= 2^23.5: rolled loops, the column in LDS (X[.][j]), the
+// partial sum reduced after every product.
+__device__ void inverse_column_big(const double (*M)[NB + 1], const double* dinv, int uplo,
+                                   int j, double (*X)[NB + 1], double P, double PI)
+{
+    for (int i = 0; i < NB; ++i) X[i][j] = 0.0;
+    for (int t = 0; t < NB; ++t) {
+        const int i = (uplo == 1) ? t : NB - 1 - t;
+        const int s0 = (uplo == 1) ? 0 : i + 1, s1 = (uplo == 1) ? i : NB;
+        double acc = 0.0;
+        for (int s = s0; s < s1; ++s) acc = mod_red(fma(M[i][s], X[s][j], acc), P, PI);
+        double r = ((i == j) ? 1.0 : 0.0) - acc;
+        r = (r < 0.0) ? r + P : r;
+        X[i][j] = mod_mul(r, dinv[i], P, PI);
     }
 }
 
@@ -112,7 +117,13 @@ __global__ __launch_bounds__(NB) void diag_prep_kernel(T* __restrict__ A, int64_
     dinv[j] = (unit || j >= nb) ? 1.0 : mod_inv(M[j][j], P, PI);
     __syncthreads();
     double x[NB];
-    inverse_column<BIG>(M, dinv, uplo, j, x, P, PI);
+    if constexpr (BIG) {
+        __shared__ double X[NB][NB + 1];
+        inverse_column_big(M, dinv, uplo, j, X, P, PI);
+        for (int i = 0; i < NB; ++i) x[i] = X[i][j];
+    } else {
+        inverse_column(M, dinv, uplo, j, x, P, PI);
+    }
     if (mode == 0) {
         double* Wb = W + (size_t)b * NB * NB;
 #pragma unroll
@@ -206,14 +217,27 @@ __global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ 
     __syncthreads();
     double x[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        double acc = 0.0;
+    for (int q = 0; q < NB; ++q) x[q] = 0.0;
+    if constexpr (BIG) {
+        for (int i = 0; i < NB; ++i) {
+            double acc = 0.0;
+            for (int s = i; s < NB; ++s) {
+                double nv = 0.0;
 #pragma unroll
-        for (int s = i; s < NB; ++s) {
-            acc = fma(Tu[i][s], ncol[s], acc);
-            maybe_reduce<BIG>(acc, s, P, PI);
+                for (int q = 0; q < NB; ++q) nv = (q == s) ? ncol[q] : nv;
+                acc = mod_red(fma(Tu[i][s], nv, acc), P, PI);
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) x[q] = (q == i) ? acc : x[q];
         }
-        x[i] = mod_red(acc, P, PI);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int s = i; s < NB; ++s) acc = fma(Tu[i][s], ncol[s], acc);
+            x[i] = mod_red(acc, P, PI);
+        }
     }
     __syncthreads();  // every read of the block is done before it is overwritten
     if (j < nb) {
