@@ -11,7 +11,8 @@
 // p < 2^23), one launch per chunk.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup (4 wave64s, 64 x 64
-// each as 4 x 4 blocks of v_mfma_f64_16x16x4f64), K tiles of 16 staged
+// each as 4 x 4 blocks of v_mfma_f64_16x16x4f64), or 64 x 64 tiles for
+// products too small to give two workgroups per CU; K tiles of 16 staged
 // through LDS (double-buffered, register prefetch of the next tile).
 #include "modarith.h"
 
@@ -21,8 +22,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int PADM = 16;  // row stride 144 doubles: adjacent k-rows 16 double-banks apart
+constexpr int BK = 16;
+constexpr int PADM = 16;  // LDS row stride BM+16 doubles: adjacent k-rows 16 double-banks apart
 
 // The residue as a 32-bit integer (int64 storage: its low word).
 __device__ __forceinline__ int ld_raw(const int64_t* a) { return *reinterpret_cast<const int*>(a); }
@@ -33,72 +34,78 @@ __device__ __forceinline__ double centre(double v, double half, double p)
     return v > half ? v - p : v;
 }
 
-template <typename T>
+// Workgroup tile BM x BN computed by 4 waves arranged 2 x 2, each a
+// (BM/2) x (BN/2) block of 16x16 MFMA tiles.
+template <typename T, int BM, int BN>
 __global__ __launch_bounds__(256, 2) void ffgemm_f64_kernel(int M, int N, int K,
                                                          const T* __restrict__ A, int64_t lda,
                                                          const T* __restrict__ B, int64_t ldb,
                                                          T* __restrict__ C, int64_t ldc, ModP mp,
                                                          int alpha)
 {
+    constexpr int TM = BM / 32, TN = BN / 32;      // 16x16 tiles per wave
     __shared__ double As[2][BK][BM + PADM];
     __shared__ double Bs[2][BK][BN + PADM];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 64;
-    const int wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * (BM / 2);
+    const int wn = (wave & 1) * (BN / 2);
     const int m0 = blockIdx.y * BM;
     const int n0 = blockIdx.x * BN;
     const double P = mp.p, PI = mp.pinv, half = floor(mp.p * 0.5);
 
-    v4d acc[4][4];
+    v4d acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
     // Rows beyond M and columns beyond N read a clamped (valid) address: they
     // only feed outputs that are never stored.  K is zero-padded.
-    const int ac = tid & 15, ar = tid >> 4;    // A tile: 16 k-columns x 128 rows
-    const int bc = tid & 127, br = tid >> 7;   // B tile: 16 k-rows x 128 columns
-    const T* pa[8];
+    constexpr int NA = BM / 16;                // A loads per thread: 16 rows per pass
+    constexpr int BSTEP = 256 / BN;            // B rows per pass
+    constexpr int NB_ = BK / BSTEP;            // B loads per thread
+    const int ac = tid & 15, ar = tid >> 4;    // A tile: 16 k-columns x BM rows
+    const int bc = tid % BN, br = tid / BN;    // B tile: 16 k-rows x BN columns
+    const T* pa[NA];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) pa[i] = A + (int64_t)min(m0 + ar + 16 * i, M - 1) * lda + ac;
+    for (int i = 0; i < NA; ++i) pa[i] = A + (int64_t)min(m0 + ar + 16 * i, M - 1) * lda + ac;
     const T* pb = B + (int64_t)br * ldb + min(n0 + bc, N - 1);
-    const int64_t ldb2 = 2 * ldb;
+    const int64_t ldbs = BSTEP * ldb;
     // raw residues of the next tile; converted to centred doubles only when
     // they are written to LDS, after the MFMAs of the current tile
-    int ra[8], rb[8];
+    int ra[NA], rb[NB_];
 
     auto load_full = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) ra[i] = ld_raw(pa[i] + k0);
+        for (int i = 0; i < NA; ++i) ra[i] = ld_raw(pa[i] + k0);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) rb[i] = ld_raw(pb + (int64_t)k0 * ldb + i * ldb2);
+        for (int i = 0; i < NB_; ++i) rb[i] = ld_raw(pb + (int64_t)k0 * ldb + i * ldbs);
     };
     auto load_tail = [&](int k0) {
         // out-of-range k reads a valid address and is zeroed
         const bool ka = k0 + ac < K;
         const int ka_off = ka ? k0 : K - 1 - ac;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < NA; ++i) {
             int x = ld_raw(pa[i] + ka_off);
             ra[i] = ka ? x : 0;
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const bool kb = k0 + br + 2 * i < K;
-            const int64_t off = kb ? (int64_t)k0 * ldb + i * ldb2 : (int64_t)(K - 1 - br) * ldb;
+        for (int i = 0; i < NB_; ++i) {
+            const bool kb = k0 + br + BSTEP * i < K;
+            const int64_t off = kb ? (int64_t)k0 * ldb + i * ldbs : (int64_t)(K - 1 - br) * ldb;
             int x = ld_raw(pb + off);
             rb[i] = kb ? x : 0;
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) As[buf][ac][ar + 16 * i] = centre((double)ra[i], half, P);
+        for (int i = 0; i < NA; ++i) As[buf][ac][ar + 16 * i] = centre((double)ra[i], half, P);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) Bs[buf][br + 2 * i][bc] = centre((double)rb[i], half, P);
+        for (int i = 0; i < NB_; ++i) Bs[buf][br + BSTEP * i][bc] = centre((double)rb[i], half, P);
     };
 
     const int ntiles = (K + BK - 1) / BK;
@@ -113,16 +120,16 @@ __global__ __launch_bounds__(256, 2) void ffgemm_f64_kernel(int M, int N, int K,
         else if (kt + 1 < ntiles) load_tail((kt + 1) * BK);
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
-            double a[4], b[4];
+            double a[TM], b[TN];
             const int kk = ks * 4 + (lane >> 4);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[buf][kk][wm + i * 16 + (lane & 15)];
+            for (int i = 0; i < TM; ++i) a[i] = As[buf][kk][wm + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kk][wn + j * 16 + (lane & 15)];
+            for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kk][wn + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (kt + 1 < ntiles) store(buf ^ 1);
@@ -136,9 +143,9 @@ __global__ __launch_bounds__(256, 2) void ffgemm_f64_kernel(int M, int N, int K,
     const int gn0 = n0 + wn + (lane & 15);
     const int gm0 = m0 + wm + (lane >> 4);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < TN; ++j) {
             const int gn = gn0 + j * 16;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -164,13 +171,21 @@ void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t l
                        int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, int kred_steps)
 {
     if (M <= 0 || N <= 0 || K <= 0) return;
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
     // products per lane-element before the sum could reach 2^53 (>= 4)
     const int64_t kmax = std::max<int64_t>(4, std::min<int64_t>(4 * (int64_t)kred_steps, K));
+    // 128 x 128 tiles when they give at least two workgroups per CU, else 64 x 64
+    const bool big = (int64_t)((M + 127) / 128) * ((N + 127) / 128) >= 512;
     for (int64_t k0 = 0; k0 < K; k0 += kmax) {
         const int kc = (int)std::min<int64_t>(kmax, K - k0);
-        hipLaunchKernelGGL(ffgemm_f64_kernel<T>, grid, dim3(256), 0, s, M, N, kc, A + k0, lda,
-                           B + k0 * ldb, ldb, C, ldc, mp, alpha);
+        if (big) {
+            dim3 grid((N + 127) / 128, (M + 127) / 128);
+            hipLaunchKernelGGL((ffgemm_f64_kernel<T, 128, 128>), grid, dim3(256), 0, s, M, N, kc,
+                               A + k0, lda, B + k0 * ldb, ldb, C, ldc, mp, alpha);
+        } else {
+            dim3 grid((N + 63) / 64, (M + 63) / 64);
+            hipLaunchKernelGGL((ffgemm_f64_kernel<T, 64, 64>), grid, dim3(256), 0, s, M, N, kc,
+                               A + k0, lda, B + k0 * ldb, ldb, C, ldc, mp, alpha);
+        }
         CUP_HIP(hipGetLastError());
     }
 }

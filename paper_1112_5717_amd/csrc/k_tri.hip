@@ -48,32 +48,33 @@ __device__ void load_triangle(double (*M)[NB + 1], const T* A, int64_t lda, int 
 }
 
 // Column j of the inverse of the triangle in M: solves M x = e_j, with the
-// column in registers and the loops unrolled (sums of up to 64 products
-// stay exact: p < 2^23.5).
+// column in registers and the loops unrolled.  Right-looking: once x[i] is
+// known it is folded into the partial sums of every later row, so the
+// dependency chain is one multiply per row and the updates run in parallel.
+// Sums of up to 64 products stay exact for p < 2^23.5.
 __device__ __forceinline__ void inverse_column(const double (*M)[NB + 1], const double* dinv,
                                                int uplo, int j, double* x, double P, double PI)
 {
+    double acc[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) x[i] = 0.0;
+    for (int i = 0; i < NB; ++i) acc[i] = (i == j) ? 1.0 : 0.0;
     if (uplo == 1) {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            double acc = 0.0;
-#pragma unroll
-            for (int s = 0; s < i; ++s) acc = fma(M[i][s], x[s], acc);
-            double r = ((i == j) ? 1.0 : 0.0) - mod_red(acc, P, PI);
-            r = (r < 0.0) ? r + P : r;
+            double r = mod_red(acc[i], P, PI);
             x[i] = mod_mul(r, dinv[i], P, PI);
+            const double nx = (x[i] == 0.0) ? 0.0 : P - x[i];
+#pragma unroll
+            for (int t = i + 1; t < NB; ++t) acc[t] = fma(M[t][i], nx, acc[t]);
         }
     } else {
 #pragma unroll
         for (int i = NB - 1; i >= 0; --i) {
-            double acc = 0.0;
-#pragma unroll
-            for (int s = i + 1; s < NB; ++s) acc = fma(M[i][s], x[s], acc);
-            double r = ((i == j) ? 1.0 : 0.0) - mod_red(acc, P, PI);
-            r = (r < 0.0) ? r + P : r;
+            double r = mod_red(acc[i], P, PI);
             x[i] = mod_mul(r, dinv[i], P, PI);
+            const double nx = (x[i] == 0.0) ? 0.0 : P - x[i];
+#pragma unroll
+            for (int t = 0; t < i; ++t) acc[t] = fma(M[t][i], nx, acc[t]);
         }
     }
 }
@@ -138,56 +139,56 @@ __global__ __launch_bounds__(NB) void diag_prep_kernel(T* __restrict__ A, int64_
 }
 
 // B <- B W (side 1, B is rows x nb) or W B (side 0, B is nb x cols), W dense
-// 64 x 64 (identity beyond nb).  Each workgroup owns 64 rows (right) or 64
-// columns (left) of B.
+// 64 x 64 (identity beyond nb).  Each workgroup owns 16 rows (right) or 16
+// columns (left) of B; each thread computes 4 of their 16 x 64 outputs.
+constexpr int AV = 16;  // vectors per workgroup
+
 template <typename T, bool BIG>
 __global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const double* __restrict__ W,
                                                         T* __restrict__ B, int64_t ldb, int other,
                                                         ModP mp)
 {
     __shared__ double Ws[NB][NB + 1];
-    __shared__ double Bs[NB][NB + 1];
+    __shared__ double Bs[AV][NB + 1];
     const int tid = threadIdx.x;
     const double P = mp.p, PI = mp.pinv;
-    const int v0 = blockIdx.x * NB;
-    const int nv = min(NB, other - v0);
-    for (int idx = tid; idx < NB * NB; idx += 256) Ws[idx >> 6][idx & 63] = W[idx];
-    // Bs[v][i]: element i of vector v (row of B on the right, column on the left)
+    const int v0 = blockIdx.x * AV;
+    const int nv = min(AV, other - v0);
     for (int idx = tid; idx < NB * NB; idx += 256) {
-        int a = idx >> 6, c = idx & 63;
-        double val = 0.0;
-        if (side == 1) {  // a = vector (row), c = element
-            if (a < nv && c < nb) val = ld_res(B + (int64_t)(v0 + a) * ldb + c);
-            Bs[a][c] = val;
-        } else {          // a = element (row of B), c = vector (column)
-            if (a < nb && c < nv) val = ld_res(B + (int64_t)a * ldb + v0 + c);
-            Bs[c][a] = val;
+        const int i = idx >> 6, e = idx & 63;
+        // right: Ws[s][e] = W[s][e]; left: Ws[e][s] = W[e][s] read as Ws[s][e] = W[e][s]
+        Ws[i][e] = (side == 1) ? W[idx] : W[e * NB + i];
+    }
+    // Bs[v][s]: element s of vector v (row of B on the right, column on the left)
+    if (side == 1) {
+        for (int idx = tid; idx < AV * NB; idx += 256) {
+            const int v = idx >> 6, c = idx & 63;
+            Bs[v][c] = (v < nv && c < nb) ? ld_res(B + (int64_t)(v0 + v) * ldb + c) : 0.0;
+        }
+    } else {
+        for (int idx = tid; idx < AV * NB; idx += 256) {
+            const int a = idx >> 4, v = idx & 15;
+            Bs[v][a] = (a < nb && v < nv) ? ld_res(B + (int64_t)a * ldb + v0 + v) : 0.0;
         }
     }
     __syncthreads();
-    // thread: vector v = tid & 63, outputs e = (tid >> 6) * 16 .. +16
-    const int v = tid & 63, e0 = (tid >> 6) * 16;
-    double acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-#pragma unroll 4
+    // thread: vector v = tid >> 4, outputs e = (tid & 15) + 16 q
+    const int v = tid >> 4, e0 = tid & 15;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
     for (int s = 0; s < NB; ++s) {
         const double bv = Bs[v][s];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            // right: out[v][e] = sum_s B[v][s] W[s][e]; left: out[e][v] = sum_s W[e][s] B[s][v]
-            const double w = (side == 1) ? Ws[s][e0 + q] : Ws[e0 + q][s];
-            acc[q] = fma(bv, w, acc[q]);
-        }
+        for (int q = 0; q < 4; ++q) acc[q] = fma(bv, Ws[s][e0 + 16 * q], acc[q]);
         if (BIG) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q] = mod_red(acc[q], P, PI);
+            for (int q = 0; q < 4; ++q) acc[q] = mod_red(acc[q], P, PI);
         }
     }
     if (v < nv) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int e = e0 + q;
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + 16 * q;
             if (e < nb) {
                 T* dst = (side == 1) ? B + (int64_t)(v0 + v) * ldb + e : B + (int64_t)e * ldb + v0 + v;
                 st_res(dst, mod_red(acc[q], P, PI));
@@ -283,7 +284,7 @@ void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, in
                       ModP mp)
 {
     if (nb <= 0 || other <= 0) return;
-    dim3 grid((other + NB - 1) / NB);
+    dim3 grid((other + AV - 1) / AV);
     if (big_prime(mp))
         hipLaunchKernelGGL((tri_apply_kernel<T, true>), grid, dim3(256), 0, s, side, nb, W, B, ldb,
                            other, mp);
