@@ -33,17 +33,23 @@ namespace cup {
 
 namespace {
 
-constexpr int WT = 256;  // threads of the window kernel
+constexpr int WT = 512;             // threads of the window kernel (8 waves)
+constexpr int NWV = WT / 64;        // waves
+constexpr int KPW = kLeafRows / NWV; // tile rows per wave
 
-// Residue in (-p, p): x - rint(x / p) p, exact for |x| < 2^53.  Zero iff
-// x = 0 mod p.
+// Residue in (-p, p): x - round(x / p) p, exact for |x| < 2^53.  Zero iff
+// x = 0 mod p.  The rounding adds and subtracts 1.5 * 2^52, which rounds any
+// value of magnitude below 2^51 to the nearest integer with two full-rate
+// additions.
 __device__ __forceinline__ double red_c(double x, double p, double pinv)
 {
-    return fma(-rint(x * pinv), p, x);
+    const double magic = 6755399441055744.0;  // 1.5 * 2^52
+    const double q = fma(x, pinv, magic) - magic;
+    return fma(-q, p, x);
 }
 
-// Register-resident tile: thread (wave w, lane l) holds rows w + 4k
-// (k = 0..15) of columns l and l + 64.  The pivot row and the multiplier
+// Register-resident tile: thread (wave w, lane l) holds rows w + 8k
+// (k = 0..7) of columns l and l + 64.  The pivot row and the multiplier
 // column of each step are exchanged through LDS buffers alternating with
 // the step's parity, so one barrier per pivot suffices.
 template <typename T>
@@ -59,52 +65,59 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     __shared__ double s_isig[kLeafRows + 1];
     __shared__ double s_ipiv[kLeafRows];
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
     const int R = b - i0;
     const double P = mp.p, PI = mp.pinv;
 
-    double v[2][16];
+    double v[2][KPW];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int r = w + 4 * k, c = lane + 64 * q;
+        for (int k = 0; k < KPW; ++k) {
+            const int r = w + NWV * k, c = lane + 64 * q;
             v[q][k] = (r < R && c < wc) ? ld_res(A + (int64_t)(i0 + r) * lda + t0 + c) : 0.0;
         }
 
+    // Publish row a (its owner wave: rowbuf and the leftmost nonzero at
+    // positions >= a) and column a (its owner lane in every wave: colbuf)
+    // into the buffers of parity a & 1.
+    auto publish = [&](int a) {
+        const int par = a & 1, qa = a >> 6, la = a & 63;
+#pragma unroll
+        for (int k = 0; k < KPW; ++k) {
+            if (w + NWV * k == a) {
+                const double x0 = v[0][k], x1 = v[1][k];
+                const unsigned long long m0 = __ballot(lane >= a && lane < wc && x0 != 0.0);
+                const unsigned long long m1 =
+                    __ballot(lane + 64 >= a && lane + 64 < wc && x1 != 0.0);
+                rowbuf[par][lane] = x0;
+                rowbuf[par][lane + 64] = x1;
+                if (lane == 0)
+                    s_j[par] = m0 ? __ffsll((long long)m0) - 1
+                                  : (m1 ? 64 + __ffsll((long long)m1) - 1 : -1);
+            }
+        }
+        if (lane == la) {
+#pragma unroll
+            for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = qa ? v[1][k] : v[0][k];
+        }
+    };
+
     int d = 0, stop = STOP_ROWS;
+    if (R > 0 && wc > 0) publish(0);
+    __syncthreads();
     for (int a = 0;; ++a) {
         if (a >= R) { stop = STOP_ROWS; break; }
         if (a >= wc) { stop = STOP_WINDOW; break; }
         const int par = a & 1, qa = a >> 6, la = a & 63;
-        if (w == (a & 3)) {
-            // this wave owns row a: publish it and find its leftmost nonzero
-            const int ka = a >> 2;
-            double x0 = 0.0, x1 = 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                x0 = (k == ka) ? v[0][k] : x0;
-                x1 = (k == ka) ? v[1][k] : x1;
-            }
-            const unsigned long long m0 = __ballot(lane >= a && lane < wc && x0 != 0.0);
-            const unsigned long long m1 = __ballot(lane + 64 >= a && lane + 64 < wc && x1 != 0.0);
-            rowbuf[par][lane] = x0;
-            rowbuf[par][lane + 64] = x1;
-            if (lane == 0)
-                s_j[par] = m0 ? __ffsll((long long)m0) - 1 : (m1 ? 64 + __ffsll((long long)m1) - 1 : -1);
-        }
-        if (lane == la) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) colbuf[par][w + 4 * k] = qa ? v[1][k] : v[0][k];
-        }
-        __syncthreads();
         const int j = s_j[par];
         if (j < 0) { stop = STOP_ZERO_ROW; break; }
         if (j != a) {
             // swap columns a and j: both live in the same lanes of every wave
             const int qj = j >> 6, lj = j & 63;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
+            for (int k = 0; k < KPW; ++k) {
                 const double ca = qa ? v[1][k] : v[0][k];
                 const double cj = qj ? v[1][k] : v[0][k];
                 const double from_j = __shfl(cj, lj, 64);
@@ -112,11 +125,11 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 if (lane == la) { if (qa) v[1][k] = from_j; else v[0][k] = from_j; }
                 if (lane == lj) { if (qj) v[1][k] = from_a; else v[0][k] = from_a; }
             }
+            __syncthreads();  // everyone has read s_j and the old column a
             if (lane == la) {
 #pragma unroll
-                for (int k = 0; k < 16; ++k) colbuf[par][w + 4 * k] = qa ? v[1][k] : v[0][k];
+                for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = qa ? v[1][k] : v[0][k];
             }
-            __syncthreads();
             if (tid == 0) {
                 double x = rowbuf[par][a];
                 rowbuf[par][a] = rowbuf[par][j];
@@ -129,18 +142,25 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             s_swap[a] = j;
             s_piv[a] = mod_red(piv, P, PI);
         }
-        // fraction-free update of rows > a, columns > a
+        // fraction-free update of rows > a, columns > a: multipliers loaded
+        // up front, rows skipped per wave, columns masked per lane
         const double u0 = rowbuf[par][lane], u1 = rowbuf[par][lane + 64];
+        const bool c0 = lane > a, c1 = lane + 64 > a;
+        double mlt[KPW];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int r = w + 4 * k;
-            if (r > a && r < R) {
-                const double mlt = colbuf[par][r];
-                if (lane > a) v[0][k] = red_c(fma(piv, v[0][k], -mlt * u0), P, PI);
-                if (lane + 64 > a) v[1][k] = red_c(fma(piv, v[1][k], -mlt * u1), P, PI);
+        for (int k = 0; k < KPW; ++k) mlt[k] = colbuf[par][w + NWV * k];
+#pragma unroll
+        for (int k = 0; k < KPW; ++k) {
+            if (w + NWV * k > a) {
+                const double n0 = red_c(fma(piv, v[0][k], -mlt[k] * u0), P, PI);
+                const double n1 = red_c(fma(piv, v[1][k], -mlt[k] * u1), P, PI);
+                v[0][k] = c0 ? n0 : v[0][k];
+                v[1][k] = c1 ? n1 : v[1][k];
             }
         }
         d = a + 1;
+        if (a + 1 < R && a + 1 < wc) publish(a + 1);
+        __syncthreads();
     }
     __syncthreads();
 
@@ -166,8 +186,8 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int r = w + 4 * k, c = lane + 64 * q;
+        for (int k = 0; k < KPW; ++k) {
+            const int r = w + NWV * k, c = lane + 64 * q;
             if (r < R && c < wc) {
                 const int lim = (r + 1 < d) ? r + 1 : d;
                 const double f = (c < lim) ? s_isig[c] : ((r < d) ? s_ipiv[r] : s_isig[d]);
