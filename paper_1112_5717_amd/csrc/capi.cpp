@@ -95,11 +95,11 @@ int resolve_form(int forced, int64_t p, bool int8_storage)
     case FORM_FP64:
         return FORM_FP64;
     case FORM_I8:
-        return p < 128 ? FORM_FP64 : -5;
+        return p < 128 ? FORM_I8 : -5;
     case FORM_I8LIMB:
-        return p <= 65536 ? FORM_FP64 : -5;
+        return p <= 65536 ? FORM_I8LIMB : -5;
     default:
-        return FORM_FP64;
+        return p < 128 ? FORM_I8 : (p <= 65536 ? FORM_I8LIMB : FORM_FP64);
     }
 }
 
@@ -146,6 +146,7 @@ Ctx make_ctx(Global& g, int64_t p, int form)
     c.d_small = g.d_small;
     c.h_small = g.h_small;
     c.log = env_flag("CUP_LOG") ? 1 : 0;
+    if (const char* v = std::getenv("CUP_I8_MIN_WORK")) c.i8_min_work = std::atof(v);
     c.prof = &g.prof;
     c.ws = &g.ws;
     ctx_set_prime(c, p);
@@ -413,7 +414,7 @@ int cup_profile_read(double* stats)
     if (!stats) return -1;
     Global& g = G();
     std::lock_guard<std::mutex> lk(g.mu);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kProfKinds; ++k) {
         stats[4 * k + 0] = g.prof.launches[k];
         stats[4 * k + 1] = g.prof.ms[k];
         stats[4 * k + 2] = g.prof.flops[k];
@@ -437,6 +438,7 @@ int cup_finalize(void)
     if (g.h_small) (void)hipHostFree(g.h_small);
     if (g.d_list) (void)hipFree(g.d_list);
     if (g.ws.tri) (void)hipFree(g.ws.tri);
+    if (g.ws.pk) (void)hipFree(g.ws.pk);
     g.ws = Workspace{};
     g.d_small = nullptr;
     g.h_small = nullptr;

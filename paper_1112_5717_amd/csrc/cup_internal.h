@@ -61,6 +61,14 @@ void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t l
                        const T* B, int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha,
                        int kred_steps);
 
+// C(MxN) <- C + alpha A(MxK) B(KxN) mod p on INT8 MFMA: limb = 0 for p < 2^7
+// (one signed byte per residue), 1 for p <= 2^16 (two signed limbs).  `ws`
+// holds at least ffgemm_i8_workspace(M, N, K, limb) bytes.
+size_t ffgemm_i8_workspace(int M, int N, int K, int limb);
+template <typename T>
+void launch_ffgemm_i8(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, const T* B,
+                      int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, int limb, int8_t* ws);
+
 // Window elimination of a leaf (see k_panel.hip).  Writes d, stop and the
 // chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col).
 template <typename T>

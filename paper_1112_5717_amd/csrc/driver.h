@@ -24,8 +24,10 @@ enum { SOLVE = 0, MULT = 1 };
 // Kernel timing with HIP events (enabled by cup_profile): every ffgemm and
 // leaf-window launch is bracketed by two events on the launch stream; the
 // elapsed times are summed after the call has synchronised.
+constexpr int kProfKinds = 3;  // 0 ffgemm FP64, 1 window, 2 ffgemm INT8 forms
+
 struct ProfRec {
-    int kind;            // 0 ffgemm, 1 window
+    int kind;            // 0 ffgemm FP64, 1 window, 2 ffgemm INT8
     double flops;        // algorithmic operations of the launch
     double bytes;        // algorithmic bytes of the launch
     hipEvent_t a, b;
@@ -36,12 +38,12 @@ struct Profiler {
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<ProfRec> recs;
-    double launches[2] = {0, 0}, ms[2] = {0, 0}, flops[2] = {0, 0}, bytes[2] = {0, 0};
+    double launches[kProfKinds] = {}, ms[kProfKinds] = {}, flops[kProfKinds] = {},
+           bytes[kProfKinds] = {};
 
     void reset()
     {
-        launches[0] = launches[1] = ms[0] = ms[1] = 0;
-        flops[0] = flops[1] = bytes[0] = bytes[1] = 0;
+        for (int k = 0; k < kProfKinds; ++k) launches[k] = ms[k] = flops[k] = bytes[k] = 0;
     }
     hipEvent_t next()
     {
@@ -80,6 +82,8 @@ struct Profiler {
 struct Workspace {
     double* tri = nullptr;
     size_t tri_cap = 0;  // doubles
+    int8_t* pk = nullptr;  // packed ffgemm operands of the INT8 forms
+    size_t pk_cap = 0;     // bytes
     size_t bytes = 0;
 };
 
@@ -95,6 +99,7 @@ struct Ctx {
     int* d_small = nullptr; // device results of the leaf kernels
     int* h_small = nullptr; // pinned host mirror
     int log = 0;
+    double i8_min_work = 16777216.0;  // M N K below which products stay on FP64
 };
 
 constexpr int kSmallInts = 4096;
@@ -147,6 +152,27 @@ inline double* tri_workspace(Ctx& c, int n)
     return w.tri;
 }
 
+inline int8_t* pack_workspace(Ctx& c, size_t need)
+{
+    Workspace& w = *c.ws;
+    if (need > w.pk_cap) {
+        if (w.pk) {
+            CUP_HIP(hipStreamSynchronize(c.s));
+            CUP_HIP(hipFree(w.pk));
+            w.bytes -= w.pk_cap;
+            w.pk = nullptr;
+            w.pk_cap = 0;
+        }
+        if (hipMalloc((void**)&w.pk, need) != hipSuccess) {
+            w.pk = nullptr;
+            throw CupError{-2000};
+        }
+        w.pk_cap = need;
+        w.bytes += need;
+    }
+    return w.pk;
+}
+
 inline int split_at(int n, int unit)
 {
     int k = ((n / 2 + unit / 2) / unit) * unit;
@@ -161,11 +187,21 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
           int64_t ldc, int alpha)
 {
     if (M <= 0 || N <= 0 || K <= 0) return;
+    // The INT8 forms pay two packing launches per product: small products
+    // stay on the FP64 carrier (the results are identical either way).
+    const bool i8 = (c.form == FORM_I8 || c.form == FORM_I8LIMB) && M >= 128 && N >= 128 &&
+                    K >= 64 && (double)M * N * K >= c.i8_min_work;
     const bool prof = c.prof && c.prof->on;
     if (prof)
-        c.prof->begin(c.s, 0, 2.0 * M * N * K,
+        c.prof->begin(c.s, i8 ? 2 : 0, 2.0 * M * N * K,
                       ((double)M * K + (double)K * N + 2.0 * M * N) * sizeof(T));
-    launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps);
+    if (i8) {
+        const int limb = (c.form == FORM_I8LIMB) ? 1 : 0;
+        int8_t* ws = pack_workspace(c, ffgemm_i8_workspace(M, N, K, limb));
+        launch_ffgemm_i8<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, limb, ws);
+    } else {
+        launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps);
+    }
     if (prof) c.prof->end(c.s);
 }
 

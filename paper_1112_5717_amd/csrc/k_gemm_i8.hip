@@ -1,0 +1,272 @@
+// ffgemm, INT8 forms: C <- C + alpha A B mod p on INT8 MFMA with exact INT32
+// accumulation.
+//
+//  * I8 (p < 2^7): residues fit a signed byte; a sum of K products stays
+//    below K (p-1)^2 < 2^31 for K <= 131072 per launch.
+//  * I8LIMB (p <= 2^16): each residue x is taken in the window
+//    [-(p - 32640), 32639] (x or x - p), then split into two signed bytes
+//    x = 256 h + l with h = floor((x + 128) / 256) and l in [-128, 127].
+//    A product sum is recombined exactly as
+//        S = 2^16 S_hh + 2^8 (S_hl + S_lh) + S_ll,
+//    with the two cross products sharing one INT32 accumulator; every
+//    accumulator stays below 2^31 for K <= 65472 per launch and S below 2^53.
+//
+// Operands are first packed into a workspace (the GEMM-internal memory that
+// the paper's in-place definition allows, Section 3.1, Definition 1): A as
+// [M][Kp] bytes and B transposed as [N][Kp] bytes per limb, zero-padded to
+// tile multiples, so every MFMA operand is 16 contiguous bytes of k.  The
+// product kernel tiles 128 x 128 outputs per 256-thread workgroup (4 wave64s
+// of 64 x 64, as 4 x 4 blocks of v_mfma_i32_16x16x64_i8), K in steps of 64
+// staged through LDS with double buffering; the epilogue reduces mod p in
+// FP64 and adds alpha S to C.
+#include "modarith.h"
+
+namespace cup {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int IBM = 128, IBN = 128, IBK = 64;
+constexpr int LROW = IBK + 16;  // LDS row stride in bytes (conflict-free 16-byte reads)
+
+__device__ __forceinline__ int res_int(const int64_t* a) { return *reinterpret_cast<const int*>(a); }
+__device__ __forceinline__ int res_int(const int8_t* a) { return (int)*a; }
+
+// Signed limbs of residue x of prime p (x in [0, p), p <= 65536).
+__device__ __forceinline__ void limbs(int x, int p, int& hi, int& lo)
+{
+    const int xc = (x <= 32639) ? x : x - p;
+    hi = (xc + 128) >> 8;  // arithmetic shift: floor
+    lo = xc - 256 * hi;
+}
+
+// D[r][k] (r < Rp, k < Kp) from S[r][k] (r < R, k < K), zero padded.
+template <typename T, int LIMB>
+__global__ void pack_rows_kernel(const T* __restrict__ S, int64_t lds, int R, int K,
+                                 int8_t* __restrict__ D0, int8_t* __restrict__ D1, int Rp, int Kp,
+                                 int p)
+{
+    for (int r = blockIdx.y; r < Rp; r += gridDim.y)
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < Kp; k += gridDim.x * blockDim.x) {
+        int x = (r < R && k < K) ? res_int(S + (int64_t)r * lds + k) : 0;
+        if (LIMB) {
+            int hi, lo;
+            limbs(x, p, hi, lo);
+            D0[(int64_t)r * Kp + k] = (int8_t)hi;
+            D1[(int64_t)r * Kp + k] = (int8_t)lo;
+        } else {
+            D0[(int64_t)r * Kp + k] = (int8_t)x;
+        }
+    }
+}
+
+// D[n][k] (n < Np, k < Kp) from S[k][n] (k < K, n < N): 64 x 64 tiles through LDS.
+template <typename T, int LIMB>
+__global__ __launch_bounds__(256) void pack_cols_kernel(const T* __restrict__ S, int64_t lds, int K,
+                                                        int N, int8_t* __restrict__ D0,
+                                                        int8_t* __restrict__ D1, int Kp, int p)
+{
+    __shared__ int tile[64][65];
+    const int k0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int kk = ty; kk < 64; kk += 4) {
+        const int k = k0 + kk, n = n0 + tx;
+        tile[kk][tx] = (k < K && n < N) ? res_int(S + (int64_t)k * lds + n) : 0;
+    }
+    __syncthreads();
+    for (int nn = ty; nn < 64; nn += 4) {
+        const int n = n0 + nn, k = k0 + tx;
+        const int x = tile[tx][nn];
+        if (LIMB) {
+            int hi, lo;
+            limbs(x, p, hi, lo);
+            D0[(int64_t)n * Kp + k] = (int8_t)hi;
+            D1[(int64_t)n * Kp + k] = (int8_t)lo;
+        } else {
+            D0[(int64_t)n * Kp + k] = (int8_t)x;
+        }
+    }
+}
+
+template <typename T, int LIMB>
+__global__ __launch_bounds__(256) void ffgemm_i8_kernel(int M, int N, int Kp,
+                                                        const int8_t* __restrict__ Ah,
+                                                        const int8_t* __restrict__ Al,
+                                                        const int8_t* __restrict__ Bh,
+                                                        const int8_t* __restrict__ Bl,
+                                                        T* __restrict__ C, int64_t ldc, ModP mp,
+                                                        int alpha)
+{
+    constexpr int NL = LIMB ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) int8_t As[2][NL][IBM * LROW];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][NL][IBN * LROW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int m0 = blockIdx.y * IBM, n0 = blockIdx.x * IBN;
+
+    // global -> LDS: each thread moves 2 x 16 bytes per limb per operand
+    const int lr = tid >> 2, lc = (tid & 3) * 16;
+    const int8_t* gA[NL];
+    const int8_t* gB[NL];
+    gA[0] = Ah + (int64_t)(m0 + lr) * Kp + lc;
+    gB[0] = Bh + (int64_t)(n0 + lr) * Kp + lc;
+    if (LIMB) {
+        gA[NL - 1] = Al + (int64_t)(m0 + lr) * Kp + lc;
+        gB[NL - 1] = Bl + (int64_t)(n0 + lr) * Kp + lc;
+    }
+    const int64_t half_rows = (int64_t)64 * Kp;
+    v4i ra[NL][2], rb[NL][2];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NL; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                ra[q][h] = *reinterpret_cast<const v4i*>(gA[q] + h * half_rows + k0);
+                rb[q][h] = *reinterpret_cast<const v4i*>(gB[q] + h * half_rows + k0);
+            }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NL; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                *reinterpret_cast<v4i*>(&As[buf][q][(lr + 64 * h) * LROW + lc]) = ra[q][h];
+                *reinterpret_cast<v4i*>(&Bs[buf][q][(lr + 64 * h) * LROW + lc]) = rb[q][h];
+            }
+    };
+
+    constexpr int NACC = LIMB ? 3 : 1;
+    v4i acc[NACC][4][4];
+#pragma unroll
+    for (int s = 0; s < NACC; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+
+    const int nk = Kp / IBK;
+    load(0);
+    store(0);
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 16;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * IBK);
+        v4i a[NL][4], b[NL][4];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                a[q][i] = *reinterpret_cast<const v4i*>(&As[buf][q][(wm + i * 16 + fr) * LROW + fk]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[q][j] = *reinterpret_cast<const v4i*>(&Bs[buf][q][(wn + j * 16 + fr) * LROW + fk]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (LIMB) {
+                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][i], b[0][j], acc[0][i][j], 0, 0, 0);
+                    acc[1][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][i], b[NL - 1][j], acc[1][i][j], 0, 0, 0);
+                    acc[1][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[NL - 1][i], b[0][j], acc[1][i][j], 0, 0, 0);
+                    acc[NACC - 1][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[NL - 1][i], b[NL - 1][j], acc[NACC - 1][i][j], 0, 0, 0);
+                } else {
+                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][i], b[0][j], acc[0][i][j], 0, 0, 0);
+                }
+            }
+        if (kt + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // Epilogue: lane l holds rows 4 (l/16) + e, column l % 16 of each block.
+    const double P = mp.p, PI = mp.pinv;
+    const int gm0 = m0 + wm + 4 * (lane >> 4), gn0 = n0 + wn + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gn = gn0 + j * 16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = gm0 + i * 16 + e;
+                if (gm < M && gn < N) {
+                    double s;
+                    if (LIMB)
+                        s = 65536.0 * (double)acc[0][i][j][e] + 256.0 * (double)acc[1][i][j][e] +
+                            (double)acc[NACC - 1][i][j][e];
+                    else
+                        s = (double)acc[0][i][j][e];
+                    s = mod_red(s, P, PI);
+                    T* cp = C + (int64_t)gm * ldc + gn;
+                    const double c = ld_res(cp);
+                    double r = (alpha < 0) ? c - s : c + s;
+                    r = (r < 0.0) ? r + P : r;
+                    r = (r >= P) ? r - P : r;
+                    st_res(cp, r);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+}
+
+}  // namespace
+
+size_t ffgemm_i8_workspace(int M, int N, int K, int limb)
+{
+    const int64_t Mp = (M + IBM - 1) / IBM * IBM, Np = (N + IBN - 1) / IBN * IBN;
+    const int64_t kc = std::min<int64_t>(K, limb ? 65472 : 131072);
+    const int64_t Kp = (kc + IBK - 1) / IBK * IBK;
+    return (size_t)((Mp + Np) * Kp * (limb ? 2 : 1));
+}
+
+template <typename T>
+void launch_ffgemm_i8(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, const T* B,
+                      int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, int limb, int8_t* ws)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return;
+    const int64_t Mp = (M + IBM - 1) / IBM * IBM, Np = (N + IBN - 1) / IBN * IBN;
+    const int kmax = limb ? 65472 : 131072;  // INT32 accumulators stay exact
+    const int p = (int)mp.p;
+    for (int k0 = 0; k0 < K; k0 += kmax) {
+        const int kc = std::min(kmax, K - k0);
+        const int Kp = (kc + IBK - 1) / IBK * IBK;
+        int8_t* Ah = ws;
+        int8_t* Al = Ah + Mp * Kp;
+        int8_t* Bh = ws + (limb ? 2 : 1) * Mp * Kp;
+        int8_t* Bl = Bh + Np * Kp;
+        const dim3 gr((Kp + 255) / 256, (unsigned)std::min<int64_t>(Mp, 65535));
+        const dim3 gc((Kp + 63) / 64, (unsigned)(Np / 64));
+        if (limb) {
+            hipLaunchKernelGGL((pack_rows_kernel<T, 1>), gr, dim3(256), 0, s, A + k0, lda, M, kc, Ah,
+                               Al, (int)Mp, Kp, p);
+            hipLaunchKernelGGL((pack_cols_kernel<T, 1>), gc, dim3(256), 0, s, B + (int64_t)k0 * ldb,
+                               ldb, kc, N, Bh, Bl, Kp, p);
+        } else {
+            hipLaunchKernelGGL((pack_rows_kernel<T, 0>), gr, dim3(256), 0, s, A + k0, lda, M, kc, Ah,
+                               Ah, (int)Mp, Kp, p);
+            hipLaunchKernelGGL((pack_cols_kernel<T, 0>), gc, dim3(256), 0, s, B + (int64_t)k0 * ldb,
+                               ldb, kc, N, Bh, Bh, Kp, p);
+        }
+        CUP_HIP(hipGetLastError());
+        const dim3 grid((unsigned)(Np / IBN), (unsigned)(Mp / IBM));
+        if (limb)
+            hipLaunchKernelGGL((ffgemm_i8_kernel<T, 1>), grid, dim3(256), 0, s, M, N, Kp, Ah, Al, Bh, Bl,
+                               C, ldc, mp, alpha);
+        else
+            hipLaunchKernelGGL((ffgemm_i8_kernel<T, 0>), grid, dim3(256), 0, s, M, N, Kp, Ah, Ah, Bh, Bh,
+                               C, ldc, mp, alpha);
+        CUP_HIP(hipGetLastError());
+    }
+}
+
+template void launch_ffgemm_i8<int64_t>(hipStream_t, int, int, int, const int64_t*, int64_t,
+                                        const int64_t*, int64_t, int64_t*, int64_t, ModP, int, int,
+                                        int8_t*);
+template void launch_ffgemm_i8<int8_t>(hipStream_t, int, int, int, const int8_t*, int64_t,
+                                       const int8_t*, int64_t, int8_t*, int64_t, ModP, int, int,
+                                       int8_t*);
+
+}  // namespace cup

@@ -255,3 +255,88 @@ def test_batched_small(cup_lib):
         assert info[i] == 0 and rank[i] == ref[1]
         assert np.array_equal(host(Ps[i]), ref[2]) and np.array_equal(host(Qs[i]), ref[3])
         assert np.array_equal(host(mats[i]), ref[0])
+
+
+# --------------------------------------------------------------- INT8 forms
+
+def _i8_small_products(monkeypatch):
+    """Send every product with M, N >= 128 and K >= 64 to the INT8 kernels."""
+    monkeypatch.setenv("CUP_I8_MIN_WORK", "0")
+
+
+@pytest.mark.parametrize("form,p,dtype", [("i8", 127, "int8"), ("i8", 2, "int8"), ("i8", 3, "int64"),
+                                          ("i8limb", 65521, "int64"), ("i8limb", 257, "int64"),
+                                          ("i8limb", 2, "int64"), ("i8limb", 32771, "int64")])
+@pytest.mark.parametrize("shape", [(128, 128, 64), (300, 200, 513), (640, 384, 1000)])
+def test_ffgemm_int8_forms(cup_lib, monkeypatch, form, p, dtype, shape):
+    _i8_small_products(monkeypatch)
+    M, N, K = shape
+    rng = np.random.default_rng(M + N + K + p)
+    A = rng.integers(0, p, size=(M, K), dtype=np.int64)
+    B = rng.integers(0, p, size=(K, N), dtype=np.int64)
+    C = rng.integers(0, p, size=(M, N), dtype=np.int64)
+    tdt = torch.int8 if dtype == "int8" else torch.int64
+    cup_lib.cup_set_form(form)
+    try:
+        for alpha in (-1, 1):
+            dC = dev(C, tdt)
+            cup_lib.cup_ffgemm(dC, dev(A, tdt), dev(B, tdt), p, alpha)
+            assert np.array_equal(host(dC), exact_gemm(C, A, B, p, alpha)), (form, p, alpha)
+    finally:
+        cup_lib.cup_set_form("auto")
+
+
+@pytest.mark.parametrize("p", [65521, 40009])
+def test_ffgemm_limb_window_extremes(cup_lib, monkeypatch, p):
+    """Residues at both ends of the signed limb window and at p - 1."""
+    _i8_small_products(monkeypatch)
+    vals = np.array([0, 1, 127, 128, 255, 256, 32639, 32640, p - 129, p - 128, p - 1], dtype=np.int64) % p
+    M, N, K = 256, 192, 4160
+    rng = np.random.default_rng(p)
+    A = vals[rng.integers(0, len(vals), size=(M, K))]
+    B = vals[rng.integers(0, len(vals), size=(K, N))]
+    A[:8, :] = p - 1
+    B[:, :8] = p - 1
+    A[8:16, :] = 32640 % p
+    B[:, 8:16] = 32640 % p
+    C = np.full((M, N), p - 1, dtype=np.int64)
+    cup_lib.cup_set_form("i8limb")
+    try:
+        dC = dev(C)
+        cup_lib.cup_ffgemm(dC, dev(A), dev(B), p, -1)
+        assert np.array_equal(host(dC), exact_gemm(C, A, B, p, -1))
+    finally:
+        cup_lib.cup_set_form("auto")
+
+
+@pytest.mark.parametrize("form,p,i8", [("i8limb", 65521, False), ("i8", 127, True), ("i8", 127, False),
+                                       ("fp64", 65521, False)])
+def test_cup_forms_vs_oracle(cup_lib, monkeypatch, form, p, i8):
+    """Every form of the product gives the same CUP, bit for bit."""
+    _i8_small_products(monkeypatch)
+    cup_lib.cup_set_form(form)
+    try:
+        for m, n, rank in [(700, 520, None), (600, 600, 350), (1100, 260, None)]:
+            A = structured(m, n, p, m + n, rank=rank)
+            assert_same_cup(run_cup(cup_lib, A, p, i8=i8), oracle.cup(A, p), f"{form} {m}x{n}")
+    finally:
+        cup_lib.cup_set_form("auto")
+
+
+def test_rref_inverse_i8limb(cup_lib, monkeypatch):
+    _i8_small_products(monkeypatch)
+    p = 65521
+    cup_lib.cup_set_form("i8limb")
+    try:
+        A = structured(500, 420, p, 17, rank=300)
+        d = dev(A)
+        r, P, Q = cup_lib.cup_rref_inplace(d, p)
+        O, rr, rP, rQ = oracle.rref_packed(A, p)
+        assert r == rr and np.array_equal(host(d), O)
+        B = inputs.uniform((384, 384), p, seed=77)
+        X = oracle.inverse(B, p)
+        d = dev(B)
+        ok, r = cup_lib.cup_inverse_inplace(d, p)
+        assert ok and np.array_equal(host(d), X)
+    finally:
+        cup_lib.cup_set_form("auto")
