@@ -96,13 +96,37 @@ def cpu_baseline(A_host, p, rows):
                       f"same GF({p}) matrix; {F:.3e} field ops in {dt:.2f} s"}
 
 
+def roofline_of(stats, form, steps):
+    """Dominant-kernel roofline from the library's HIP-event timing."""
+    key = "ffgemm" if form == "fp64" else "ffgemm_i8"
+    st = stats[key]
+    mult = 4.0 if form == "i8limb" else 1.0  # INT8 MFMA operations per field operation
+    peak, unit = PEAK[form]
+    achieved = (mult * st["flops"] / (st["ms"] * 1e-3) / 1e12) if st["ms"] > 0 else 0.0
+    return {
+        "bound": "mfma",
+        "kernel": "ffgemm_f64_kernel" if form == "fp64" else "ffgemm_i8_kernel",
+        "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+        "frac": round(achieved / peak, 4), "traffic": None,
+        "launches_per_step": st["launches"] / steps,
+        "avg_launch_ms": st["ms"] / max(1.0, st["launches"]),
+        "ops_per_launch": mult * st["flops"] / max(1.0, st["launches"]),
+        "kernel_ms_per_step": st["ms"] / steps,
+    }
+
+
+def breakdown(stats, steps):
+    return {k: {"launches_per_step": v["launches"] / steps, "ms_per_step": v["ms"] / steps}
+            for k, v in stats.items() if v["launches"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--form", default="auto", choices=["auto", "fp64", "i8limb"])
+    ap.add_argument("--form", default="i8limb", choices=["fp64", "i8limb"])
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -115,7 +139,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1112_5717_amd import cup, inputs
@@ -126,51 +149,45 @@ def main():
     print(f"[bench] generating {n}x{n} uniform residues mod {P16} (seed 2)", file=sys.stderr, flush=True)
     A_host = inputs.uniform((n, n), P16, seed=2)
     A0 = torch.from_numpy(A_host).cuda()
+    gkey = f"cup_{n}_uniform_p{P16}_seed2"
 
-    main_form = args.form
-    print(f"[bench] timing form={main_form} steps={args.steps} warmup={args.warmup}", file=sys.stderr,
+    def parity_of(res, key):
+        if key not in gold:
+            return "no oracle digest at this size"
+        return "oracle digest match" if gold[key]["digest"] == res["digest"] else "ORACLE DIGEST MISMATCH"
+
+    form = args.form
+    print(f"[bench] timing form={form} steps={args.steps} warmup={args.warmup}", file=sys.stderr,
           flush=True)
-    res = run_form(cup, torch, A0, P16, main_form, args.steps, args.warmup, profile=True)
+    res = run_form(cup, torch, A0, P16, form, args.steps, args.warmup, profile=True)
     r = res["rank"]
     F = field_ops(n, n, r)
     value = F / res["seconds"]
-    resolved = "fp64" if main_form in ("auto", "fp64") else main_form
-    gkey = f"cup_{n}_uniform_p{P16}_seed2"
-    parity = ("oracle digest match" if gold.get(gkey, {}).get("digest") == res["digest"]
-              else ("ORACLE DIGEST MISMATCH" if gkey in gold else "no oracle digest at this size"))
-
-    st = res["stats"]["ffgemm"]
-    peak, unit = PEAK[resolved]
-    mult = 4.0 if resolved == "i8limb" else 1.0
-    achieved = (mult * st["flops"] / (st["ms"] * 1e-3) / 1e12) if st["ms"] > 0 else 0.0
-    roofline = {
-        "bound": "mfma", "kernel": f"ffgemm ({resolved})",
-        "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-        "frac": round(achieved / peak, 4),
-        "traffic": None,
-        "launches_per_step": st["launches"] / args.steps,
-        "avg_launch_ms": st["ms"] / max(1.0, st["launches"]),
-        "ops_per_launch": mult * st["flops"] / max(1.0, st["launches"]),
-        "kernel_ms_per_step": st["ms"] / args.steps,
-    }
-    win = res["stats"]["window"]
-    extra = {"window_kernel": {"launches_per_step": win["launches"] / args.steps,
-                               "kernel_ms_per_step": win["ms"] / args.steps}}
-
-    forms = {resolved: {"ms_per_step": res["seconds"] * 1e3, "field_ops_per_s": value,
-                        "parity": parity}}
+    parity = parity_of(res, gkey)
+    roofline = roofline_of(res["stats"], form, args.steps)
+    forms = {form: {"ms_per_step": res["seconds"] * 1e3, "field_ops_per_s": value, "parity": parity,
+                    "kernels": breakdown(res["stats"], args.steps)}}
+    extra = {}
+    if form != "fp64" and not args.no_variants:
+        print("[bench] plain FP64-carrier form on the same input", file=sys.stderr, flush=True)
+        rf = run_form(cup, torch, A0, P16, "fp64", max(1, args.steps // 2), 1, profile=True)
+        forms["fp64"] = {"ms_per_step": rf["seconds"] * 1e3,
+                         "field_ops_per_s": field_ops(n, n, rf["rank"]) / rf["seconds"],
+                         "parity": parity_of(rf, gkey),
+                         "kernels": breakdown(rf["stats"], max(1, args.steps // 2)),
+                         "roofline": roofline_of(rf["stats"], "fp64", max(1, args.steps // 2))}
+        extra["speedup_vs_fp64_form"] = forms["fp64"]["ms_per_step"] / forms[form]["ms_per_step"]
     if not args.no_variants:
         print("[bench] rank-6000 variant (seed 20)", file=sys.stderr, flush=True)
         B0 = torch.from_numpy(inputs.low_rank(n, n, min(6000, n), P16, seed=20, device="cuda")).cuda()
-        rv = run_form(cup, torch, B0, P16, main_form, max(1, args.steps // 2), 1, profile=False)
-        gk = f"cup_{n}_rank6000_p{P16}_seed20"
+        rv = run_form(cup, torch, B0, P16, form, max(1, args.steps // 2), 1, profile=False)
         extra["rank6000"] = {
-            "rank": rv["rank"], "ms_per_step": rv["seconds"] * 1e3,
+            "rank": rv["rank"], "form": form, "ms_per_step": rv["seconds"] * 1e3,
             "field_ops_per_s": field_ops(n, n, rv["rank"]) / rv["seconds"],
-            "parity": ("oracle digest match" if gold.get(gk, {}).get("digest") == rv["digest"]
-                       else ("ORACLE DIGEST MISMATCH" if gk in gold else "no oracle digest")),
+            "parity": parity_of(rv, f"cup_{n}_rank6000_p{P16}_seed20"),
         }
         del B0
+    cup.cup_set_form("auto")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -181,10 +198,10 @@ def main():
         "metric": METRIC, "value": value, "unit": "field ops/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["seconds"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if resolved == "fp64" else "i8", "data": "synthetic",
+        "dtype": "f64" if form == "fp64" else "i8", "data": "synthetic",
         "config": {"workload": f"CUP over GF({P16}), {n}x{n} uniform residues (seed 2), "
                                f"full rank; packed [C\\U], P, Q in place",
-                   "m": n, "n": n, "p": P16, "rank": r, "form": resolved,
+                   "m": n, "n": n, "p": P16, "rank": r, "form": form,
                    "field_ops_per_step": F, "parity": parity},
         "roofline": roofline, "cpu_baseline": cpu, "forms": forms, **extra,
     }

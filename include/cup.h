@@ -171,13 +171,14 @@ const char *cup_strerror(int status);
  * Kernel timing for measurement.  cup_profile(1) resets and starts timing
  * every ffgemm launch and every leaf-window launch with a pair of HIP events
  * on the launch stream (no extra synchronisation); cup_profile(0) stops.
- * cup_profile_read fills stats[12] with four figures for each of three
+ * cup_profile_read fills stats[16] with four figures for each of four
  * kernel classes: {launches, kernel ms, algorithmic field operations
- * (2MNK per product), algorithmic bytes ((MK + KN + 2MN) x element size per
- * product)} for the FP64-carrier ffgemm, then the leaf window kernel
- * (operations 0, bytes = one read and one write of its tile), then the INT8
- * ffgemm forms (packing launches included in the time).  Returns -1 if
- * stats is NULL.
+ * (2MNK per product), algorithmic bytes} for (0) the FP64-carrier ffgemm
+ * (bytes (MK + KN + 2MN) x element size), (1) the leaf window kernel
+ * (operations 0, bytes one read and one write of its tile), (2) the INT8
+ * ffgemm product kernel (bytes: packed operands read once plus C read and
+ * written), (3) the INT8 operand packing (operations 0, bytes read and
+ * written).  Returns -1 if stats is NULL.
  */
 int cup_profile(int enable);
 int cup_profile_read(double *stats);

@@ -62,12 +62,18 @@ void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t l
                        int kred_steps);
 
 // C(MxN) <- C + alpha A(MxK) B(KxN) mod p on INT8 MFMA: limb = 0 for p < 2^7
-// (one signed byte per residue), 1 for p <= 2^16 (two signed limbs).  `ws`
-// holds at least ffgemm_i8_workspace(M, N, K, limb) bytes.
+// (one signed byte per residue), 1 for p <= 2^16 (two signed limbs).  Per K
+// chunk of at most ffgemm_i8_kmax(limb) terms: launch_pack_i8 packs A and B
+// into `ws` (ffgemm_i8_workspace bytes) and returns the padded depth Kp,
+// then launch_mma_i8 multiplies and adds alpha A B to C.
+int ffgemm_i8_kmax(int limb);
 size_t ffgemm_i8_workspace(int M, int N, int K, int limb);
 template <typename T>
-void launch_ffgemm_i8(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, const T* B,
-                      int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, int limb, int8_t* ws);
+int launch_pack_i8(hipStream_t s, int M, int N, int kc, const T* A, int64_t lda, const T* B,
+                   int64_t ldb, ModP mp, int limb, int8_t* ws);
+template <typename T>
+void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, int64_t ldc,
+                   ModP mp, int alpha, int limb);
 
 // Window elimination of a leaf (see k_panel.hip).  Writes d, stop and the
 // chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col).

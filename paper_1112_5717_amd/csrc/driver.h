@@ -24,7 +24,7 @@ enum { SOLVE = 0, MULT = 1 };
 // Kernel timing with HIP events (enabled by cup_profile): every ffgemm and
 // leaf-window launch is bracketed by two events on the launch stream; the
 // elapsed times are summed after the call has synchronised.
-constexpr int kProfKinds = 3;  // 0 ffgemm FP64, 1 window, 2 ffgemm INT8 forms
+constexpr int kProfKinds = 4;  // 0 ffgemm FP64, 1 window, 2 ffgemm INT8 MFMA, 3 INT8 packing
 
 struct ProfRec {
     int kind;            // 0 ffgemm FP64, 1 window, 2 ffgemm INT8
@@ -192,17 +192,33 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
     const bool i8 = (c.form == FORM_I8 || c.form == FORM_I8LIMB) && M >= 128 && N >= 128 &&
                     K >= 64 && (double)M * N * K >= c.i8_min_work;
     const bool prof = c.prof && c.prof->on;
-    if (prof)
-        c.prof->begin(c.s, i8 ? 2 : 0, 2.0 * M * N * K,
-                      ((double)M * K + (double)K * N + 2.0 * M * N) * sizeof(T));
     if (i8) {
         const int limb = (c.form == FORM_I8LIMB) ? 1 : 0;
+        const int nl = limb ? 2 : 1;
         int8_t* ws = pack_workspace(c, ffgemm_i8_workspace(M, N, K, limb));
-        launch_ffgemm_i8<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, limb, ws);
+        const int kmax = ffgemm_i8_kmax(limb);
+        for (int k0 = 0; k0 < K; k0 += kmax) {
+            const int kc = std::min(kmax, K - k0);
+            if (prof)
+                c.prof->begin(c.s, 3, 0.0,
+                              ((double)M * kc + (double)kc * N) * (sizeof(T) + nl));
+            const int Kp = launch_pack_i8<T>(c.s, M, N, kc, A + k0, lda, B + (int64_t)k0 * ldb, ldb,
+                                             c.mp, limb, ws);
+            if (prof) {
+                c.prof->end(c.s);
+                c.prof->begin(c.s, 2, 2.0 * M * N * kc,
+                              ((double)M * kc + (double)kc * N) * nl + 2.0 * M * N * sizeof(T));
+            }
+            launch_mma_i8<T>(c.s, M, N, Kp, ws, C, ldc, c.mp, alpha, limb);
+            if (prof) c.prof->end(c.s);
+        }
     } else {
+        if (prof)
+            c.prof->begin(c.s, 0, 2.0 * M * N * K,
+                          ((double)M * K + (double)K * N + 2.0 * M * N) * sizeof(T));
         launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps);
+        if (prof) c.prof->end(c.s);
     }
-    if (prof) c.prof->end(c.s);
 }
 
 // ------------------------------------------------------------ TRSM / TRMM

@@ -214,59 +214,80 @@ __global__ __launch_bounds__(256) void ffgemm_i8_kernel(int M, int N, int Kp,
 
 }  // namespace
 
+int ffgemm_i8_kmax(int limb) { return limb ? 65472 : 131072; }  // INT32 stays exact
+
 size_t ffgemm_i8_workspace(int M, int N, int K, int limb)
 {
     const int64_t Mp = (M + IBM - 1) / IBM * IBM, Np = (N + IBN - 1) / IBN * IBN;
-    const int64_t kc = std::min<int64_t>(K, limb ? 65472 : 131072);
+    const int64_t kc = std::min<int64_t>(K, ffgemm_i8_kmax(limb));
     const int64_t Kp = (kc + IBK - 1) / IBK * IBK;
     return (size_t)((Mp + Np) * Kp * (limb ? 2 : 1));
 }
 
-template <typename T>
-void launch_ffgemm_i8(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, const T* B,
-                      int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, int limb, int8_t* ws)
+namespace {
+struct PackedPtrs {
+    int8_t *Ah, *Al, *Bh, *Bl;
+};
+PackedPtrs packed_ptrs(int8_t* ws, int M, int N, int Kp, int limb)
 {
-    if (M <= 0 || N <= 0 || K <= 0) return;
     const int64_t Mp = (M + IBM - 1) / IBM * IBM, Np = (N + IBN - 1) / IBN * IBN;
-    const int kmax = limb ? 65472 : 131072;  // INT32 accumulators stay exact
+    PackedPtrs q;
+    q.Ah = ws;
+    q.Al = limb ? ws + Mp * Kp : ws;
+    q.Bh = ws + (limb ? 2 : 1) * Mp * Kp;
+    q.Bl = limb ? q.Bh + Np * Kp : q.Bh;
+    return q;
+}
+}  // namespace
+
+template <typename T>
+int launch_pack_i8(hipStream_t s, int M, int N, int kc, const T* A, int64_t lda, const T* B,
+                   int64_t ldb, ModP mp, int limb, int8_t* ws)
+{
+    const int64_t Mp = (M + IBM - 1) / IBM * IBM, Np = (N + IBN - 1) / IBN * IBN;
+    const int Kp = (kc + IBK - 1) / IBK * IBK;
     const int p = (int)mp.p;
-    for (int k0 = 0; k0 < K; k0 += kmax) {
-        const int kc = std::min(kmax, K - k0);
-        const int Kp = (kc + IBK - 1) / IBK * IBK;
-        int8_t* Ah = ws;
-        int8_t* Al = Ah + Mp * Kp;
-        int8_t* Bh = ws + (limb ? 2 : 1) * Mp * Kp;
-        int8_t* Bl = Bh + Np * Kp;
-        const dim3 gr((Kp + 255) / 256, (unsigned)std::min<int64_t>(Mp, 65535));
-        const dim3 gc((Kp + 63) / 64, (unsigned)(Np / 64));
-        if (limb) {
-            hipLaunchKernelGGL((pack_rows_kernel<T, 1>), gr, dim3(256), 0, s, A + k0, lda, M, kc, Ah,
-                               Al, (int)Mp, Kp, p);
-            hipLaunchKernelGGL((pack_cols_kernel<T, 1>), gc, dim3(256), 0, s, B + (int64_t)k0 * ldb,
-                               ldb, kc, N, Bh, Bl, Kp, p);
-        } else {
-            hipLaunchKernelGGL((pack_rows_kernel<T, 0>), gr, dim3(256), 0, s, A + k0, lda, M, kc, Ah,
-                               Ah, (int)Mp, Kp, p);
-            hipLaunchKernelGGL((pack_cols_kernel<T, 0>), gc, dim3(256), 0, s, B + (int64_t)k0 * ldb,
-                               ldb, kc, N, Bh, Bh, Kp, p);
-        }
-        CUP_HIP(hipGetLastError());
-        const dim3 grid((unsigned)(Np / IBN), (unsigned)(Mp / IBM));
-        if (limb)
-            hipLaunchKernelGGL((ffgemm_i8_kernel<T, 1>), grid, dim3(256), 0, s, M, N, Kp, Ah, Al, Bh, Bl,
-                               C, ldc, mp, alpha);
-        else
-            hipLaunchKernelGGL((ffgemm_i8_kernel<T, 0>), grid, dim3(256), 0, s, M, N, Kp, Ah, Ah, Bh, Bh,
-                               C, ldc, mp, alpha);
-        CUP_HIP(hipGetLastError());
+    const PackedPtrs q = packed_ptrs(ws, M, N, Kp, limb);
+    const dim3 gr((Kp + 255) / 256, (unsigned)std::min<int64_t>(Mp, 65535));
+    const dim3 gc((Kp + 63) / 64, (unsigned)(Np / 64));
+    if (limb) {
+        hipLaunchKernelGGL((pack_rows_kernel<T, 1>), gr, dim3(256), 0, s, A, lda, M, kc, q.Ah, q.Al,
+                           (int)Mp, Kp, p);
+        hipLaunchKernelGGL((pack_cols_kernel<T, 1>), gc, dim3(256), 0, s, B, ldb, kc, N, q.Bh, q.Bl,
+                           Kp, p);
+    } else {
+        hipLaunchKernelGGL((pack_rows_kernel<T, 0>), gr, dim3(256), 0, s, A, lda, M, kc, q.Ah, q.Ah,
+                           (int)Mp, Kp, p);
+        hipLaunchKernelGGL((pack_cols_kernel<T, 0>), gc, dim3(256), 0, s, B, ldb, kc, N, q.Bh, q.Bh,
+                           Kp, p);
     }
+    CUP_HIP(hipGetLastError());
+    return Kp;
 }
 
-template void launch_ffgemm_i8<int64_t>(hipStream_t, int, int, int, const int64_t*, int64_t,
-                                        const int64_t*, int64_t, int64_t*, int64_t, ModP, int, int,
-                                        int8_t*);
-template void launch_ffgemm_i8<int8_t>(hipStream_t, int, int, int, const int8_t*, int64_t,
-                                       const int8_t*, int64_t, int8_t*, int64_t, ModP, int, int,
-                                       int8_t*);
+template <typename T>
+void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, int64_t ldc,
+                   ModP mp, int alpha, int limb)
+{
+    const int64_t Mp = (M + IBM - 1) / IBM * IBM, Np = (N + IBN - 1) / IBN * IBN;
+    const PackedPtrs q = packed_ptrs(const_cast<int8_t*>(ws), M, N, Kp, limb);
+    const dim3 grid((unsigned)(Np / IBN), (unsigned)(Mp / IBM));
+    if (limb)
+        hipLaunchKernelGGL((ffgemm_i8_kernel<T, 1>), grid, dim3(256), 0, s, M, N, Kp, q.Ah, q.Al, q.Bh,
+                           q.Bl, C, ldc, mp, alpha);
+    else
+        hipLaunchKernelGGL((ffgemm_i8_kernel<T, 0>), grid, dim3(256), 0, s, M, N, Kp, q.Ah, q.Al, q.Bh,
+                           q.Bl, C, ldc, mp, alpha);
+    CUP_HIP(hipGetLastError());
+}
+
+#define CUP_INST(T)                                                                             \
+    template int launch_pack_i8<T>(hipStream_t, int, int, int, const T*, int64_t, const T*,     \
+                                   int64_t, ModP, int, int8_t*);                                \
+    template void launch_mma_i8<T>(hipStream_t, int, int, int, const int8_t*, T*, int64_t, ModP, \
+                                   int, int);
+CUP_INST(int64_t)
+CUP_INST(int8_t)
+#undef CUP_INST
 
 }  // namespace cup

@@ -221,12 +221,12 @@ def cup_profile(enable: bool) -> None:
 
 def cup_profile_read() -> dict:
     """Kernel timing collected since cup_profile(True)."""
-    buf = (ctypes.c_double * 12)()
+    buf = (ctypes.c_double * 16)()
     load().cup_profile_read(buf)
     v = list(buf)
     keys = ("launches", "ms", "flops", "bytes")
     return {"ffgemm": dict(zip(keys, v[0:4])), "window": dict(zip(keys, v[4:8])),
-            "ffgemm_i8": dict(zip(keys, v[8:12]))}
+            "ffgemm_i8": dict(zip(keys, v[8:12])), "pack_i8": dict(zip(keys, v[12:16]))}
 
 
 def cup_workspace_bytes() -> int:
