@@ -47,40 +47,9 @@ __device__ void load_triangle(double (*M)[NB + 1], const T* A, int64_t lda, int 
     }
 }
 
-// Column j of the inverse of the triangle in M: solves M x = e_j, with the
-// column in registers and the loops unrolled.  Right-looking: once x[i] is
-// known it is folded into the partial sums of every later row, so the
-// dependency chain is one multiply per row and the updates run in parallel.
-// Sums of up to 64 products stay exact for p < 2^23.5.
-__device__ __forceinline__ void inverse_column(const double (*M)[NB + 1], const double* dinv,
-                                               int uplo, int j, double* x, double P, double PI)
-{
-    double acc[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) acc[i] = (i == j) ? 1.0 : 0.0;
-    if (uplo == 1) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            double r = mod_red(acc[i], P, PI);
-            x[i] = mod_mul(r, dinv[i], P, PI);
-            const double nx = (x[i] == 0.0) ? 0.0 : P - x[i];
-#pragma unroll
-            for (int t = i + 1; t < NB; ++t) acc[t] = fma(M[t][i], nx, acc[t]);
-        }
-    } else {
-#pragma unroll
-        for (int i = NB - 1; i >= 0; --i) {
-            double r = mod_red(acc[i], P, PI);
-            x[i] = mod_mul(r, dinv[i], P, PI);
-            const double nx = (x[i] == 0.0) ? 0.0 : P - x[i];
-#pragma unroll
-            for (int t = 0; t < i; ++t) acc[t] = fma(M[t][i], nx, acc[t]);
-        }
-    }
-}
-
-// The same for p >= 2^23.5: rolled loops, the column in LDS (X[.][j]), the
-// partial sum reduced after every product.
+// Column j of the inverse of the triangle in M (solves M x = e_j) for
+// p >= 2^23.5: rolled loops, the column in LDS (X[.][j]), the partial sum
+// reduced after every product.
 __device__ void inverse_column_big(const double (*M)[NB + 1], const double* dinv, int uplo,
                                    int j, double (*X)[NB + 1], double P, double PI)
 {
@@ -96,44 +65,115 @@ __device__ void inverse_column_big(const double (*M)[NB + 1], const double* dinv
     }
 }
 
+// Inverse of the upper triangle held in M (64 x 64, identity-padded), into X,
+// by 16 x 16 blocks: the four diagonal blocks are inverted column-parallel
+// (a chain of 16 steps), then the off-diagonal blocks follow by increasing
+// block distance d = b - a:  X_ab = -D_a (sum_{a < k <= b} M_ak X_kb).
+// 256 threads; sums of at most 48 products stay exact for p < 2^23.5.
+__device__ void block_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 1],
+                                    double (*S)[NB + 1], const double* dinv, double P, double PI)
+{
+    const int tid = threadIdx.x;
+    if (tid < NB) {
+        const int a = tid >> 4, j = tid & 15, o = 16 * a;  // column o + j of block a
+        double acc[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            const double x = mod_mul(mod_red(acc[i], P, PI), dinv[o + i], P, PI);
+            X[o + i][o + j] = x;
+            const double nx = (x == 0.0) ? 0.0 : P - x;
+#pragma unroll
+            for (int t = 0; t < i; ++t) acc[t] = fma(M[o + t][o + i], nx, acc[t]);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            for (int b = 0; b < 4; ++b)
+                if (b != a) X[o + i][16 * b + j] = 0.0;
+    }
+    __syncthreads();
+    for (int d = 1; d < 4; ++d) {
+        const int nblk = 4 - d;  // blocks (a, a + d)
+        // S_ab = sum_{k=a+1..b} M_ak X_kb
+        for (int idx = tid; idx < nblk * 256; idx += 256) {
+            const int a = idx >> 8, e = idx & 255, i = e >> 4, j = e & 15, b = a + d;
+            double acc = 0.0;
+            for (int s = 16 * (a + 1); s < 16 * (b + 1); ++s) acc = fma(M[16 * a + i][s], X[s][16 * b + j], acc);
+            S[16 * a + i][16 * b + j] = mod_red(acc, P, PI);
+        }
+        __syncthreads();
+        // X_ab = -D_a S_ab
+        for (int idx = tid; idx < nblk * 256; idx += 256) {
+            const int a = idx >> 8, e = idx & 255, i = e >> 4, j = e & 15, b = a + d;
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < 16; ++s) acc = fma(X[16 * a + i][16 * a + s], S[16 * a + s][16 * b + j], acc);
+            const double x = mod_red(acc, P, PI);
+            X[16 * a + i][16 * b + j] = (x == 0.0) ? 0.0 : P - x;
+        }
+        __syncthreads();
+    }
+}
+
 // mode 0: W[b] = T_bb^{-1}; mode 1: W[b] = T_bb; mode 2: T_bb <- T_bb^{-1} in
-// place (the unit diagonal, if any, is left untouched).  One block of 64
-// threads per diagonal block.
+// place (the unit diagonal, if any, is left untouched).  One workgroup of
+// 256 threads per diagonal block; a lower triangle is handled as the
+// transpose of an upper one.
 template <typename T, bool BIG>
-__global__ __launch_bounds__(NB) void diag_prep_kernel(T* __restrict__ A, int64_t lda, int n, int uplo,
-                                                       int unit, int mode, double* __restrict__ W,
-                                                       ModP mp)
+__global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64_t lda, int n, int uplo,
+                                                        int unit, int mode, double* __restrict__ W,
+                                                        ModP mp)
 {
     __shared__ double M[NB][NB + 1];
+    __shared__ double X[NB][NB + 1];
+    __shared__ double S[NB][NB + 1];
     __shared__ double dinv[NB];
-    const int b = blockIdx.x, o = b * NB, nb = min(NB, n - o), j = threadIdx.x;
+    const int b = blockIdx.x, o = b * NB, nb = min(NB, n - o), tid = threadIdx.x;
     const double P = mp.p, PI = mp.pinv;
-    load_triangle(M, A, lda, o, nb, uplo, unit);
+    // M = T_bb (upper) or its transpose (lower), identity-padded
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int i = idx >> 6, s = idx & 63;
+        double v;
+        if (i >= nb || s >= nb) {
+            v = (i == s) ? 1.0 : 0.0;
+        } else {
+            const int r = (uplo == 0) ? i : s, c = (uplo == 0) ? s : i;  // element (r, c) of T
+            v = (s >= i) ? ld_res(A + (int64_t)(o + r) * lda + o + c) : 0.0;
+            if (i == s && unit) v = 1.0;
+        }
+        M[i][s] = v;
+    }
     __syncthreads();
     if (mode == 1) {
         double* Wb = W + (size_t)b * NB * NB;
-        for (int i = 0; i < NB; ++i) Wb[i * NB + j] = M[i][j];
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            const int i = idx >> 6, s = idx & 63;
+            Wb[idx] = (uplo == 0) ? M[i][s] : M[s][i];
+        }
         return;
     }
-    dinv[j] = (unit || j >= nb) ? 1.0 : mod_inv(M[j][j], P, PI);
+    if (tid < NB) dinv[tid] = (unit || tid >= nb) ? 1.0 : mod_inv(M[tid][tid], P, PI);
     __syncthreads();
-    double x[NB];
     if constexpr (BIG) {
-        __shared__ double X[NB][NB + 1];
-        inverse_column_big(M, dinv, uplo, j, X, P, PI);
-        for (int i = 0; i < NB; ++i) x[i] = X[i][j];
+        if (tid < NB) inverse_column_big(M, dinv, 0, tid, X, P, PI);
+        __syncthreads();
     } else {
-        inverse_column(M, dinv, uplo, j, x, P, PI);
+        block_upper_inverse(M, X, S, dinv, P, PI);
     }
+    // X holds the inverse of the upper form; the lower inverse is its transpose
     if (mode == 0) {
         double* Wb = W + (size_t)b * NB * NB;
-#pragma unroll
-        for (int i = 0; i < NB; ++i) Wb[i * NB + j] = x[i];
-    } else if (j < nb) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            bool write = (uplo == 0) ? (unit ? j > i : j >= i) : (unit ? j < i : j <= i);
-            if (i < nb && write) st_res(A + (int64_t)(o + i) * lda + o + j, x[i]);
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            const int i = idx >> 6, s = idx & 63;
+            Wb[idx] = (uplo == 0) ? X[i][s] : X[s][i];
+        }
+    } else {
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            const int i = idx >> 6, s = idx & 63;  // element (i, s) of the inverse
+            if (i >= nb || s >= nb) continue;
+            const bool write = (uplo == 0) ? (unit ? s > i : s >= i) : (unit ? s < i : s <= i);
+            if (write) st_res(A + (int64_t)(o + i) * lda + o + s, (uplo == 0) ? X[i][s] : X[s][i]);
         }
     }
 }
@@ -271,10 +311,10 @@ void launch_diag_prep(hipStream_t s, T* A, int64_t lda, int n, int uplo, int uni
     if (n <= 0) return;
     const int nblk = (mode == 2) ? 1 : (n + NB - 1) / NB;
     if (big_prime(mp))
-        hipLaunchKernelGGL((diag_prep_kernel<T, true>), dim3(nblk), dim3(NB), 0, s, A, lda, n, uplo,
+        hipLaunchKernelGGL((diag_prep_kernel<T, true>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
                            unit, mode, W, mp);
     else
-        hipLaunchKernelGGL((diag_prep_kernel<T, false>), dim3(nblk), dim3(NB), 0, s, A, lda, n, uplo,
+        hipLaunchKernelGGL((diag_prep_kernel<T, false>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
                            unit, mode, W, mp);
     CUP_HIP(hipGetLastError());
 }
