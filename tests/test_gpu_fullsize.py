@@ -1,0 +1,107 @@
+"""Full-size GPU parity: the library's outputs at the full workload sizes
+hash to the SHA-256 digests of the CPU oracle's outputs on the same seeded
+inputs (tests/golden/full_size_hashes.json, written by
+tests/golden/make_full_size_hashes.py, which calls only the oracle).
+
+A digest match means every entry of the packed matrix, every transposition
+of P and Q and the rank agree bit for bit.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1112_5717_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "full_size_hashes.json")))
+
+
+def cup_digest(packed, r, P, Q) -> str:
+    h = hashlib.sha256()
+    for a in (packed, P, Q):
+        h.update(np.ascontiguousarray(a, dtype=np.int64).tobytes())
+    h.update(np.int64(r).tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.parametrize("form", ["i8limb", "fp64"])
+def test_config2_uniform_8192(cup_lib, form):
+    """8192 x 8192 uniform over GF(65521), seed 2 (full rank)."""
+    p = 65521
+    d = torch.from_numpy(inputs.uniform((8192, 8192), p, seed=2)).cuda()
+    cup_lib.cup_set_form(form)
+    try:
+        r, P, Q = cup_lib.cup_factor(d, p)
+    finally:
+        cup_lib.cup_set_form("auto")
+    g = GOLD["cup_8192_uniform_p65521_seed2"]
+    assert r == g["rank"] == 8192
+    assert cup_digest(d.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()) == g["digest"]
+
+
+def test_config2_rank6000(cup_lib):
+    """X(8192 x 6000) Y(6000 x 8192) mod 65521, seed 20."""
+    p = 65521
+    d = torch.from_numpy(inputs.low_rank(8192, 8192, 6000, p, seed=20, device="cuda")).cuda()
+    r, P, Q = cup_lib.cup_factor(d, p)
+    g = GOLD["cup_8192_rank6000_p65521_seed20"]
+    assert r == g["rank"] == 6000
+    assert cup_digest(d.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()) == g["digest"]
+
+
+def test_config3_int8_16384(cup_lib):
+    """X(16384 x 12000) Y(12000 x 16384) mod 127, int8 storage, seed 3."""
+    p = 127
+    A = inputs.low_rank(16384, 16384, 12000, p, seed=3, device="cuda")
+    d = torch.from_numpy(A.astype(np.int8)).cuda()
+    del A
+    r, P, Q = cup_lib.cup_factor_i8(d, p)
+    g = GOLD["cup_16384_rank12000_p127_seed3"]
+    assert r == g["rank"] == 12000
+    assert cup_digest(d.cpu().numpy().astype(np.int64), r, P.cpu().numpy(), Q.cpu().numpy()) == g["digest"]
+
+
+def test_config3_inverse_8192(cup_lib):
+    """Inverse of the first nonsingular uniform 8192 x 8192 over GF(127) (seed 30), int8 storage."""
+    p = 127
+    g = GOLD["inverse_8192_p127_seed30"]
+    d = torch.from_numpy(inputs.uniform((8192, 8192), p, seed=g["seed"]).astype(np.int8)).cuda()
+    ok, r = cup_lib.cup_inverse_inplace_i8(d, p)
+    assert ok and r == 8192
+    X = d.cpu().numpy().astype(np.int64)
+    assert hashlib.sha256(np.ascontiguousarray(X).tobytes()).hexdigest() == g["digest"]
+
+
+def _staircase():
+    p = 65521
+    A, piv = inputs.staircase(32768, 8192, 2048, p, seed=5, device="cuda")
+    return p, A, piv
+
+
+def test_config5_staircase_cup(cup_lib):
+    """32768 x 8192 over GF(65521), rank 2048, seeded staircase profile."""
+    p, A, piv = _staircase()
+    d = torch.from_numpy(A).cuda()
+    del A
+    r, P, Q = cup_lib.cup_factor(d, p)
+    g = GOLD["cup_32768x8192_staircase2048_p65521_seed5"]
+    assert r == g["rank"] == 2048
+    assert np.array_equal(Q.cpu().numpy()[:r], piv)
+    assert cup_digest(d.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()) == g["digest"]
+
+
+def test_config5_staircase_rref(cup_lib):
+    p, A, piv = _staircase()
+    d = torch.from_numpy(A).cuda()
+    del A
+    r, P, Q = cup_lib.cup_rref_inplace(d, p)
+    g = GOLD["rref_32768x8192_staircase2048_p65521_seed5"]
+    assert r == g["rank"] == 2048
+    assert cup_digest(d.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()) == g["digest"]
