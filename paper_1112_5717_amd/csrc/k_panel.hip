@@ -111,7 +111,13 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         if (a >= R) { stop = STOP_ROWS; break; }
         if (a >= wc) { stop = STOP_WINDOW; break; }
         const int par = a & 1, qa = a >> 6, la = a & 63;
+        // every LDS read of the step issued together (no swap assumed)
         const int j = s_j[par];
+        double piv = rowbuf[par][a];
+        double u0 = rowbuf[par][lane], u1 = rowbuf[par][lane + 64];
+        double mlt[KPW];
+#pragma unroll
+        for (int k = 0; k < KPW; ++k) mlt[k] = colbuf[par][w + NWV * k];
         if (j < 0) { stop = STOP_ZERO_ROW; break; }
         if (j != a) {
             // swap columns a and j: both live in the same lanes of every wave
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 if (lane == la) { if (qa) v[1][k] = from_j; else v[0][k] = from_j; }
                 if (lane == lj) { if (qj) v[1][k] = from_a; else v[0][k] = from_a; }
             }
-            __syncthreads();  // everyone has read s_j and the old column a
+            __syncthreads();  // every wave has read the step's buffers
             if (lane == la) {
 #pragma unroll
                 for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = qa ? v[1][k] : v[0][k];
@@ -136,19 +142,19 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 rowbuf[par][j] = x;
             }
             __syncthreads();
+            piv = rowbuf[par][a];
+            u0 = rowbuf[par][lane];
+            u1 = rowbuf[par][lane + 64];
+#pragma unroll
+            for (int k = 0; k < KPW; ++k) mlt[k] = colbuf[par][w + NWV * k];
         }
-        const double piv = rowbuf[par][a];
         if (tid == 0) {
             s_swap[a] = j;
             s_piv[a] = mod_red(piv, P, PI);
         }
-        // fraction-free update of rows > a, columns > a: multipliers loaded
-        // up front, rows skipped per wave, columns masked per lane
-        const double u0 = rowbuf[par][lane], u1 = rowbuf[par][lane + 64];
+        // fraction-free update of rows > a, columns > a: rows skipped per
+        // wave, columns masked per lane
         const bool c0 = lane > a, c1 = lane + 64 > a;
-        double mlt[KPW];
-#pragma unroll
-        for (int k = 0; k < KPW; ++k) mlt[k] = colbuf[par][w + NWV * k];
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
             if (w + NWV * k > a) {

@@ -99,7 +99,13 @@ __device__ void block_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 
         for (int idx = tid; idx < nblk * 256; idx += 256) {
             const int a = idx >> 8, e = idx & 255, i = e >> 4, j = e & 15, b = a + d;
             double acc = 0.0;
-            for (int s = 16 * (a + 1); s < 16 * (b + 1); ++s) acc = fma(M[16 * a + i][s], X[s][16 * b + j], acc);
+            for (int kb = a + 1; kb <= b; ++kb) {
+                double part = 0.0;
+#pragma unroll
+                for (int s = 0; s < 16; ++s)
+                    part = fma(M[16 * a + i][16 * kb + s], X[16 * kb + s][16 * b + j], part);
+                acc += part;
+            }
             S[16 * a + i][16 * b + j] = mod_red(acc, P, PI);
         }
         __syncthreads();
