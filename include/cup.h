@@ -132,19 +132,22 @@ int cup_inverse_inplace_i8(int64_t n, int8_t *A, int64_t lda, int64_t p, int64_t
 
 /*
  * Batched CUP of independent matrices, each with its own prime
- * (Algorithm 6 per matrix; a multi-modular workload).
+ * (Algorithm 6 per matrix; a multi-modular workload).  One GPU workgroup
+ * factors one matrix, largest matrices first (batches of up to 32768 are
+ * ordered by m n min(m,n)); each result is the one cup_factor gives.
  *   batch          : number of matrices (>= 0)
- *   m, n, lda, p   : device int64 arrays of length batch
+ *   m, n, lda, p   : device int64 arrays of length batch; n[i] <= 512
  *   A              : device array of batch device pointers (int64 matrices)
  *   rank           : device int64 array of length batch
  *   P, Q           : device arrays of batch device pointers (each P[i] of
  *                    length n[i], Q[i] of length m[i]); P or Q may be NULL
  *   info           : device int32 array; info[i] receives matrix i's status
- *                    with the codes of cup_factor
- * Returns 0 when the batch was processed (per-matrix status in info), or a
- * negative code for an invalid batch-level argument (-1 batch, -3 A, -7
- * rank, -10 info).  The call is asynchronous on the stream: outputs are on
- * the device only.
+ *                    with the argument codes of cup_factor (-1 m, -2 n or
+ *                    n > 512, -3 A, -4 lda, -5 p); rank[i] is 0 on error
+ * Returns 0 when the batch was queued (per-matrix status in info), or a
+ * negative code for an invalid batch-level argument (-1 batch, -2 m, -3 n,
+ * -4 A, -5 lda, -6 p, -7 rank, -10 info; -2000 workspace allocation).  The
+ * call is asynchronous on the stream: outputs are on the device only.
  */
 int cup_factor_batched(int64_t batch, const int64_t *m, const int64_t *n, int64_t *const *A,
                        const int64_t *lda, const int64_t *p, int64_t *rank, int64_t *const *P,

@@ -23,10 +23,14 @@ struct Global {
     int* h_small = nullptr;
     int* d_list = nullptr;
     size_t list_cap = 0;  // ints
+    int* d_order = nullptr;  // processing order of the batched entry point
+    size_t order_cap = 0;    // ints
     size_t bytes = 0;
     Profiler prof;
     Workspace ws;
 };
+
+constexpr int64_t kOrderMax = 32768;  // largest batch that is sorted by cost
 
 Global& G()
 {
@@ -331,39 +335,35 @@ int cup_factor_batched(int64_t batch, const int64_t* m, const int64_t* n, int64_
     if (!p) return -6;
     if (!rank) return -7;
     if (!info) return -10;
-    // Gather the batch description on the host, then factor each matrix.
+    if (batch > INT32_MAX) return -1;
     Global& g = G();
-    hipStream_t s;
-    {
-        std::lock_guard<std::mutex> lk(g.mu);
-        s = g.stream;
-    }
+    std::lock_guard<std::mutex> lk(g.mu);
     try {
-        size_t B = (size_t)batch;
-        std::vector<int64_t> hm(B), hn(B), hl(B), hp(B), hr(B, 0);
-        std::vector<int64_t*> hA(B), hP(B, nullptr), hQ(B, nullptr);
-        std::vector<int32_t> hi(B, 0);
-        CUP_HIP(hipMemcpyAsync(hm.data(), m, 8 * B, hipMemcpyDeviceToHost, s));
-        CUP_HIP(hipMemcpyAsync(hn.data(), n, 8 * B, hipMemcpyDeviceToHost, s));
-        CUP_HIP(hipMemcpyAsync(hl.data(), lda, 8 * B, hipMemcpyDeviceToHost, s));
-        CUP_HIP(hipMemcpyAsync(hp.data(), p, 8 * B, hipMemcpyDeviceToHost, s));
-        CUP_HIP(hipMemcpyAsync(hA.data(), A, sizeof(void*) * B, hipMemcpyDeviceToHost, s));
-        if (P) CUP_HIP(hipMemcpyAsync(hP.data(), P, sizeof(void*) * B, hipMemcpyDeviceToHost, s));
-        if (Q) CUP_HIP(hipMemcpyAsync(hQ.data(), Q, sizeof(void*) * B, hipMemcpyDeviceToHost, s));
-        CUP_HIP(hipStreamSynchronize(s));
-        for (size_t i = 0; i < B; ++i) {
-            int64_t r = 0;
-            hi[i] = factor_impl<int64_t>(hm[i], hn[i], hA[i], hl[i], hp[i], &r, hP[i], hQ[i], 0);
-            hr[i] = r;
+        // Largest matrices first (a counting sort on the device, quadratic in
+        // the batch, so only up to kOrderMax matrices); then one workgroup
+        // per matrix.  Nothing is read back: the call stays asynchronous.
+        int* order = nullptr;
+        if (batch <= kOrderMax) {
+            if ((size_t)batch > g.order_cap) {
+                if (g.d_order) {
+                    CUP_HIP(hipDeviceSynchronize());
+                    (void)hipFree(g.d_order);
+                    g.bytes -= sizeof(int) * g.order_cap;
+                    g.d_order = nullptr;
+                    g.order_cap = 0;
+                }
+                size_t cap = std::max<size_t>((size_t)batch, 4096);
+                if (hipMalloc((void**)&g.d_order, sizeof(int) * cap) != hipSuccess)
+                    throw CupError{CUP_ERR_ALLOC};
+                g.order_cap = cap;
+                g.bytes += sizeof(int) * cap;
+            }
+            order = g.d_order;
         }
-        CUP_HIP(hipMemcpyAsync(rank, hr.data(), 8 * B, hipMemcpyHostToDevice, s));
-        CUP_HIP(hipMemcpyAsync(info, hi.data(), 4 * B, hipMemcpyHostToDevice, s));
-        CUP_HIP(hipStreamSynchronize(s));
+        launch_batched_cup(g.stream, (int)batch, m, n, A, lda, p, rank, P, Q, info, order);
         return CUP_OK;
     } catch (const CupError& e) {
         return e.code;
-    } catch (const std::bad_alloc&) {
-        return CUP_ERR_ALLOC;
     }
 }
 
@@ -437,6 +437,7 @@ int cup_finalize(void)
     if (g.d_small) (void)hipFree(g.d_small);
     if (g.h_small) (void)hipHostFree(g.h_small);
     if (g.d_list) (void)hipFree(g.d_list);
+    if (g.d_order) (void)hipFree(g.d_order);
     if (g.ws.tri) (void)hipFree(g.ws.tri);
     if (g.ws.pk) (void)hipFree(g.ws.pk);
     g.ws = Workspace{};
@@ -444,6 +445,8 @@ int cup_finalize(void)
     g.h_small = nullptr;
     g.d_list = nullptr;
     g.list_cap = 0;
+    g.d_order = nullptr;
+    g.order_cap = 0;
     g.bytes = 0;
     return CUP_OK;
 }

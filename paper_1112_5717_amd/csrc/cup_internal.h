@@ -142,4 +142,12 @@ template <typename T>
 void launch_copy2d(hipStream_t s, const T* src, int64_t lds, T* dst, int64_t ldd, int rows,
                    int cols);
 
+// Batched CUP (one workgroup per matrix, n <= batched_max_n()), all
+// descriptors on the device; `order` (batch ints) receives the processing
+// order, or is null to process the matrices in index order.
+int batched_max_n();
+void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_t* n,
+                        int64_t* const* A, const int64_t* lda, const int64_t* p, int64_t* rank,
+                        int64_t* const* P, int64_t* const* Q, int32_t* info, int* order);
+
 }  // namespace cup

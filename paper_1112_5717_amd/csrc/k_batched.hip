@@ -1,0 +1,424 @@
+// Batched CUP: many independent small matrices, each over its own prime
+// (Algorithm 6 applied to every matrix of a multi-modular batch).
+//
+// One workgroup factors one matrix, start to finish, in a single launch.
+// The recursion of Algorithm 6 visits rows top-down and, with the pivot rule
+// of its base case (leftmost nonzero in the current column order), the
+// decisions it takes are those of a row-by-row elimination.  The kernel
+// groups rows into blocks of 64 and, for each block:
+//
+//  1. loads the block into registers in the current column order (the
+//     composition of every transposition so far, kept in LDS);
+//  2. eliminates it against the t pivots found before it (left-looking): for
+//     s = 0..t-1 the block's residual at position s is its entry of C, and
+//     the block rows lose C(., s) times U row s, read from the matrix, where
+//     the packed U rows live (rows 0..t-1, positions after the diagonal);
+//  3. runs the row-by-row base case inside the block: the owner wave reduces
+//     the next row, finds its leftmost nonzero at positions >= t with a
+//     ballot, inverts the pivot and publishes the normalised U row in LDS;
+//     every wave swaps the two positions in its rows and subtracts
+//     residual(i, t) times the U row from its later rows; the U row goes to
+//     row t of the matrix and the transposition to the U rows above;
+//  4. writes the block's C entries (and the echelon zeros) back.
+//
+// Updates are not reduced one by one: a residual absorbs
+// floor((2^53 - p) / (p - 1)^2) products of canonical residues before the
+// block is reduced again, and only the values that are used (a pivot row, a
+// multiplier) are reduced when they are read.
+//
+// Layout: 512 threads = 8 waves; wave w owns block rows w + 8k (k < 8);
+// lane l holds positions l + 64q (q < 8) of those rows, so n <= 512.
+#include <type_traits>
+
+#include "modarith.h"
+
+namespace cup {
+
+namespace {
+
+constexpr int BW = 8;          // waves per workgroup
+constexpr int BT = 64 * BW;    // threads per workgroup
+constexpr int BR = 64;         // rows per block
+constexpr int BK = BR / BW;    // block rows per wave
+constexpr int BQ = 8;          // position registers per lane (n <= 64 BQ)
+
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// f(std::integral_constant<int, 0>), ..., f(..., Q - 1): the index reaches
+// the body as a constant, so register arrays indexed by it stay in registers.
+template <int Q>
+struct Unroll {
+    template <class F>
+    __device__ __forceinline__ static void run(F&& f)
+    {
+        Unroll<Q - 1>::run(f);
+        f(std::integral_constant<int, Q - 1>{});
+    }
+};
+template <>
+struct Unroll<0> {
+    template <class F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
+struct BatchDesc {
+    const int64_t* m;
+    const int64_t* n;
+    int64_t* const* A;
+    const int64_t* lda;
+    const int64_t* p;
+    int64_t* rank;
+    int64_t* const* P;
+    int64_t* const* Q;
+    int32_t* info;
+    const int* order;  // processing order (largest first), or null
+};
+
+__global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
+{
+    __shared__ int perm[BQ * 64];          // position -> original column
+    __shared__ double urow[2][BQ * 64];    // published U rows (zeros up to the pivot)
+    __shared__ int s_j[2];
+    __shared__ double s_piv[2];
+    __shared__ int s_rowt[BR];             // pivots found before each block row
+    __shared__ int s_rowpiv[BR];           // 1 if the block row holds a pivot
+    __shared__ int s_composite;
+
+    const int b = blockIdx.x;
+    if (b >= batch) return;
+    const int idx = g.order ? g.order[b] : b;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    const int64_t M64 = g.m[idx], N64 = g.n[idx], ld = g.lda[idx], p64 = g.p[idx];
+    int64_t* const A = g.A[idx];
+    int64_t* const Pv = g.P ? g.P[idx] : nullptr;
+    int64_t* const Qv = g.Q ? g.Q[idx] : nullptr;
+
+    // Argument checks, in the order of the single-matrix entry point.
+    int code = 0;
+    if (M64 < 0 || M64 > 0x3fffffff) code = -1;
+    else if (N64 < 0 || N64 > BQ * 64) code = -2;
+    else if (!A && M64 > 0 && N64 > 0) code = -3;
+    else if (ld < (N64 > 1 ? N64 : 1)) code = -4;
+    else if (p64 < 2 || p64 >= (1 << 26)) code = -5;
+    if (code == 0 && p64 > 3) {
+        // trial division by 2 and the odd numbers up to sqrt(p) < 2^13
+        if (tid == 0) s_composite = (p64 % 2 == 0);
+        __syncthreads();
+        const unsigned pu = (unsigned)p64;
+        for (unsigned d = 3 + 2 * (unsigned)tid; d * d <= pu; d += 2 * BT)
+            if (pu % d == 0) s_composite = 1;
+        __syncthreads();
+        if (s_composite) code = -5;
+    }
+    if (code) {
+        if (tid == 0) {
+            g.info[idx] = code;
+            g.rank[idx] = 0;
+        }
+        return;
+    }
+    const int M = (int)M64, N = (int)N64;
+    if (Pv)
+        for (int c = tid; c < N; c += BT) Pv[c] = c;
+    if (Qv)
+        for (int i = tid; i < M; i += BT) Qv[i] = i;
+    if (M == 0 || N == 0) {
+        if (tid == 0) {
+            g.info[idx] = 0;
+            g.rank[idx] = 0;
+        }
+        return;
+    }
+
+    const double P = (double)p64, PI = 1.0 / P;
+    const double pm1 = P - 1.0;
+    const double kr = floor((9007199254740992.0 - P) / (pm1 * pm1));
+    const int kred = kr > 1e9 ? 1000000000 : (int)kr;  // >= 2 for p < 2^26
+    const int nq = (N + 63) >> 6;
+    for (int c = tid; c < BQ * 64; c += BT) perm[c] = c;
+
+    double x[BK][BQ];
+    auto reduce_all = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < BK; ++k)
+#pragma unroll
+            for (int q = 0; q < BQ; ++q)
+                if (q < nq) x[k][q] = mod_red(x[k][q], P, PI);
+    };
+
+    int t = 0;
+    for (int i0 = 0; i0 < M; i0 += BR) {
+        const int rows = min(BR, M - i0);
+        // U rows and transpositions written by this workgroup are visible
+        __threadfence();
+        __syncthreads();
+
+        // 1. load the block in the current column order
+#pragma unroll
+        for (int k = 0; k < BK; ++k) {
+            const int row = w + BW * k;
+            const int64_t* src = A + (int64_t)(i0 + row) * ld;
+#pragma unroll
+            for (int q = 0; q < BQ; ++q) {
+                const int c = lane + 64 * q;
+                x[k][q] = (row < rows && c < N) ? ld_res(src + perm[c]) : 0.0;
+            }
+        }
+        int cnt = 0;
+
+        // 2. left-looking elimination against U rows 0..t-1
+        Unroll<BQ>::run([&](auto qsc) __attribute__((always_inline)) {
+            constexpr int qs = decltype(qsc)::value;
+            const int s_end = min(t, 64 * (qs + 1));
+            double un[BQ];
+            if (64 * qs < s_end) {
+                const int64_t* urs = A + (int64_t)(64 * qs) * ld;
+#pragma unroll
+                for (int q = qs; q < BQ; ++q) {
+                    const int c = lane + 64 * q;
+                    un[q] = (q < nq && c > 64 * qs && c < N) ? ld_res(urs + c) : 0.0;
+                }
+            }
+            for (int s = 64 * qs; s < s_end; ++s) {
+                if (cnt >= kred) {
+                    reduce_all();
+                    cnt = 0;
+                }
+                const int ls = s & 63;
+                // U row s was fetched one step ahead; fetch U row s + 1 now
+                double u[BQ];
+#pragma unroll
+                for (int q = qs; q < BQ; ++q) u[q] = un[q];
+                if (s + 1 < s_end) {
+                    const int64_t* urs = A + (int64_t)(s + 1) * ld;
+#pragma unroll
+                    for (int q = qs; q < BQ; ++q) {
+                        const int c = lane + 64 * q;
+                        un[q] = (q < nq && c > s + 1 && c < N) ? ld_res(urs + c) : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < BK; ++k) {
+                    if (w + BW * k < rows) {
+                        const double mk = mod_red(readlane_d(x[k][qs], ls), P, PI);
+                        x[k][qs] = (lane == ls) ? mk : x[k][qs];
+#pragma unroll
+                        for (int q = qs; q < BQ; ++q)
+                            if (q < nq) x[k][q] = fma(-mk, u[q], x[k][q]);
+                    }
+                }
+                ++cnt;
+            }
+        });
+
+        // 3. row-by-row base case inside the block
+        int a = 0;
+        Unroll<BQ>::run([&](auto qtc) __attribute__((always_inline)) {
+            constexpr int qt = decltype(qtc)::value;
+            while (a < rows && t < N && (t >> 6) == qt) {
+                if (cnt >= kred) {
+                    reduce_all();
+                    cnt = 0;
+                }
+                const int par = a & 1;
+                const int lt = t & 63;
+                if (w == (a & (BW - 1))) {
+                    const int ka = a / BW;
+                    double rv[BQ];
+#pragma unroll
+                    for (int q = 0; q < BQ; ++q) rv[q] = 0.0;
+#pragma unroll
+                    for (int k = 0; k < BK; ++k)
+                        if (k == ka)
+#pragma unroll
+                            for (int q = 0; q < BQ; ++q)
+                                if (q < nq) rv[q] = mod_red(x[k][q], P, PI);
+                    int j = -1;
+#pragma unroll
+                    for (int q = BQ - 1; q >= qt; --q) {
+                        const int c = lane + 64 * q;
+                        const unsigned long long mk = __ballot(c >= t && c < N && rv[q] != 0.0);
+                        if (mk) j = 64 * q + __ffsll((long long)mk) - 1;
+                    }
+                    double piv = 0.0;
+                    if (j >= 0) {
+                        const int qj = j >> 6, lj = j & 63;
+                        double vj = 0.0;
+#pragma unroll
+                        for (int q = 0; q < BQ; ++q)
+                            if (q == qj) vj = readlane_d(rv[q], lj);
+                        const double vt = readlane_d(rv[qt], lt);
+                        piv = vj;
+                        const double ipiv = mod_inv(piv, P, PI);
+#pragma unroll
+                        for (int q = 0; q < BQ; ++q) {
+                            const int c = lane + 64 * q;
+                            const double val = (c == j) ? vt : rv[q];
+                            urow[par][c] = (c > t && c < N) ? mod_mul(val, ipiv, P, PI) : 0.0;
+                        }
+                    }
+                    if (lane == 0) {
+                        s_j[par] = j;
+                        s_piv[par] = piv;
+                    }
+                }
+                __syncthreads();
+                const int j = s_j[par];
+                if (tid == 0) {
+                    s_rowt[a] = t;
+                    s_rowpiv[a] = (j >= 0);
+                }
+                if (j >= 0) {
+                    const double piv = s_piv[par];
+                    if (j != t) {
+                        // transposition t <-> j in the block rows
+                        const int qj = j >> 6, lj = j & 63;
+#pragma unroll
+                        for (int k = 0; k < BK; ++k) {
+                            double xj = 0.0;
+#pragma unroll
+                            for (int q = 0; q < BQ; ++q)
+                                if (q == qj) xj = x[k][q];
+                            const double vt = readlane_d(x[k][qt], lt);
+                            const double vj = readlane_d(xj, lj);
+                            x[k][qt] = (lane == lt) ? vj : x[k][qt];
+#pragma unroll
+                            for (int q = 0; q < BQ; ++q)
+                                if (q == qj) x[k][q] = (lane == lj) ? vt : x[k][q];
+                        }
+                    }
+                    double u[BQ];
+#pragma unroll
+                    for (int q = qt; q < BQ; ++q) u[q] = (q < nq) ? urow[par][lane + 64 * q] : 0.0;
+#pragma unroll
+                    for (int k = 0; k < BK; ++k) {
+                        const int row = w + BW * k;
+                        if (row > a && row < rows) {
+                            const double mk = mod_red(readlane_d(x[k][qt], lt), P, PI);
+                            x[k][qt] = (lane == lt) ? mk : x[k][qt];
+#pragma unroll
+                            for (int q = qt; q < BQ; ++q)
+                                if (q < nq) x[k][q] = fma(-mk, u[q], x[k][q]);
+                        } else if (row == a) {
+                            x[k][qt] = (lane == lt) ? piv : x[k][qt];
+                        }
+                    }
+                    // U row t into row t of the matrix, positions t+1..N-1
+                    int64_t* urt = A + (int64_t)t * ld;
+                    for (int c = t + 1 + tid; c < N; c += BT) urt[c] = (int64_t)(int)urow[par][c];
+                    if (j != t) {
+                        for (int s = tid; s < t; s += BT) {
+                            int64_t* r = A + (int64_t)s * ld;
+                            const int64_t e = r[t];
+                            r[t] = r[j];
+                            r[j] = e;
+                        }
+                        if (tid == 0) {
+                            const int e = perm[t];
+                            perm[t] = perm[j];
+                            perm[j] = e;
+                        }
+                    }
+                    if (tid == 0) {
+                        if (Pv) Pv[t] = j;
+                        if (Qv) Qv[t] = i0 + a;
+                    }
+                    ++t;
+                    ++cnt;
+                }
+                ++a;
+            }
+        });
+        // rows left once every position holds a pivot are dependent
+        for (int aa = a + tid; aa < rows; aa += BT) {
+            s_rowt[aa] = t;
+            s_rowpiv[aa] = 0;
+        }
+        __syncthreads();
+
+        // 4. C entries (reduced when stored) and echelon zeros, positions <= row
+#pragma unroll
+        for (int k = 0; k < BK; ++k) {
+            const int row = w + BW * k;
+            if (row < rows) {
+                const int i = i0 + row;
+                const int tr = s_rowt[row], pv = s_rowpiv[row];
+                int64_t* dst = A + (int64_t)i * ld;
+#pragma unroll
+                for (int q = 0; q < BQ; ++q) {
+                    const int c = lane + 64 * q;
+                    if (q < nq && c <= i && c < N) {
+                        const bool cpart = (c < tr) || (pv && c == tr);
+                        dst[c] = cpart ? (int64_t)(int)x[k][q] : 0;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // rows r..M-1 carry no U row: zeros after the diagonal
+    const int r = t;
+    for (int i = r + w; i < M; i += BW) {
+        int64_t* dst = A + (int64_t)i * ld;
+        for (int c = i + 1 + lane; c < N; c += 64) dst[c] = 0;
+    }
+    if (tid == 0) {
+        g.info[idx] = 0;
+        g.rank[idx] = r;
+    }
+}
+
+// order[k] = index of the matrix with the k-th largest cost m n min(m, n)
+// (ties by index), by counting: thread i counts the matrices that precede it.
+__global__ __launch_bounds__(256) void batched_order_kernel(const int64_t* m, const int64_t* n,
+                                                            int batch, int* order)
+{
+    __shared__ double cost[256];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    auto cost_of = [&](int e) {
+        const double a = (double)m[e], c = (double)n[e];
+        return (a > 0.0 && c > 0.0) ? a * c * (a < c ? a : c) : 0.0;
+    };
+    const double mine = (i < batch) ? cost_of(i) : 0.0;
+    int pos = 0;
+    for (int j0 = 0; j0 < batch; j0 += 256) {
+        __syncthreads();
+        const int e = j0 + threadIdx.x;
+        cost[threadIdx.x] = (e < batch) ? cost_of(e) : -1.0;
+        __syncthreads();
+        const int lim = min(256, batch - j0);
+        for (int jj = 0; jj < lim; ++jj) {
+            const double o = cost[jj];
+            pos += (o > mine) || (o == mine && j0 + jj < i);
+        }
+    }
+    if (i < batch) order[pos] = i;
+}
+
+}  // namespace
+
+int batched_max_n() { return BQ * 64; }
+
+void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_t* n,
+                        int64_t* const* A, const int64_t* lda, const int64_t* p, int64_t* rank,
+                        int64_t* const* P, int64_t* const* Q, int32_t* info, int* order)
+{
+    if (batch <= 0) return;
+    if (order) {
+        hipLaunchKernelGGL(batched_order_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, m, n,
+                           batch, order);
+        CUP_HIP(hipGetLastError());
+    }
+    BatchDesc g{m, n, A, lda, p, rank, P, Q, info, order};
+    hipLaunchKernelGGL(batched_cup_kernel, dim3(batch), dim3(BT), 0, s, g, batch);
+    CUP_HIP(hipGetLastError());
+}
+
+}  // namespace cup

@@ -130,6 +130,7 @@ def batch_specs(count: int, lo: int, hi: int, seed: int):
     return m, n, r
 
 
-def batch_matrix(i: int, m: int, n: int, r: int, p: int, seed: int) -> np.ndarray:
-    """Matrix i of the batched workload: X.Y mod p with its own sub-seed."""
-    return low_rank(int(m), int(n), int(r), int(p), seed=int(seed) * 1_000_003 + int(i))
+def batch_matrix(i: int, m: int, n: int, r: int, p: int, seed: int, device=None) -> np.ndarray:
+    """Matrix i of the batched workload: X.Y mod p with its own sub-seed
+    (the product on ``device`` when given; the values do not depend on it)."""
+    return low_rank(int(m), int(n), int(r), int(p), seed=int(seed) * 1_000_003 + int(i), device=device)

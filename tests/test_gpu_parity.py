@@ -238,23 +238,92 @@ def test_inverse_i8(cup_lib):
 
 # ------------------------------------------------------------------ batched
 
+def _check_batched(cup_lib, hosts, ps, mats=None, views=None, want_pq=True):
+    mats = mats if mats is not None else [dev(A) for A in hosts]
+    views = views if views is not None else mats
+    rank, info, Ps, Qs = cup_lib.cup_factor_batched(views, ps, want_pq=want_pq)
+    rank, info = host(rank), host(info)
+    for i, A in enumerate(hosts):
+        ref = oracle.cup(A, ps[i])
+        assert info[i] == 0, (i, info[i])
+        assert rank[i] == ref[1], (i, A.shape, ps[i], rank[i], ref[1])
+        if want_pq:
+            assert np.array_equal(host(Ps[i]), ref[2]), (i, "P")
+            assert np.array_equal(host(Qs[i]), ref[3]), (i, "Q")
+        got = host(views[i])
+        if not np.array_equal(got, ref[0]):
+            bad = np.argwhere(got != ref[0])
+            raise AssertionError(f"matrix {i} {A.shape} p={ps[i]}: {len(bad)} entries differ, "
+                                 f"first {bad[:5].tolist()}")
+    return mats
+
+
 def test_batched_small(cup_lib):
+    """The multi-modular workload's recipe at small sizes: m, n ~ U[16, 90]."""
     primes = inputs.largest_primes_below(2 ** 23, 32)
     m, n, r = inputs.batch_specs(40, 16, 90, seed=4)
-    mats, hosts, ps = [], [], []
-    for i in range(40):
-        p = primes[i % 32]
-        A = inputs.batch_matrix(i, m[i], n[i], r[i], p, seed=4)
-        hosts.append(A)
-        mats.append(dev(A))
-        ps.append(p)
+    hosts = [inputs.batch_matrix(i, m[i], n[i], r[i], primes[i % 32], seed=4) for i in range(40)]
+    _check_batched(cup_lib, hosts, [primes[i % 32] for i in range(40)])
+
+
+def test_batched_recipe_full_range(cup_lib):
+    """m, n ~ U[16, 512], ranks ~ U[1, min(m, n)]: several 64-row blocks,
+    positions in every register block, more than 128 pending updates."""
+    primes = inputs.largest_primes_below(2 ** 23, 32)
+    m, n, r = inputs.batch_specs(24, 16, 512, seed=41)
+    hosts = [inputs.batch_matrix(i, m[i], n[i], r[i], primes[i % 32], seed=41) for i in range(24)]
+    _check_batched(cup_lib, hosts, [primes[i % 32] for i in range(24)])
+
+
+def test_batched_shapes_and_primes(cup_lib):
+    """Edge shapes, structured rank profiles, primes from 2 to below 2^26."""
+    cases = []
+    for (mm, nn, rr, p, seed) in [(1, 1, 1, 2, 0), (1, 512, 1, 3, 1), (512, 1, 1, 65521, 2),
+                                  (512, 512, 512, 8388593, 3), (64, 64, 64, 2, 4), (65, 65, 40, 3, 5),
+                                  (300, 500, 7, 33554393, 6), (130, 200, 130, 65521, 7),
+                                  (200, 130, 129, 8388593, 8), (129, 511, 100, 5, 9)]:
+        cases.append((inputs.low_rank(mm, nn, rr, p, seed=seed), p))
+    cases.append((np.zeros((70, 90), np.int64), 65521))
+    cases.append((inputs.staircase(300, 257, 60, 8388593, seed=11)[0], 8388593))
+    cases.append((structured(150, 140, 65521, seed=12), 65521))
+    cases.append((structured(200, 300, 3, seed=13, rank=90), 3))
+    cases.append((structured(512, 512, 8388593, seed=14), 8388593))
+    hosts = [c[0] for c in cases]
+    ps = [c[1] for c in cases]
+    _check_batched(cup_lib, hosts, ps)
+
+
+def test_batched_strided_and_no_pq(cup_lib):
+    """lda > n (the padding is left alone) and P = Q = NULL."""
+    p = 8388593
+    hosts = [inputs.low_rank(100, 70, 50, p, seed=21), inputs.low_rank(260, 300, 260, p, seed=22)]
+    bigs, views = [], []
+    for A in hosts:
+        big = np.full((A.shape[0], A.shape[1] + 9), 7, dtype=np.int64)
+        big[:, :A.shape[1]] = A
+        d = dev(big)
+        bigs.append(d)
+        views.append(d[:, :A.shape[1]])
+    _check_batched(cup_lib, hosts, [p, p], mats=bigs, views=views, want_pq=False)
+    for d, A in zip(bigs, hosts):
+        assert np.all(host(d)[:, A.shape[1]:] == 7)
+
+
+def test_batched_argument_errors(cup_lib):
+    """Per-matrix codes: n > 512 -> -2, composite or out-of-range p -> -5;
+    empty matrices give rank 0 and identity P, Q; the others still run."""
+    A_ok = inputs.low_rank(40, 30, 20, 65521, seed=31)
+    mats = [dev(A_ok), dev(np.zeros((3, 513), np.int64)), dev(A_ok), dev(A_ok),
+            dev(np.zeros((0, 5), np.int64)), dev(np.zeros((4, 0), np.int64))]
+    ps = [65521, 65521, 65519 * 3, 1 << 26, 65521, 65521]
     rank, info, Ps, Qs = cup_lib.cup_factor_batched(mats, ps)
-    rank, info = host(rank), host(info)
-    for i in range(40):
-        ref = oracle.cup(hosts[i], ps[i])
-        assert info[i] == 0 and rank[i] == ref[1]
-        assert np.array_equal(host(Ps[i]), ref[2]) and np.array_equal(host(Qs[i]), ref[3])
-        assert np.array_equal(host(mats[i]), ref[0])
+    info, rank = host(info), host(rank)
+    assert info.tolist() == [0, -2, -5, -5, 0, 0]
+    ref = oracle.cup(A_ok, 65521)
+    assert rank[0] == ref[1] and np.array_equal(host(mats[0]), ref[0])
+    assert rank[4] == 0 and rank[5] == 0
+    assert np.array_equal(host(Ps[4]), np.arange(5)) and np.array_equal(host(Qs[5]), np.arange(4))
+    assert np.array_equal(host(mats[2]), A_ok) and np.array_equal(host(mats[3]), A_ok)
 
 
 # --------------------------------------------------------------- INT8 forms
