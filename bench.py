@@ -12,8 +12,9 @@ Metric: CUP field operations per second with the paper's count for
 classical matrix products, F = 2mnr - (m+n) r^2 + 2/3 r^3 (Section 4.2).
 
 Besides the headline form, the same steps run in the plain FP64-carrier
-form, and once on the rank-6000 variant X(8192x6000) Y(6000x8192) mod p
-(seed 20).  Every timed result is checked against the CPU oracle's SHA-256
+form, once on the rank-6000 variant X(8192x6000) Y(6000x8192) mod p
+(seed 20), and on the multi-modular batch (4096 matrices of up to 512 x 512,
+one prime below 2^23 each, one batched call per step).  Every timed result is checked against the CPU oracle's SHA-256
 digest when tests/golden/full_size_hashes.json has it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -94,6 +95,54 @@ def cpu_baseline(A_host, p, rows):
     return {"value": F / dt, "unit": "field ops/s", "cores": threads, "kind": "oracle",
             "sample": f"CUP of the first {rows} rows ({rows}x{A_host.shape[1]}, rank {r}) of the "
                       f"same GF({p}) matrix; {F:.3e} field ops in {dt:.2f} s"}
+
+
+def batched_variant(cup, torch, inputs, steps, warmup, gold):
+    """The multi-modular batch: 4096 matrices, m, n ~ U[16, 512], r ~ U[1, min(m, n)],
+    matrix i over the (i mod 32)-th largest prime below 2^23 (seed 4), stored back
+    to back; one cup_factor_batched call per step on a fresh copy."""
+    import numpy as np
+    count, seed = 4096, 4
+    primes = inputs.largest_primes_below(2 ** 23, 32)
+    m, n, r = inputs.batch_specs(count, 16, 512, seed=seed)
+    ps = [primes[i % 32] for i in range(count)]
+    fb = cup.FlatBatch(m, n, ps)
+    src = torch.empty(fb.size, dtype=torch.int64, device="cuda")
+    for i in range(count):
+        A = inputs.batch_matrix(i, m[i], n[i], r[i], ps[i], seed=seed, device="cuda")
+        o = int(fb.offsets[i])
+        src[o:o + A.size].copy_(torch.from_numpy(A.reshape(-1)))
+    times, work = [], None
+    for k in range(warmup + steps):
+        work = src.clone()
+        ptrs = fb.pointers(work)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fb.factor(ptrs)
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= warmup:
+            times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    ranks = fb.rank.cpu().numpy()
+    info = fb.info.cpu().numpy()
+    F = float(sum(field_ops(int(a), int(b), int(c)) for a, b, c in zip(m, n, ranks)))
+    flat, P, Q = work.cpu().numpy(), fb.P.cpu().numpy(), fb.Q.cpu().numpy()
+    h = hashlib.sha256()
+    for i in range(count):
+        o, mm, nn = int(fb.offsets[i]), int(m[i]), int(n[i])
+        po, qo = int(fb.p_offsets[i]), int(fb.q_offsets[i])
+        h.update(bytes.fromhex(digest(flat[o:o + mm * nn].reshape(mm, nn), int(ranks[i]),
+                                      P[po:po + nn], Q[qo:qo + mm])))
+    key = "batched_4096_m16to512_p2e23_seed4"
+    if key not in gold:
+        parity = "no oracle digest at this size"
+    else:
+        parity = "oracle digest match" if gold[key]["digest"] == h.hexdigest() else "ORACLE DIGEST MISMATCH"
+    return {"matrices": count, "shapes": "m, n ~ U[16,512], r ~ U[1,min(m,n)], 32 primes < 2^23, seed 4",
+            "ms_per_batch": ms, "field_ops": F, "field_ops_per_s": F / (ms * 1e-3),
+            "errors": int((info != 0).sum()), "parity": parity, "timing": "HIP events, median"}
 
 
 def roofline_of(stats, form, steps):
@@ -188,6 +237,9 @@ def main():
         }
         del B0
     cup.cup_set_form("auto")
+    if not args.no_variants:
+        print("[bench] multi-modular batch (4096 matrices)", file=sys.stderr, flush=True)
+        extra["batched"] = batched_variant(cup, torch, inputs, max(1, args.steps), 1, gold)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -5,15 +5,19 @@
 // The recursion of Algorithm 6 visits rows top-down and, with the pivot rule
 // of its base case (leftmost nonzero in the current column order), the
 // decisions it takes are those of a row-by-row elimination.  The kernel
-// groups rows into blocks of 64 and, for each block:
+// groups rows into blocks of 32 and, for each block:
 //
 //  1. loads the block into registers in the current column order (the
 //     composition of every transposition so far, kept in LDS);
 //  2. eliminates it against the t pivots found before it (left-looking): for
 //     s = 0..t-1 the block's residual at position s is its entry of C, and
-//     the block rows lose C(., s) times U row s, read from the matrix, where
-//     the packed U rows live (rows 0..t-1, positions after the diagonal);
-//  3. runs the row-by-row base case inside the block: the owner wave reduces
+//     the block rows lose C(., s) times U row s; the U rows live in the
+//     matrix (rows 0..t-1, positions after the diagonal) and pass through
+//     LDS in double-buffered chunks of 8, the next chunk in flight while the
+//     current one is used;
+//  3. runs the row-by-row base case inside the block (rows whose residual is
+//     already zero need no step: later pivots leave them zero): the owner
+//     wave reduces
 //     the next row, finds its leftmost nonzero at positions >= t with a
 //     ballot, inverts the pivot and publishes the normalised U row in LDS;
 //     every wave swaps the two positions in its rows and subtracts
@@ -21,12 +25,14 @@
 //     row t of the matrix and the transposition to the U rows above;
 //  4. writes the block's C entries (and the echelon zeros) back.
 //
-// Updates are not reduced one by one: a residual absorbs
-// floor((2^53 - p) / (p - 1)^2) products of canonical residues before the
-// block is reduced again, and only the values that are used (a pivot row, a
-// multiplier) are reduced when they are read.
+// Updates are not reduced one by one.  A multiplier is reduced lazily, to
+// x - floor(x / p) p in [-p, 2p), and a residual absorbs
+// floor((2^53 - p) / (2p (p - 1))) products of such a multiplier with a
+// canonical U entry before the block is reduced again.  A position that has
+// become an entry of C is never updated again, so the C entries are the
+// residuals themselves, reduced once when the block is written back.
 //
-// Layout: 512 threads = 8 waves; wave w owns block rows w + 8k (k < 8);
+// Layout: 1024 threads = 16 waves; wave w owns block rows w + 16k (k < 2);
 // lane l holds positions l + 64q (q < 8) of those rows, so n <= 512.
 #include <type_traits>
 
@@ -36,11 +42,23 @@ namespace cup {
 
 namespace {
 
-constexpr int BW = 8;          // waves per workgroup
+constexpr int BW = 16;         // waves per workgroup
 constexpr int BT = 64 * BW;    // threads per workgroup
-constexpr int BR = 64;         // rows per block
+constexpr int BR = 32;         // rows per block
 constexpr int BK = BR / BW;    // block rows per wave
 constexpr int BQ = 8;          // position registers per lane (n <= 64 BQ)
+constexpr int CH = 8;          // U rows per LDS chunk of the left-looking phase
+constexpr int NP = 64 * BQ;    // positions
+constexpr int SPT = CH * NP / BT;  // staged values per thread
+
+static_assert(BT % NP == 0 && CH % (BT / NP) == 0, "threads tile the staged chunk");
+
+// x - floor(x / p) p, in [-p, 2p) for |x| < 2^53 (the quotient from the
+// rounded reciprocal is off by at most one; the fma is exact).
+__device__ __forceinline__ double red_lazy(double x, double p, double pinv)
+{
+    return fma(-floor(x * pinv), p, x);
+}
 
 __device__ __forceinline__ double readlane_d(double v, int l)
 {
@@ -84,10 +102,11 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
     __shared__ int perm[BQ * 64];          // position -> original column
     __shared__ double urow[2][BQ * 64];    // published U rows (zeros up to the pivot)
     __shared__ int s_j[2];
-    __shared__ double s_piv[2];
     __shared__ int s_rowt[BR];             // pivots found before each block row
     __shared__ int s_rowpiv[BR];           // 1 if the block row holds a pivot
     __shared__ int s_composite;
+    __shared__ int s_nz[BR];               // block row has a nonzero residual
+    __shared__ double ush[2][CH][BQ * 64]; // staged U rows (zeros up to the diagonal)
 
     const int b = blockIdx.x;
     if (b >= batch) return;
@@ -138,11 +157,10 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
     }
 
     const double P = (double)p64, PI = 1.0 / P;
-    const double pm1 = P - 1.0;
-    const double kr = floor((9007199254740992.0 - P) / (pm1 * pm1));
-    const int kred = kr > 1e9 ? 1000000000 : (int)kr;  // >= 2 for p < 2^26
+    const double kr = floor((9007199254740992.0 - P) / (2.0 * P * (P - 1.0)));
+    const int kred = kr > 1e9 ? 1000000000 : (int)kr;  // >= 1 for p < 2^26
     const int nq = (N + 63) >> 6;
-    for (int c = tid; c < BQ * 64; c += BT) perm[c] = c;
+    for (int c = tid; c < NP; c += BT) perm[c] = c;
 
     double x[BK][BQ];
     auto reduce_all = [&]() __attribute__((always_inline)) {
@@ -173,56 +191,81 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
         }
         int cnt = 0;
 
-        // 2. left-looking elimination against U rows 0..t-1
+        // 2. left-looking elimination against U rows 0..t-1.  Thread tid
+        // stages position tid % NP of SPT consecutive rows of a chunk.
+        const int nch = (t + CH - 1) / CH;
+        const int spos = tid % NP, se0 = (tid / NP) * SPT;
+        int stg[SPT];
+        auto fetch = [&](int ch) __attribute__((always_inline)) {
+#pragma unroll
+            for (int e = 0; e < SPT; ++e) {
+                const int sr = ch * CH + se0 + e;
+                stg[e] = (sr < t && spos > sr && spos < N) ? (int)A[(int64_t)sr * ld + spos] : 0;
+            }
+        };
+        if (nch > 0) fetch(0);
+        int ch = 0;
         Unroll<BQ>::run([&](auto qsc) __attribute__((always_inline)) {
             constexpr int qs = decltype(qsc)::value;
-            const int s_end = min(t, 64 * (qs + 1));
-            double un[BQ];
-            if (64 * qs < s_end) {
-                const int64_t* urs = A + (int64_t)(64 * qs) * ld;
+            for (; ch < nch && ch * CH < 64 * (qs + 1); ++ch) {
+                const int buf = ch & 1;
 #pragma unroll
-                for (int q = qs; q < BQ; ++q) {
-                    const int c = lane + 64 * q;
-                    un[q] = (q < nq && c > 64 * qs && c < N) ? ld_res(urs + c) : 0.0;
-                }
-            }
-            for (int s = 64 * qs; s < s_end; ++s) {
-                if (cnt >= kred) {
-                    reduce_all();
-                    cnt = 0;
-                }
-                const int ls = s & 63;
-                // U row s was fetched one step ahead; fetch U row s + 1 now
-                double u[BQ];
-#pragma unroll
-                for (int q = qs; q < BQ; ++q) u[q] = un[q];
-                if (s + 1 < s_end) {
-                    const int64_t* urs = A + (int64_t)(s + 1) * ld;
-#pragma unroll
-                    for (int q = qs; q < BQ; ++q) {
-                        const int c = lane + 64 * q;
-                        un[q] = (q < nq && c > s + 1 && c < N) ? ld_res(urs + c) : 0.0;
+                for (int e = 0; e < SPT; ++e) ush[buf][se0 + e][spos] = (double)stg[e];
+                __syncthreads();
+                if (ch + 1 < nch) fetch(ch + 1);
+                const int s0 = ch * CH, s1 = min(t, s0 + CH);
+                for (int s = s0; s < s1; ++s) {
+                    if (cnt >= kred) {
+                        reduce_all();
+                        cnt = 0;
                     }
-                }
+                    const int ls = s & 63;
+                    double u[BQ];
 #pragma unroll
-                for (int k = 0; k < BK; ++k) {
-                    if (w + BW * k < rows) {
-                        const double mk = mod_red(readlane_d(x[k][qs], ls), P, PI);
-                        x[k][qs] = (lane == ls) ? mk : x[k][qs];
+                    for (int q = qs; q < BQ; ++q) u[q] = (q < nq) ? ush[buf][s - s0][lane + 64 * q] : 0.0;
 #pragma unroll
-                        for (int q = qs; q < BQ; ++q)
-                            if (q < nq) x[k][q] = fma(-mk, u[q], x[k][q]);
+                    for (int k = 0; k < BK; ++k) {
+                        if (w + BW * k < rows) {
+                            const double mk = red_lazy(readlane_d(x[k][qs], ls), P, PI);
+#pragma unroll
+                            for (int q = qs; q < BQ; ++q)
+                                if (q < nq) x[k][q] = fma(-mk, u[q], x[k][q]);
+                        }
                     }
+                    ++cnt;
                 }
-                ++cnt;
             }
         });
+
+        // rows whose residual at positions >= t is zero need no base-case step
+        reduce_all();
+        cnt = 0;
+#pragma unroll
+        for (int k = 0; k < BK; ++k) {
+            bool nz = false;
+#pragma unroll
+            for (int q = 0; q < BQ; ++q) {
+                const int c = lane + 64 * q;
+                nz |= __ballot(q < nq && c >= t && c < N && x[k][q] != 0.0) != 0ull;
+            }
+            const int row = w + BW * k;
+            if (lane == 0) s_nz[row] = nz && row < rows;
+        }
+        __syncthreads();
 
         // 3. row-by-row base case inside the block
         int a = 0;
         Unroll<BQ>::run([&](auto qtc) __attribute__((always_inline)) {
             constexpr int qt = decltype(qtc)::value;
             while (a < rows && t < N && (t >> 6) == qt) {
+                if (!s_nz[a]) {
+                    if (tid == 0) {
+                        s_rowt[a] = t;
+                        s_rowpiv[a] = 0;
+                    }
+                    ++a;
+                    continue;
+                }
                 if (cnt >= kred) {
                     reduce_all();
                     cnt = 0;
@@ -230,16 +273,22 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                 const int par = a & 1;
                 const int lt = t & 63;
                 if (w == (a & (BW - 1))) {
+                    // the owner wave: row a, positions >= 64 qt (the rest are < t)
+                    // row a = sum_k [k == a / BW] x[k]: products with 0 and 1 are
+                    // exact, and a select between register-array elements could
+                    // turn into an indexed access that keeps x out of registers
                     const int ka = a / BW;
+                    double ek[BK];
+#pragma unroll
+                    for (int k = 0; k < BK; ++k) ek[k] = (ka == k) ? 1.0 : 0.0;
                     double rv[BQ];
 #pragma unroll
-                    for (int q = 0; q < BQ; ++q) rv[q] = 0.0;
+                    for (int q = qt; q < BQ; ++q) {
+                        double v = x[0][q] * ek[0];
 #pragma unroll
-                    for (int k = 0; k < BK; ++k)
-                        if (k == ka)
-#pragma unroll
-                            for (int q = 0; q < BQ; ++q)
-                                if (q < nq) rv[q] = mod_red(x[k][q], P, PI);
+                        for (int k = 1; k < BK; ++k) v = fma(x[k][q], ek[k], v);
+                        rv[q] = (q < nq) ? mod_red(v, P, PI) : 0.0;
+                    }
                     int j = -1;
 #pragma unroll
                     for (int q = BQ - 1; q >= qt; --q) {
@@ -247,27 +296,25 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                         const unsigned long long mk = __ballot(c >= t && c < N && rv[q] != 0.0);
                         if (mk) j = 64 * q + __ffsll((long long)mk) - 1;
                     }
-                    double piv = 0.0;
                     if (j >= 0) {
                         const int qj = j >> 6, lj = j & 63;
-                        double vj = 0.0;
+                        double piv = 0.0;
 #pragma unroll
-                        for (int q = 0; q < BQ; ++q)
-                            if (q == qj) vj = readlane_d(rv[q], lj);
+                        for (int q = qt; q < BQ; ++q) piv = (q == qj) ? readlane_d(rv[q], lj) : piv;
                         const double vt = readlane_d(rv[qt], lt);
-                        piv = vj;
                         const double ipiv = mod_inv(piv, P, PI);
 #pragma unroll
                         for (int q = 0; q < BQ; ++q) {
                             const int c = lane + 64 * q;
-                            const double val = (c == j) ? vt : rv[q];
-                            urow[par][c] = (c > t && c < N) ? mod_mul(val, ipiv, P, PI) : 0.0;
+                            if (q < qt) {
+                                urow[par][c] = 0.0;
+                            } else {
+                                const double val = (c == j) ? vt : rv[q];
+                                urow[par][c] = (c > t && c < N) ? mod_mul(val, ipiv, P, PI) : 0.0;
+                            }
                         }
                     }
-                    if (lane == 0) {
-                        s_j[par] = j;
-                        s_piv[par] = piv;
-                    }
+                    if (lane == 0) s_j[par] = j;
                 }
                 __syncthreads();
                 const int j = s_j[par];
@@ -276,22 +323,18 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                     s_rowpiv[a] = (j >= 0);
                 }
                 if (j >= 0) {
-                    const double piv = s_piv[par];
                     if (j != t) {
-                        // transposition t <-> j in the block rows
+                        // transposition t <-> j (j > t) in the block rows
                         const int qj = j >> 6, lj = j & 63;
 #pragma unroll
                         for (int k = 0; k < BK; ++k) {
-                            double xj = 0.0;
-#pragma unroll
-                            for (int q = 0; q < BQ; ++q)
-                                if (q == qj) xj = x[k][q];
                             const double vt = readlane_d(x[k][qt], lt);
-                            const double vj = readlane_d(xj, lj);
+                            double vj = 0.0;
+#pragma unroll
+                            for (int q = qt; q < BQ; ++q) vj = (q == qj) ? readlane_d(x[k][q], lj) : vj;
                             x[k][qt] = (lane == lt) ? vj : x[k][qt];
 #pragma unroll
-                            for (int q = 0; q < BQ; ++q)
-                                if (q == qj) x[k][q] = (lane == lj) ? vt : x[k][q];
+                            for (int q = qt; q < BQ; ++q) x[k][q] = (q == qj && lane == lj) ? vt : x[k][q];
                         }
                     }
                     double u[BQ];
@@ -301,13 +344,10 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                     for (int k = 0; k < BK; ++k) {
                         const int row = w + BW * k;
                         if (row > a && row < rows) {
-                            const double mk = mod_red(readlane_d(x[k][qt], lt), P, PI);
-                            x[k][qt] = (lane == lt) ? mk : x[k][qt];
+                            const double mk = red_lazy(readlane_d(x[k][qt], lt), P, PI);
 #pragma unroll
                             for (int q = qt; q < BQ; ++q)
                                 if (q < nq) x[k][q] = fma(-mk, u[q], x[k][q]);
-                        } else if (row == a) {
-                            x[k][qt] = (lane == lt) ? piv : x[k][qt];
                         }
                     }
                     // U row t into row t of the matrix, positions t+1..N-1
@@ -343,7 +383,8 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
         }
         __syncthreads();
 
-        // 4. C entries (reduced when stored) and echelon zeros, positions <= row
+        // 4. C entries and echelon zeros, positions <= row
+        reduce_all();
 #pragma unroll
         for (int k = 0; k < BK; ++k) {
             const int row = w + BW * k;

@@ -200,6 +200,49 @@ def cup_factor_batched(mats: list[torch.Tensor], primes, want_pq: bool = True):
     return rank, info, Ps, Qs
 
 
+class FlatBatch:
+    """A batch stored back to back in one int64 device buffer (matrix i is
+    m[i] x n[i] with lda = n[i] at element offset ``offsets[i]``), with its
+    device descriptors built once, so that a call only passes pointers."""
+
+    def __init__(self, m, n, primes, device="cuda"):
+        import numpy as np
+        self.m = np.asarray(m, dtype=np.int64)
+        self.n = np.asarray(n, dtype=np.int64)
+        self.count = len(self.m)
+        sizes = self.m * self.n
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        self.size = int(sizes.sum())
+        dev = torch.device(device)
+        self.dm = torch.from_numpy(self.m).to(dev)
+        self.dn = torch.from_numpy(self.n).to(dev)
+        self.dp = torch.tensor([int(q) for q in primes], dtype=torch.int64, device=dev)
+        self.dbyte_offs = torch.from_numpy(self.offsets * 8).to(dev)
+        self.P = torch.empty(int(self.n.sum()), dtype=torch.int64, device=dev)
+        self.Q = torch.empty(int(self.m.sum()), dtype=torch.int64, device=dev)
+        self.p_offsets = np.concatenate([[0], np.cumsum(self.n)[:-1]]).astype(np.int64)
+        self.q_offsets = np.concatenate([[0], np.cumsum(self.m)[:-1]]).astype(np.int64)
+        self.pP = self.P.data_ptr() + torch.from_numpy(self.p_offsets * 8).to(dev)
+        self.pQ = self.Q.data_ptr() + torch.from_numpy(self.q_offsets * 8).to(dev)
+        self.rank = torch.zeros(self.count, dtype=torch.int64, device=dev)
+        self.info = torch.zeros(self.count, dtype=torch.int32, device=dev)
+
+    def pointers(self, flat: torch.Tensor) -> torch.Tensor:
+        """Device array of the matrices' addresses inside ``flat``."""
+        if flat.dtype != torch.int64 or flat.numel() < self.size or not flat.is_contiguous():
+            raise TypeError("flat must be a contiguous int64 device buffer holding the batch")
+        return flat.data_ptr() + self.dbyte_offs
+
+    def factor(self, ptrs: torch.Tensor) -> None:
+        """cup_factor_batched over the matrices at ``ptrs`` (asynchronous)."""
+        _sync_stream()
+        rc = load().cup_factor_batched(self.count, _vec(self.dm), _vec(self.dn), _vec(ptrs),
+                                       _vec(self.dn), _vec(self.dp), _vec(self.rank),
+                                       _vec(self.pP), _vec(self.pQ), _vec(self.info))
+        if rc < 0:
+            raise CupError(rc, "cup_factor_batched")
+
+
 def cup_ffgemm(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, p: int, alpha: int = -1):
     """C <- C + alpha A B mod p in place (int64 or int8 device matrices)."""
     dtype = C.dtype

@@ -7,7 +7,8 @@ parity tests and the benchmark compare against.  Run from the repo root:
     python tests/golden/make_full_size_hashes.py [name ...]
 
 Digest of a CUP result: sha256(packed int64 bytes | P int64 | Q int64 |
-rank int64); of an inverse: sha256(inverse int64 bytes).
+rank int64); of an inverse: sha256(inverse int64 bytes); of a batch:
+sha256 over the concatenated binary digests of its matrices, in order.
 """
 from __future__ import annotations
 
@@ -60,7 +61,20 @@ def workloads():
         "rref_32768x8192_staircase2048_p65521_seed5": lambda: ("rref", inputs.staircase(32768, 8192, 2048, p16, seed=5)[0], p16),
         "cup_16384_rank12000_p127_seed3": lambda: ("cup", inputs.low_rank(16384, 16384, 12000, 127, seed=3), 127),
         "inverse_8192_p127_seed30": lambda: ("inverse", None, 127),
+        "batched_4096_m16to512_p2e23_seed4": lambda: ("batched", None, None),
     }
+
+
+BATCH = {"count": 4096, "lo": 16, "hi": 512, "seed": 4, "primes_below": 2 ** 23, "nprimes": 32}
+
+
+def batched_workload():
+    """The multi-modular batch: m, n ~ U[16, 512], r ~ U[1, min(m, n)], matrix i
+    over the (i mod 32)-th largest prime below 2^23."""
+    primes = inputs.largest_primes_below(BATCH["primes_below"], BATCH["nprimes"])
+    m, n, r = inputs.batch_specs(BATCH["count"], BATCH["lo"], BATCH["hi"], seed=BATCH["seed"])
+    ps = [primes[i % BATCH["nprimes"]] for i in range(BATCH["count"])]
+    return m, n, r, ps
 
 
 def main(names):
@@ -77,6 +91,17 @@ def main(names):
         elif kind == "rref":
             O, r, P, Q = oracle.rref_packed(A, p)
             entry = {"digest": cup_digest(O, r, P, Q), "rank": r}
+        elif kind == "batched":
+            m, n, rr, ps = batched_workload()
+            h = hashlib.sha256()
+            rank_sum, F = 0, 0.0
+            for i in range(len(m)):
+                B = inputs.batch_matrix(i, m[i], n[i], rr[i], ps[i], seed=BATCH["seed"])
+                packed, r, P, Q = oracle.cup(B, ps[i])
+                h.update(bytes.fromhex(cup_digest(packed, r, P, Q)))
+                rank_sum += int(r)
+                F += 2.0 * m[i] * n[i] * r - (m[i] + n[i]) * r * r + 2.0 * r ** 3 / 3.0
+            entry = {"digest": h.hexdigest(), "rank_sum": rank_sum, "field_ops": F}
         else:
             seed, A, X = first_nonsingular(8192, p, 30)
             entry = {"digest": mat_digest(X), "seed": seed}

@@ -105,3 +105,33 @@ def test_config5_staircase_rref(cup_lib):
     g = GOLD["rref_32768x8192_staircase2048_p65521_seed5"]
     assert r == g["rank"] == 2048
     assert cup_digest(d.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()) == g["digest"]
+
+
+def test_batched_multimodular_4096(cup_lib):
+    """4096 matrices, m, n ~ U[16, 512], r ~ U[1, min(m, n)], one prime below
+    2^23 each (seed 4), factored by one batched call."""
+    g = GOLD["batched_4096_m16to512_p2e23_seed4"]
+    count, seed = 4096, 4
+    primes = inputs.largest_primes_below(2 ** 23, 32)
+    m, n, r = inputs.batch_specs(count, 16, 512, seed=seed)
+    ps = [primes[i % 32] for i in range(count)]
+    fb = cup_lib.FlatBatch(m, n, ps)
+    flat = torch.empty(fb.size, dtype=torch.int64, device="cuda")
+    for i in range(count):
+        A = inputs.batch_matrix(i, m[i], n[i], r[i], ps[i], seed=seed, device="cuda")
+        o = int(fb.offsets[i])
+        flat[o:o + A.size].copy_(torch.from_numpy(A.reshape(-1)))
+    fb.factor(fb.pointers(flat))
+    torch.cuda.synchronize()
+    info = fb.info.cpu().numpy()
+    ranks = fb.rank.cpu().numpy()
+    assert not info.any()
+    assert int(ranks.sum()) == g["rank_sum"]
+    X, P, Q = flat.cpu().numpy(), fb.P.cpu().numpy(), fb.Q.cpu().numpy()
+    h = hashlib.sha256()
+    for i in range(count):
+        o, mm, nn = int(fb.offsets[i]), int(m[i]), int(n[i])
+        po, qo = int(fb.p_offsets[i]), int(fb.q_offsets[i])
+        h.update(bytes.fromhex(cup_digest(X[o:o + mm * nn].reshape(mm, nn), int(ranks[i]),
+                                          P[po:po + nn], Q[qo:qo + mm])))
+    assert h.hexdigest() == g["digest"]
