@@ -17,13 +17,15 @@
 //     current one is used;
 //  3. runs the row-by-row base case inside the block (rows whose residual is
 //     already zero need no step: later pivots leave them zero): the owner
-//     wave reduces
-//     the next row, finds its leftmost nonzero at positions >= t with a
-//     ballot, inverts the pivot and publishes the normalised U row in LDS;
-//     every wave swaps the two positions in its rows and subtracts
-//     residual(i, t) times the U row from its later rows; the U row goes to
-//     row t of the matrix and the transposition to the U rows above;
-//  4. writes the block's C entries (and the echelon zeros) back.
+//     wave reduces the next row, finds its leftmost nonzero at positions >= t
+//     with a ballot, inverts the pivot and publishes the normalised U row in
+//     LDS; every wave swaps the two positions in its rows and subtracts
+//     residual(i, t) times the U row from its later rows.  A step touches no
+//     global memory: the block's U rows, transpositions and profile entries
+//     collect in LDS;
+//  4. writes the block's C entries (and the echelon zeros) and its U rows,
+//     applies its transpositions to the U rows of earlier blocks, and
+//     appends its entries of P and Q.
 //
 // Updates are not reduced one by one.  A multiplier is reduced lazily, to
 // x - floor(x / p) p in [-p, 2p), and a residual absorbs
@@ -32,7 +34,7 @@
 // become an entry of C is never updated again, so the C entries are the
 // residuals themselves, reduced once when the block is written back.
 //
-// Layout: 1024 threads = 16 waves; wave w owns block rows w + 16k (k < 2);
+// Layout: 512 threads = 8 waves; wave w owns block rows w + 8k (k < 4);
 // lane l holds positions l + 64q (q < 8) of those rows, so n <= 512.
 #include <type_traits>
 
@@ -42,7 +44,7 @@ namespace cup {
 
 namespace {
 
-constexpr int BW = 16;         // waves per workgroup
+constexpr int BW = 8;          // waves per workgroup
 constexpr int BT = 64 * BW;    // threads per workgroup
 constexpr int BR = 32;         // rows per block
 constexpr int BK = BR / BW;    // block rows per wave
@@ -65,6 +67,20 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
+}
+
+// Inverse of a nonzero residue, a^(p-2) (Fermat).  For p < 2^25 the chain
+// keeps its values in [-p, 2p) (products below 4p^2 < 2^53) and reduces
+// fully once at the end; larger p take the exact chain.
+__device__ __forceinline__ double inv_pivot(double a, double p, double pinv)
+{
+    if (p >= 33554432.0) return mod_inv(a, p, pinv);
+    double r = 1.0, b = a;
+    for (int64_t e = (int64_t)p - 2; e > 0; e >>= 1) {
+        if (e & 1) r = red_lazy(r * b, p, pinv);
+        b = red_lazy(b * b, p, pinv);
+    }
+    return mod_red(r, p, pinv);
 }
 
 // f(std::integral_constant<int, 0>), ..., f(..., Q - 1): the index reaches
@@ -107,6 +123,9 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
     __shared__ int s_composite;
     __shared__ int s_nz[BR];               // block row has a nonzero residual
     __shared__ double ush[2][CH][BQ * 64]; // staged U rows (zeros up to the diagonal)
+    __shared__ int ublk[BR][BQ * 64];      // U rows found in the current block
+    __shared__ int s_tj[BR];               // their transpositions t <-> s_tj
+    __shared__ int s_ti[BR];               // and their rows (entries of Q)
 
     const int b = blockIdx.x;
     if (b >= batch) return;
@@ -174,19 +193,22 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
     int t = 0;
     for (int i0 = 0; i0 < M; i0 += BR) {
         const int rows = min(BR, M - i0);
-        // U rows and transpositions written by this workgroup are visible
-        __threadfence();
+        const int t0 = t;  // pivots before the block
+        // the previous block's global writes are visible to the workgroup
         __syncthreads();
 
         // 1. load the block in the current column order
 #pragma unroll
         for (int k = 0; k < BK; ++k) {
+            // every address valid (row and position clamped), so the loads
+            // of the block issue together
             const int row = w + BW * k;
-            const int64_t* src = A + (int64_t)(i0 + row) * ld;
+            const int64_t* src = A + (int64_t)(i0 + min(row, rows - 1)) * ld;
 #pragma unroll
             for (int q = 0; q < BQ; ++q) {
                 const int c = lane + 64 * q;
-                x[k][q] = (row < rows && c < N) ? ld_res(src + perm[c]) : 0.0;
+                const double v = ld_res(src + perm[min(c, N - 1)]);
+                x[k][q] = (row < rows && c < N) ? v : 0.0;
             }
         }
         int cnt = 0;
@@ -200,7 +222,8 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
 #pragma unroll
             for (int e = 0; e < SPT; ++e) {
                 const int sr = ch * CH + se0 + e;
-                stg[e] = (sr < t && spos > sr && spos < N) ? (int)A[(int64_t)sr * ld + spos] : 0;
+                const int v = (int)A[(int64_t)min(sr, t - 1) * ld + min(spos, N - 1)];
+                stg[e] = (sr < t && spos > sr && spos < N) ? v : 0;
             }
         };
         if (nch > 0) fetch(0);
@@ -302,7 +325,8 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
 #pragma unroll
                         for (int q = qt; q < BQ; ++q) piv = (q == qj) ? readlane_d(rv[q], lj) : piv;
                         const double vt = readlane_d(rv[qt], lt);
-                        const double ipiv = mod_inv(piv, P, PI);
+                        const double ipiv = inv_pivot(piv, P, PI);
+                        int* ub = ublk[t - t0];
 #pragma unroll
                         for (int q = 0; q < BQ; ++q) {
                             const int c = lane + 64 * q;
@@ -310,7 +334,9 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                                 urow[par][c] = 0.0;
                             } else {
                                 const double val = (c == j) ? vt : rv[q];
-                                urow[par][c] = (c > t && c < N) ? mod_mul(val, ipiv, P, PI) : 0.0;
+                                const double u = (c > t && c < N) ? mod_mul(val, ipiv, P, PI) : 0.0;
+                                urow[par][c] = u;
+                                ub[c] = (int)u;
                             }
                         }
                     }
@@ -350,15 +376,12 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                                 if (q < nq) x[k][q] = fma(-mk, u[q], x[k][q]);
                         }
                     }
-                    // U row t into row t of the matrix, positions t+1..N-1
-                    int64_t* urt = A + (int64_t)t * ld;
-                    for (int c = t + 1 + tid; c < N; c += BT) urt[c] = (int64_t)(int)urow[par][c];
                     if (j != t) {
-                        for (int s = tid; s < t; s += BT) {
-                            int64_t* r = A + (int64_t)s * ld;
-                            const int64_t e = r[t];
-                            r[t] = r[j];
-                            r[j] = e;
+                        // the block's earlier U rows (LDS) and the column order
+                        for (int d = tid; d < t - t0; d += BT) {
+                            const int e = ublk[d][t];
+                            ublk[d][t] = ublk[d][j];
+                            ublk[d][j] = e;
                         }
                         if (tid == 0) {
                             const int e = perm[t];
@@ -367,8 +390,8 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                         }
                     }
                     if (tid == 0) {
-                        if (Pv) Pv[t] = j;
-                        if (Qv) Qv[t] = i0 + a;
+                        s_tj[t - t0] = j;
+                        s_ti[t - t0] = i0 + a;
                     }
                     ++t;
                     ++cnt;
@@ -383,7 +406,30 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
         }
         __syncthreads();
 
-        // 4. C entries and echelon zeros, positions <= row
+        // 4. the block's transpositions on the U rows of earlier blocks (one
+        // thread per row, in order), its U rows, and its entries of P and Q
+        const int nd = t - t0;
+        for (int sr = tid; sr < t0; sr += BT) {
+            int64_t* ur = A + (int64_t)sr * ld;
+            for (int d = 0; d < nd; ++d) {
+                const int tt = t0 + d, jj = s_tj[d];
+                if (jj != tt) {
+                    const int64_t e = ur[tt];
+                    ur[tt] = ur[jj];
+                    ur[jj] = e;
+                }
+            }
+        }
+        for (int d = 0; d < nd; ++d) {
+            const int tt = t0 + d;
+            int64_t* ur = A + (int64_t)tt * ld;
+            for (int c = tt + 1 + tid; c < N; c += BT) ur[c] = ublk[d][c];
+        }
+        if (tid < nd) {
+            if (Pv) Pv[t0 + tid] = s_tj[tid];
+            if (Qv) Qv[t0 + tid] = s_ti[tid];
+        }
+        // C entries and echelon zeros, positions <= row
         reduce_all();
 #pragma unroll
         for (int k = 0; k < BK; ++k) {
