@@ -35,7 +35,12 @@
 // residuals themselves, reduced once when the block is written back.
 //
 // Layout: 512 threads = 8 waves; wave w owns block rows w + 8k (k < 4);
-// lane l holds positions l + 64q (q < 8) of those rows, so n <= 512.
+// lane l holds positions l + 64q (q < BQ) of those rows.  Three widths are
+// compiled (BQ = 2, 4, 8: n <= 128, 256, 512) so that a narrow matrix pays
+// for its own width only and leaves room for more workgroups per CU.  Inner
+// loops run over every register of the width without per-register or
+// per-row branches: positions past n and rows past m hold zeros, which the
+// updates leave zero.
 #include <type_traits>
 
 #include "modarith.h"
@@ -48,12 +53,8 @@ constexpr int BW = 8;          // waves per workgroup
 constexpr int BT = 64 * BW;    // threads per workgroup
 constexpr int BR = 32;         // rows per block
 constexpr int BK = BR / BW;    // block rows per wave
-constexpr int BQ = 8;          // position registers per lane (n <= 64 BQ)
+constexpr int BQMAX = 8;       // position registers per lane at most (n <= 512)
 constexpr int CH = 8;          // U rows per LDS chunk of the left-looking phase
-constexpr int NP = 64 * BQ;    // positions
-constexpr int SPT = CH * NP / BT;  // staged values per thread
-
-static_assert(BT % NP == 0 && CH % (BT / NP) == 0, "threads tile the staged chunk");
 
 // x - floor(x / p) p, in [-p, 2p) for |x| < 2^53 (the quotient from the
 // rounded reciprocal is off by at most one; the fma is exact).
@@ -113,17 +114,24 @@ struct BatchDesc {
     const int* order;  // processing order (largest first), or null
 };
 
-__global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
+// BQ position registers per lane (n <= 64 BQ).  The kernel takes the
+// matrices with nlo < n <= nhi and leaves the others to its siblings.
+template <int BQ>
+__global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch, int64_t nlo,
+                                                         int64_t nhi)
 {
-    __shared__ int perm[BQ * 64];          // position -> original column
-    __shared__ double urow[2][BQ * 64];    // published U rows (zeros up to the pivot)
+    constexpr int NP = 64 * BQ;        // positions
+    constexpr int SPT = CH * NP / BT;  // staged values per thread
+    static_assert(BT % NP == 0 && CH % (BT / NP) == 0, "threads tile the staged chunk");
+    __shared__ int perm[NP];               // position -> original column
+    __shared__ double urow[2][NP];         // published U rows (zeros up to the pivot)
     __shared__ int s_j[2];
     __shared__ int s_rowt[BR];             // pivots found before each block row
     __shared__ int s_rowpiv[BR];           // 1 if the block row holds a pivot
     __shared__ int s_composite;
     __shared__ int s_nz[BR];               // block row has a nonzero residual
-    __shared__ double ush[2][CH][BQ * 64]; // staged U rows (zeros up to the diagonal)
-    __shared__ int ublk[BR][BQ * 64];      // U rows found in the current block
+    __shared__ double ush[2][CH][NP];      // staged U rows (zeros up to the diagonal)
+    __shared__ int ublk[BR][NP];           // U rows found in the current block
     __shared__ int s_tj[BR];               // their transpositions t <-> s_tj
     __shared__ int s_ti[BR];               // and their rows (entries of Q)
 
@@ -133,7 +141,9 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    const int64_t M64 = g.m[idx], N64 = g.n[idx], ld = g.lda[idx], p64 = g.p[idx];
+    const int64_t N64 = g.n[idx];
+    if (N64 <= nlo || N64 > nhi) return;
+    const int64_t M64 = g.m[idx], ld = g.lda[idx], p64 = g.p[idx];
     int64_t* const A = g.A[idx];
     int64_t* const Pv = g.P ? g.P[idx] : nullptr;
     int64_t* const Qv = g.Q ? g.Q[idx] : nullptr;
@@ -245,15 +255,12 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                     const int ls = s & 63;
                     double u[BQ];
 #pragma unroll
-                    for (int q = qs; q < BQ; ++q) u[q] = (q < nq) ? ush[buf][s - s0][lane + 64 * q] : 0.0;
+                    for (int q = qs; q < BQ; ++q) u[q] = ush[buf][s - s0][lane + 64 * q];
 #pragma unroll
                     for (int k = 0; k < BK; ++k) {
-                        if (w + BW * k < rows) {
-                            const double mk = red_lazy(readlane_d(x[k][qs], ls), P, PI);
+                        const double mk = red_lazy(readlane_d(x[k][qs], ls), P, PI);
 #pragma unroll
-                            for (int q = qs; q < BQ; ++q)
-                                if (q < nq) x[k][q] = fma(-mk, u[q], x[k][q]);
-                        }
+                        for (int q = qs; q < BQ; ++q) x[k][q] = fma(-mk, u[q], x[k][q]);
                     }
                     ++cnt;
                 }
@@ -365,15 +372,14 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch)
                     }
                     double u[BQ];
 #pragma unroll
-                    for (int q = qt; q < BQ; ++q) u[q] = (q < nq) ? urow[par][lane + 64 * q] : 0.0;
+                    for (int q = qt; q < BQ; ++q) u[q] = urow[par][lane + 64 * q];
 #pragma unroll
                     for (int k = 0; k < BK; ++k) {
                         const int row = w + BW * k;
-                        if (row > a && row < rows) {
-                            const double mk = red_lazy(readlane_d(x[k][qt], lt), P, PI);
+                        {
+                            const double mk = (row > a && row < rows) ? red_lazy(readlane_d(x[k][qt], lt), P, PI) : 0.0;
 #pragma unroll
-                            for (int q = qt; q < BQ; ++q)
-                                if (q < nq) x[k][q] = fma(-mk, u[q], x[k][q]);
+                            for (int q = qt; q < BQ; ++q) x[k][q] = fma(-mk, u[q], x[k][q]);
                         }
                     }
                     if (j != t) {
@@ -491,7 +497,7 @@ __global__ __launch_bounds__(256) void batched_order_kernel(const int64_t* m, co
 
 }  // namespace
 
-int batched_max_n() { return BQ * 64; }
+int batched_max_n() { return BQMAX * 64; }
 
 void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_t* n,
                         int64_t* const* A, const int64_t* lda, const int64_t* p, int64_t* rank,
@@ -503,8 +509,17 @@ void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_
                            batch, order);
         CUP_HIP(hipGetLastError());
     }
+    // three widths: n <= 128, n <= 256, and the rest (n <= 512; wider or
+    // invalid descriptors are rejected there)
     BatchDesc g{m, n, A, lda, p, rank, P, Q, info, order};
-    hipLaunchKernelGGL(batched_cup_kernel, dim3(batch), dim3(BT), 0, s, g, batch);
+    hipLaunchKernelGGL(batched_cup_kernel<2>, dim3(batch), dim3(BT), 0, s, g, batch, INT64_MIN,
+                       (int64_t)128);
+    CUP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(batched_cup_kernel<4>, dim3(batch), dim3(BT), 0, s, g, batch, (int64_t)128,
+                       (int64_t)256);
+    CUP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(batched_cup_kernel<BQMAX>, dim3(batch), dim3(BT), 0, s, g, batch,
+                       (int64_t)256, INT64_MAX);
     CUP_HIP(hipGetLastError());
 }
 
