@@ -137,18 +137,26 @@ __global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64
     __shared__ double dinv[NB];
     const int b = blockIdx.x, o = b * NB, nb = min(NB, n - o), tid = threadIdx.x;
     const double P = mp.p, PI = mp.pinv;
-    // M = T_bb (upper) or its transpose (lower), identity-padded
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx >> 6, s = idx & 63;
-        double v;
-        if (i >= nb || s >= nb) {
-            v = (i == s) ? 1.0 : 0.0;
-        } else {
+    // M = T_bb (upper) or its transpose (lower), identity-padded.  Every
+    // address is clamped into the block so the 16 loads of a thread issue
+    // together; the selects pick identity and zeros afterwards.
+    {
+        double ld_v[NB * NB / 256];
+#pragma unroll
+        for (int it = 0; it < NB * NB / 256; ++it) {
+            const int idx = tid + 256 * it, i = idx >> 6, s = idx & 63;
             const int r = (uplo == 0) ? i : s, c = (uplo == 0) ? s : i;  // element (r, c) of T
-            v = (s >= i) ? ld_res(A + (int64_t)(o + r) * lda + o + c) : 0.0;
-            if (i == s && unit) v = 1.0;
+            const int rc = min(r, nb - 1), cc = min(c, nb - 1);
+            ld_v[it] = ld_res(A + (int64_t)(o + rc) * lda + o + cc);
         }
-        M[i][s] = v;
+#pragma unroll
+        for (int it = 0; it < NB * NB / 256; ++it) {
+            const int idx = tid + 256 * it, i = idx >> 6, s = idx & 63;
+            double v = (s >= i) ? ld_v[it] : 0.0;
+            if (i == s && unit) v = 1.0;
+            if (i >= nb || s >= nb) v = (i == s) ? 1.0 : 0.0;
+            M[i][s] = v;
+        }
     }
     __syncthreads();
     if (mode == 1) {
@@ -200,21 +208,43 @@ __global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const 
     const double P = mp.p, PI = mp.pinv;
     const int v0 = blockIdx.x * AV;
     const int nv = min(AV, other - v0);
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx >> 6, e = idx & 63;
-        // right: Ws[s][e] = W[s][e]; left: Ws[e][s] = W[e][s] read as Ws[s][e] = W[e][s]
-        Ws[i][e] = (side == 1) ? W[idx] : W[e * NB + i];
-    }
-    // Bs[v][s]: element s of vector v (row of B on the right, column on the left)
-    if (side == 1) {
-        for (int idx = tid; idx < AV * NB; idx += 256) {
-            const int v = idx >> 6, c = idx & 63;
-            Bs[v][c] = (v < nv && c < nb) ? ld_res(B + (int64_t)(v0 + v) * ldb + c) : 0.0;
+    // all loads of a thread issued together (addresses clamped, selects after)
+    {
+        double wv[NB * NB / 256];
+#pragma unroll
+        for (int it = 0; it < NB * NB / 256; ++it) {
+            const int idx = tid + 256 * it, i = idx >> 6, e = idx & 63;
+            // right: Ws[s][e] = W[s][e]; left: Ws[e][s] = W[e][s] read as Ws[s][e] = W[e][s]
+            wv[it] = (side == 1) ? W[idx] : W[e * NB + i];
         }
-    } else {
-        for (int idx = tid; idx < AV * NB; idx += 256) {
-            const int a = idx >> 4, v = idx & 15;
-            Bs[v][a] = (a < nb && v < nv) ? ld_res(B + (int64_t)a * ldb + v0 + v) : 0.0;
+        double bv[AV * NB / 256];
+#pragma unroll
+        for (int it = 0; it < AV * NB / 256; ++it) {
+            const int idx = tid + 256 * it;
+            if (side == 1) {
+                const int v = idx >> 6, c = idx & 63;
+                bv[it] = ld_res(B + (int64_t)(v0 + min(v, nv - 1)) * ldb + min(c, nb - 1));
+            } else {
+                const int a = idx >> 4, v = idx & 15;
+                bv[it] = ld_res(B + (int64_t)min(a, nb - 1) * ldb + v0 + min(v, nv - 1));
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < NB * NB / 256; ++it) {
+            const int idx = tid + 256 * it;
+            Ws[idx >> 6][idx & 63] = wv[it];
+        }
+        // Bs[v][s]: element s of vector v (row of B on the right, column on the left)
+#pragma unroll
+        for (int it = 0; it < AV * NB / 256; ++it) {
+            const int idx = tid + 256 * it;
+            if (side == 1) {
+                const int v = idx >> 6, c = idx & 63;
+                Bs[v][c] = (v < nv && c < nb) ? bv[it] : 0.0;
+            } else {
+                const int a = idx >> 4, v = idx & 15;
+                Bs[v][a] = (a < nb && v < nv) ? bv[it] : 0.0;
+            }
         }
     }
     __syncthreads();
