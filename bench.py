@@ -145,7 +145,29 @@ def batched_variant(cup, torch, inputs, steps, warmup, gold):
             "errors": int((info != 0).sum()), "parity": parity, "timing": "HIP events, median"}
 
 
-def roofline_of(stats, form, steps):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ffgemm_i8_cup8192_gf65521_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the INT8 product kernel from the committed
+    counter summary, or None when the kernel source has changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        for key in ("traffic_bytes_per_launch:", "kernel_source:", "kernel_source_sha256:"):
+            if line.startswith(key):
+                vals[key[:-1]] = line[len(key):].strip()
+    try:
+        src = os.path.join(ROOT, vals["kernel_source"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        return float(vals["traffic_bytes_per_launch"]) if sha == vals["kernel_source_sha256"] else None
+    except (KeyError, OSError, ValueError):
+        return None
+
+
+def roofline_of(stats, form, steps, traffic=None):
     """Dominant-kernel roofline from the library's HIP-event timing."""
     key = "ffgemm" if form == "fp64" else "ffgemm_i8"
     st = stats[key]
@@ -156,7 +178,9 @@ def roofline_of(stats, form, steps):
         "bound": "mfma",
         "kernel": "ffgemm_f64_kernel" if form == "fp64" else "ffgemm_i8_kernel",
         "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-        "frac": round(achieved / peak, 4), "traffic": None,
+        "frac": round(achieved / peak, 4), "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "algorithmic_bytes_per_launch": st["bytes"] / max(1.0, st["launches"]),
         "launches_per_step": st["launches"] / steps,
         "avg_launch_ms": st["ms"] / max(1.0, st["launches"]),
         "ops_per_launch": mult * st["flops"] / max(1.0, st["launches"]),
@@ -176,7 +200,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--form", default="i8limb", choices=["fp64", "i8limb"])
-    ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--cpu-rows", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
@@ -213,7 +237,8 @@ def main():
     F = field_ops(n, n, r)
     value = F / res["seconds"]
     parity = parity_of(res, gkey)
-    roofline = roofline_of(res["stats"], form, args.steps)
+    traffic = measured_traffic() if (form == "i8limb" and n == 8192) else None
+    roofline = roofline_of(res["stats"], form, args.steps, traffic)
     forms = {form: {"ms_per_step": res["seconds"] * 1e3, "field_ops_per_s": value, "parity": parity,
                     "kernels": breakdown(res["stats"], args.steps)}}
     extra = {}

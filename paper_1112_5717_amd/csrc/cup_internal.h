@@ -59,7 +59,7 @@ struct TranspList {
 template <typename T>
 void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t lda,
                        const T* B, int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha,
-                       int kred_steps);
+                       int kred_steps, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // C(MxN) <- C + alpha A(MxK) B(KxN) mod p on INT8 MFMA: limb = 0 for p < 2^7
 // (one signed byte per residue), 1 for p <= 2^16 (two signed limbs).  Per K
@@ -73,7 +73,7 @@ int launch_pack_i8(hipStream_t s, int M, int N, int kc, const T* A, int64_t lda,
                    int64_t ldb, ModP mp, int limb, int8_t* ws);
 template <typename T>
 void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, int64_t ldc,
-                   ModP mp, int alpha, int limb);
+                   ModP mp, int alpha, int limb, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Window elimination of a leaf (see k_panel.hip).  Writes d, stop and the
 // chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col).

@@ -61,6 +61,13 @@ struct Profiler {
         recs.push_back(r);
     }
     void end(hipStream_t s) { CUP_HIP(hipEventRecord(recs.back().b, s)); }
+    // An event pair for a launch that records it itself (hipExtLaunchKernel):
+    // the interval is then the kernel's own execution, as a profiler sees it.
+    ProfRec& open(int kind, double f, double by)
+    {
+        recs.push_back(ProfRec{kind, f, by, next(), next()});
+        return recs.back();
+    }
     // after the stream has synchronised
     void collect()
     {
@@ -204,20 +211,25 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
                               ((double)M * kc + (double)kc * N) * (sizeof(T) + nl));
             const int Kp = launch_pack_i8<T>(c.s, M, N, kc, A + k0, lda, B + (int64_t)k0 * ldb, ldb,
                                              c.mp, limb, ws);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
             if (prof) {
                 c.prof->end(c.s);
-                c.prof->begin(c.s, 2, 2.0 * M * N * kc,
-                              ((double)M * kc + (double)kc * N) * nl + 2.0 * M * N * sizeof(T));
+                ProfRec& r = c.prof->open(2, 2.0 * M * N * kc,
+                                          ((double)M * kc + (double)kc * N) * nl + 2.0 * M * N * sizeof(T));
+                e0 = r.a;
+                e1 = r.b;
             }
-            launch_mma_i8<T>(c.s, M, N, Kp, ws, C, ldc, c.mp, alpha, limb);
-            if (prof) c.prof->end(c.s);
+            launch_mma_i8<T>(c.s, M, N, Kp, ws, C, ldc, c.mp, alpha, limb, e0, e1);
         }
     } else {
-        if (prof)
-            c.prof->begin(c.s, 0, 2.0 * M * N * K,
-                          ((double)M * K + (double)K * N + 2.0 * M * N) * sizeof(T));
-        launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps);
-        if (prof) c.prof->end(c.s);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (prof) {
+            ProfRec& r = c.prof->open(0, 2.0 * M * N * K,
+                                      ((double)M * K + (double)K * N + 2.0 * M * N) * sizeof(T));
+            e0 = r.a;
+            e1 = r.b;
+        }
+        launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps, e0, e1);
     }
 }
 

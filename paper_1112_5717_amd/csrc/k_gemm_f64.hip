@@ -14,6 +14,8 @@
 // each as 4 x 4 blocks of v_mfma_f64_16x16x4f64), or 64 x 64 tiles for
 // products too small to give two workgroups per CU; K tiles of 16 staged
 // through LDS (double-buffered, register prefetch of the next tile).
+#include <hip/hip_ext.h>
+
 #include "modarith.h"
 
 namespace cup {
@@ -168,7 +170,8 @@ __global__ __launch_bounds__(256, 2) void ffgemm_f64_kernel(int M, int N, int K,
 
 template <typename T>
 void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, const T* B,
-                       int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, int kred_steps)
+                       int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, int kred_steps,
+                       hipEvent_t ev0, hipEvent_t ev1)
 {
     if (M <= 0 || N <= 0 || K <= 0) return;
     // products per lane-element before the sum could reach 2^53 (>= 4)
@@ -177,14 +180,18 @@ void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t l
     const bool big = (int64_t)((M + 127) / 128) * ((N + 127) / 128) >= 512;
     for (int64_t k0 = 0; k0 < K; k0 += kmax) {
         const int kc = (int)std::min<int64_t>(kmax, K - k0);
+        // timing events (optional) open with the first chunk's dispatch and
+        // close with the last one's
+        hipEvent_t a = (k0 == 0) ? ev0 : nullptr;
+        hipEvent_t b = (k0 + kmax >= K) ? ev1 : nullptr;
         if (big) {
             dim3 grid((N + 127) / 128, (M + 127) / 128);
-            hipLaunchKernelGGL((ffgemm_f64_kernel<T, 128, 128>), grid, dim3(256), 0, s, M, N, kc,
-                               A + k0, lda, B + k0 * ldb, ldb, C, ldc, mp, alpha);
+            hipExtLaunchKernelGGL((ffgemm_f64_kernel<T, 128, 128>), grid, dim3(256), 0, s, a, b, 0, M,
+                                  N, kc, A + k0, lda, B + k0 * ldb, ldb, C, ldc, mp, alpha);
         } else {
             dim3 grid((N + 63) / 64, (M + 63) / 64);
-            hipLaunchKernelGGL((ffgemm_f64_kernel<T, 64, 64>), grid, dim3(256), 0, s, M, N, kc,
-                               A + k0, lda, B + k0 * ldb, ldb, C, ldc, mp, alpha);
+            hipExtLaunchKernelGGL((ffgemm_f64_kernel<T, 64, 64>), grid, dim3(256), 0, s, a, b, 0, M, N,
+                                  kc, A + k0, lda, B + k0 * ldb, ldb, C, ldc, mp, alpha);
         }
         CUP_HIP(hipGetLastError());
     }
@@ -192,8 +199,9 @@ void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t l
 
 template void launch_ffgemm_f64<int64_t>(hipStream_t, int, int, int, const int64_t*, int64_t,
                                          const int64_t*, int64_t, int64_t*, int64_t, ModP, int,
-                                         int);
+                                         int, hipEvent_t, hipEvent_t);
 template void launch_ffgemm_f64<int8_t>(hipStream_t, int, int, int, const int8_t*, int64_t,
-                                        const int8_t*, int64_t, int8_t*, int64_t, ModP, int, int);
+                                        const int8_t*, int64_t, int8_t*, int64_t, ModP, int, int,
+                                        hipEvent_t, hipEvent_t);
 
 }  // namespace cup

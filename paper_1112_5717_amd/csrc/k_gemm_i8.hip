@@ -19,6 +19,8 @@
 // of 64 x 64, as 4 x 4 blocks of v_mfma_i32_16x16x64_i8), K in steps of 64
 // staged through LDS with double buffering; the epilogue reduces mod p in
 // FP64 and adds alpha S to C.
+#include <hip/hip_ext.h>
+
 #include "modarith.h"
 
 namespace cup {
@@ -267,17 +269,18 @@ int launch_pack_i8(hipStream_t s, int M, int N, int kc, const T* A, int64_t lda,
 
 template <typename T>
 void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, int64_t ldc,
-                   ModP mp, int alpha, int limb)
+                   ModP mp, int alpha, int limb, hipEvent_t ev0, hipEvent_t ev1)
 {
     const int64_t Mp = (M + IBM - 1) / IBM * IBM, Np = (N + IBN - 1) / IBN * IBN;
     const PackedPtrs q = packed_ptrs(const_cast<int8_t*>(ws), M, N, Kp, limb);
     const dim3 grid((unsigned)(Np / IBN), (unsigned)(Mp / IBM));
+    // the events (timing only) are recorded by the dispatch itself
     if (limb)
-        hipLaunchKernelGGL((ffgemm_i8_kernel<T, 1>), grid, dim3(256), 0, s, M, N, Kp, q.Ah, q.Al, q.Bh,
-                           q.Bl, C, ldc, mp, alpha);
+        hipExtLaunchKernelGGL((ffgemm_i8_kernel<T, 1>), grid, dim3(256), 0, s, ev0, ev1, 0, M, N, Kp,
+                              q.Ah, q.Al, q.Bh, q.Bl, C, ldc, mp, alpha);
     else
-        hipLaunchKernelGGL((ffgemm_i8_kernel<T, 0>), grid, dim3(256), 0, s, M, N, Kp, q.Ah, q.Al, q.Bh,
-                           q.Bl, C, ldc, mp, alpha);
+        hipExtLaunchKernelGGL((ffgemm_i8_kernel<T, 0>), grid, dim3(256), 0, s, ev0, ev1, 0, M, N, Kp,
+                              q.Ah, q.Al, q.Bh, q.Bl, C, ldc, mp, alpha);
     CUP_HIP(hipGetLastError());
 }
 
@@ -285,7 +288,7 @@ void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, 
     template int launch_pack_i8<T>(hipStream_t, int, int, int, const T*, int64_t, const T*,     \
                                    int64_t, ModP, int, int8_t*);                                \
     template void launch_mma_i8<T>(hipStream_t, int, int, int, const int8_t*, T*, int64_t, ModP, \
-                                   int, int);
+                                   int, int, hipEvent_t, hipEvent_t);
 CUP_INST(int64_t)
 CUP_INST(int8_t)
 #undef CUP_INST
