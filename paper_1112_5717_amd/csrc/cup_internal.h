@@ -31,7 +31,7 @@ struct CupError {
 
 // Leaf sizes of the recursions.
 constexpr int kLeafRows = 64;   // rows of a CUP leaf (one window-elimination block)
-constexpr int kWin = 128;       // window width of the leaf elimination
+constexpr int kWin = 64;        // window width of the leaf elimination
 constexpr int kTriNB = 64;      // order of a triangular leaf block
 
 // Stop reasons of the window elimination.

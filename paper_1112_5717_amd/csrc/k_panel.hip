@@ -5,8 +5,9 @@
 // column to the front and scales the rest of the row by the pivot's inverse.
 // Unrolled over a block of rows, this is row-by-row elimination in which
 // every decision depends on all earlier ones, so it is the sequential chain
-// of the method.  It is confined here to one workgroup and to a window of at
-// most 128 columns held in LDS:
+// of the method.  It is confined here to one workgroup and to a window of 64
+// columns (compiled for 64 or 128; a full-rank leaf of 64 rows finds its 64
+// pivots in the first 64 columns) held in registers:
 //
 //  * Each row's residual is tested for its leftmost nonzero with one
 //    wave-wide ballot per 64 columns.
@@ -48,16 +49,26 @@ __device__ __forceinline__ double red_c(double x, double p, double pinv)
     return fma(-q, p, x);
 }
 
+// v[q][k] for a wave-uniform q (a select chain over the register halves)
+template <int WQ>
+__device__ __forceinline__ double pick(const double (&v)[WQ][KPW], int k, int q)
+{
+    double x = v[0][k];
+#pragma unroll
+    for (int e = 1; e < WQ; ++e) x = (q == e) ? v[e][k] : x;
+    return x;
+}
+
 // Register-resident tile: thread (wave w, lane l) holds rows w + 8k
-// (k = 0..7) of columns l and l + 64.  The pivot row and the multiplier
+// (k = 0..7) of columns l + 64q (q < WQ).  The pivot row and the multiplier
 // column of each step are exchanged through LDS buffers alternating with
 // the step's parity, so one barrier per pivot suffices.
-template <typename T>
+template <typename T, int WQ>
 __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t lda, int b, int N,
                                                     int i0, int t0, int wc, ModP mp,
                                                     int* __restrict__ out)
 {
-    __shared__ double rowbuf[2][kWin];
+    __shared__ double rowbuf[2][64 * WQ];
     __shared__ double colbuf[2][kLeafRows];
     __shared__ int s_j[2];
     __shared__ int s_swap[kLeafRows];
@@ -70,9 +81,9 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     const int R = b - i0;
     const double P = mp.p, PI = mp.pinv;
 
-    double v[2][KPW];
+    double v[WQ][KPW];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < WQ; ++q)
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
             const int r = w + NWV * k, c = lane + 64 * q;
@@ -87,20 +98,20 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
             if (w + NWV * k == a) {
-                const double x0 = v[0][k], x1 = v[1][k];
-                const unsigned long long m0 = __ballot(lane >= a && lane < wc && x0 != 0.0);
-                const unsigned long long m1 =
-                    __ballot(lane + 64 >= a && lane + 64 < wc && x1 != 0.0);
-                rowbuf[par][lane] = x0;
-                rowbuf[par][lane + 64] = x1;
-                if (lane == 0)
-                    s_j[par] = m0 ? __ffsll((long long)m0) - 1
-                                  : (m1 ? 64 + __ffsll((long long)m1) - 1 : -1);
+                int jj = -1;
+#pragma unroll
+                for (int q = WQ - 1; q >= 0; --q) {
+                    const int c = lane + 64 * q;
+                    const unsigned long long mq = __ballot(c >= a && c < wc && v[q][k] != 0.0);
+                    rowbuf[par][c] = v[q][k];
+                    if (mq) jj = 64 * q + __ffsll((long long)mq) - 1;
+                }
+                if (lane == 0) s_j[par] = jj;
             }
         }
         if (lane == la) {
 #pragma unroll
-            for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = qa ? v[1][k] : v[0][k];
+            for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = pick(v, k, qa);
         }
     };
 
@@ -114,7 +125,9 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         // every LDS read of the step issued together (no swap assumed)
         const int j = s_j[par];
         double piv = rowbuf[par][a];
-        double u0 = rowbuf[par][lane], u1 = rowbuf[par][lane + 64];
+        double u[WQ];
+#pragma unroll
+        for (int q = 0; q < WQ; ++q) u[q] = rowbuf[par][lane + 64 * q];
         double mlt[KPW];
 #pragma unroll
         for (int k = 0; k < KPW; ++k) mlt[k] = colbuf[par][w + NWV * k];
@@ -124,17 +137,20 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             const int qj = j >> 6, lj = j & 63;
 #pragma unroll
             for (int k = 0; k < KPW; ++k) {
-                const double ca = qa ? v[1][k] : v[0][k];
-                const double cj = qj ? v[1][k] : v[0][k];
+                const double ca = pick(v, k, qa);
+                const double cj = pick(v, k, qj);
                 const double from_j = __shfl(cj, lj, 64);
                 const double from_a = __shfl(ca, la, 64);
-                if (lane == la) { if (qa) v[1][k] = from_j; else v[0][k] = from_j; }
-                if (lane == lj) { if (qj) v[1][k] = from_a; else v[0][k] = from_a; }
+#pragma unroll
+                for (int q = 0; q < WQ; ++q) {
+                    if (lane == la && q == qa) v[q][k] = from_j;
+                    if (lane == lj && q == qj) v[q][k] = from_a;
+                }
             }
             __syncthreads();  // every wave has read the step's buffers
             if (lane == la) {
 #pragma unroll
-                for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = qa ? v[1][k] : v[0][k];
+                for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = pick(v, k, qa);
             }
             if (tid == 0) {
                 double x = rowbuf[par][a];
@@ -143,8 +159,8 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             }
             __syncthreads();
             piv = rowbuf[par][a];
-            u0 = rowbuf[par][lane];
-            u1 = rowbuf[par][lane + 64];
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) u[q] = rowbuf[par][lane + 64 * q];
 #pragma unroll
             for (int k = 0; k < KPW; ++k) mlt[k] = colbuf[par][w + NWV * k];
         }
@@ -154,14 +170,14 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         }
         // fraction-free update of rows > a, columns > a: rows skipped per
         // wave, columns masked per lane
-        const bool c0 = lane > a, c1 = lane + 64 > a;
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
             if (w + NWV * k > a) {
-                const double n0 = red_c(fma(piv, v[0][k], -mlt[k] * u0), P, PI);
-                const double n1 = red_c(fma(piv, v[1][k], -mlt[k] * u1), P, PI);
-                v[0][k] = c0 ? n0 : v[0][k];
-                v[1][k] = c1 ? n1 : v[1][k];
+#pragma unroll
+                for (int q = 0; q < WQ; ++q) {
+                    const double nq = red_c(fma(piv, v[q][k], -mlt[k] * u[q]), P, PI);
+                    v[q][k] = (lane + 64 * q > a) ? nq : v[q][k];
+                }
             }
         }
         d = a + 1;
@@ -190,7 +206,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     __syncthreads();
 
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < WQ; ++q)
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
             const int r = w + NWV * k, c = lane + 64 * q;
@@ -257,8 +273,9 @@ template <typename T>
 void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
                    ModP mp, int* out)
 {
-    hipLaunchKernelGGL(window_kernel<T>, dim3(1), dim3(WT), 0, s, A, lda, b, N, i0, t0, wc, mp,
-                       out);
+    static_assert(kWin % 64 == 0 && kWin <= 128, "window of 64 or 128 columns");
+    hipLaunchKernelGGL((window_kernel<T, kWin / 64>), dim3(1), dim3(WT), 0, s, A, lda, b, N, i0, t0,
+                       wc, mp, out);
     CUP_HIP(hipGetLastError());
 }
 
