@@ -65,13 +65,30 @@ __device__ void inverse_column_big(const double (*M)[NB + 1], const double* dinv
     }
 }
 
+// Residue in (-p, p): x - round(x / p) p, exact for |x| < 2^53 with
+// |x / p| < 2^51 (the rounding adds and subtracts 1.5 * 2^52; the quotient
+// from the rounded reciprocal is within one of x / p, so |x - q p| < p).
+// Three dependent operations, against six for the canonical reduction, on
+// the latency-bound chains below.
+__device__ __forceinline__ double red_near(double x, double p, double pinv)
+{
+    const double magic = 6755399441055744.0;  // 1.5 * 2^52
+    const double q = fma(x, pinv, magic) - magic;
+    return fma(-q, p, x);
+}
+
+__device__ __forceinline__ double canon(double x, double p) { return (x < 0.0) ? x + p : x; }
+
 // Inverse of the upper triangle held in M (64 x 64, identity-padded), into X,
 // by 16 x 16 blocks: the four diagonal blocks are inverted column-parallel
 // (a chain of 16 steps), then the off-diagonal blocks follow by increasing
 // block distance d = b - a:  X_ab = -D_a (sum_{a < k <= b} M_ak X_kb).
-// 256 threads; sums of at most 48 products stay exact for p < 2^23.5.
+// 256 threads.  X and S hold residues in (-p, p); every product is below
+// p^2 and a sum of at most 48 of them stays exact for p < 2^23.5.  Sums run
+// in four independent partial accumulators to shorten the dependent chains.
 __device__ void block_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 1],
-                                    double (*S)[NB + 1], const double* dinv, double P, double PI)
+                                    double (*S)[NB + 1], const double* dinv, int unit, double P,
+                                    double PI)
 {
     const int tid = threadIdx.x;
     if (tid < NB) {
@@ -81,11 +98,11 @@ __device__ void block_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 
         for (int i = 0; i < 16; ++i) acc[i] = (i == j) ? 1.0 : 0.0;
 #pragma unroll
         for (int i = 15; i >= 0; --i) {
-            const double x = mod_mul(mod_red(acc[i], P, PI), dinv[o + i], P, PI);
+            const double r = red_near(acc[i], P, PI);
+            const double x = unit ? r : red_near(r * dinv[o + i], P, PI);
             X[o + i][o + j] = x;
-            const double nx = (x == 0.0) ? 0.0 : P - x;
 #pragma unroll
-            for (int t = 0; t < i; ++t) acc[t] = fma(M[o + t][o + i], nx, acc[t]);
+            for (int t = 0; t < i; ++t) acc[t] = fma(M[o + t][o + i], -x, acc[t]);
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i)
@@ -93,30 +110,33 @@ __device__ void block_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 
                 if (b != a) X[o + i][16 * b + j] = 0.0;
     }
     __syncthreads();
+    // every loop below has constant bounds once d is unrolled: thread tid
+    // owns element (i, j) = (tid / 16, tid % 16) of each block (a, a + d)
+    const int i = tid >> 4, j = tid & 15;
+#pragma unroll
     for (int d = 1; d < 4; ++d) {
-        const int nblk = 4 - d;  // blocks (a, a + d)
         // S_ab = sum_{k=a+1..b} M_ak X_kb
-        for (int idx = tid; idx < nblk * 256; idx += 256) {
-            const int a = idx >> 8, e = idx & 255, i = e >> 4, j = e & 15, b = a + d;
-            double acc = 0.0;
-            for (int kb = a + 1; kb <= b; ++kb) {
-                double part = 0.0;
+#pragma unroll
+        for (int a = 0; a + d < 4; ++a) {
+            const int b = a + d;
+            double pa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kb = a + 1; kb <= b; ++kb)
 #pragma unroll
                 for (int s = 0; s < 16; ++s)
-                    part = fma(M[16 * a + i][16 * kb + s], X[16 * kb + s][16 * b + j], part);
-                acc += part;
-            }
-            S[16 * a + i][16 * b + j] = mod_red(acc, P, PI);
+                    pa[s & 3] = fma(M[16 * a + i][16 * kb + s], X[16 * kb + s][16 * b + j], pa[s & 3]);
+            S[16 * a + i][16 * b + j] = red_near((pa[0] + pa[1]) + (pa[2] + pa[3]), P, PI);
         }
         __syncthreads();
         // X_ab = -D_a S_ab
-        for (int idx = tid; idx < nblk * 256; idx += 256) {
-            const int a = idx >> 8, e = idx & 255, i = e >> 4, j = e & 15, b = a + d;
-            double acc = 0.0;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) acc = fma(X[16 * a + i][16 * a + s], S[16 * a + s][16 * b + j], acc);
-            const double x = mod_red(acc, P, PI);
-            X[16 * a + i][16 * b + j] = (x == 0.0) ? 0.0 : P - x;
+        for (int a = 0; a + d < 4; ++a) {
+            const int b = a + d;
+            double pa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                pa[s & 3] = fma(X[16 * a + i][16 * a + s], S[16 * a + s][16 * b + j], pa[s & 3]);
+            X[16 * a + i][16 * b + j] = -red_near((pa[0] + pa[1]) + (pa[2] + pa[3]), P, PI);
         }
         __syncthreads();
     }
@@ -173,21 +193,21 @@ __global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64
         if (tid < NB) inverse_column_big(M, dinv, 0, tid, X, P, PI);
         __syncthreads();
     } else {
-        block_upper_inverse(M, X, S, dinv, P, PI);
+        block_upper_inverse(M, X, S, dinv, unit, P, PI);
     }
     // X holds the inverse of the upper form; the lower inverse is its transpose
     if (mode == 0) {
         double* Wb = W + (size_t)b * NB * NB;
         for (int idx = tid; idx < NB * NB; idx += 256) {
             const int i = idx >> 6, s = idx & 63;
-            Wb[idx] = (uplo == 0) ? X[i][s] : X[s][i];
+            Wb[idx] = canon((uplo == 0) ? X[i][s] : X[s][i], P);
         }
     } else {
         for (int idx = tid; idx < NB * NB; idx += 256) {
             const int i = idx >> 6, s = idx & 63;  // element (i, s) of the inverse
             if (i >= nb || s >= nb) continue;
             const bool write = (uplo == 0) ? (unit ? s > i : s >= i) : (unit ? s < i : s <= i);
-            if (write) st_res(A + (int64_t)(o + i) * lda + o + s, (uplo == 0) ? X[i][s] : X[s][i]);
+            if (write) st_res(A + (int64_t)(o + i) * lda + o + s, canon((uplo == 0) ? X[i][s] : X[s][i], P));
         }
     }
 }
