@@ -106,7 +106,7 @@ struct Ctx {
     int* d_small = nullptr; // device results of the leaf kernels
     int* h_small = nullptr; // pinned host mirror
     int log = 0;
-    double i8_min_work = 16777216.0;  // M N K below which products stay on FP64
+    double i8_min_work = 1.0e9;  // M N K below which products stay on FP64
 };
 
 constexpr int kSmallInts = 4096;

@@ -166,6 +166,108 @@ __global__ __launch_bounds__(256, 2) void ffgemm_f64_kernel(int M, int N, int K,
         }
 }
 
+// Products with K <= 64 (the thin updates of the triangular recursion and of
+// the lowest CUP levels): one 64 x 64 tile per workgroup with the whole
+// K-extent staged at once.  Every global load of the tile (A, B and the C
+// entries the epilogue updates) is issued before the first wait, so the
+// launch pays one memory latency instead of one per 16-deep K tile.
+constexpr int SK = 64;  // largest K of this variant
+
+template <typename T>
+__global__ __launch_bounds__(256) void ffgemm_f64_k64_kernel(int M, int N, int K,
+                                                           const T* __restrict__ A, int64_t lda,
+                                                           const T* __restrict__ B, int64_t ldb,
+                                                           T* __restrict__ C, int64_t ldc, ModP mp,
+                                                           int alpha)
+{
+    constexpr int BM = 64, BN = 64, TM = 2, TN = 2;
+    __shared__ double As[SK][BM + PADM];
+    __shared__ double Bs[SK][BN + PADM];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const double P = mp.p, PI = mp.pinv, half = floor(mp.p * 0.5);
+
+    // C entries of this thread's outputs (the MFMA result layout: lane l
+    // holds column l % 16 of rows l / 16 + 4e of each 16 x 16 block)
+    const int gn0 = n0 + wn + (lane & 15), gm0 = m0 + wm + (lane >> 4);
+    int rc[TM][TN][4];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = min(gm0 + i * 16 + 4 * e, M - 1), gn = min(gn0 + j * 16, N - 1);
+                rc[i][j][e] = ld_raw(C + (int64_t)gm * ldc + gn);
+            }
+    // A: 64 rows x 64 k, thread (row ar + 16 i, k = ac + 16 u); B: 64 k x 64 cols
+    const int ac = tid & 15, ar = tid >> 4;
+    int ra[4][4], rb[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const T* pa = A + (int64_t)min(m0 + ar + 16 * i, M - 1) * lda;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ra[i][u] = ld_raw(pa + min(ac + 16 * u, K - 1));
+    }
+    const int bc = tid & 63, br = tid >> 6;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        rb[u] = ld_raw(B + (int64_t)min(br + 4 * u, K - 1) * ldb + min(n0 + bc, N - 1));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = ac + 16 * u;
+            As[k][ar + 16 * i] = (k < K) ? centre((double)ra[i][u], half, P) : 0.0;
+        }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int k = br + 4 * u;
+        Bs[k][bc] = (k < K) ? centre((double)rb[u], half, P) : 0.0;
+    }
+    __syncthreads();
+
+    v4d acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nks = (K + 3) >> 2;
+    for (int ks = 0; ks < nks; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        double a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = As[kk][wm + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = Bs[kk][wn + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int gn = gn0 + j * 16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = gm0 + i * 16 + 4 * e;
+                if (gm < M && gn < N) {
+                    const double sv = mod_red(acc[i][j][e], P, PI);
+                    const double c = (double)rc[i][j][e];
+                    double r = (alpha < 0) ? c - sv : c + sv;
+                    r = (r < 0.0) ? r + P : r;
+                    r = (r >= P) ? r - P : r;
+                    st_res(C + (int64_t)gm * ldc + gn, r);
+                }
+            }
+        }
+}
+
 }  // namespace
 
 template <typename T>
@@ -176,6 +278,13 @@ void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t l
     if (M <= 0 || N <= 0 || K <= 0) return;
     // products per lane-element before the sum could reach 2^53 (>= 4)
     const int64_t kmax = std::max<int64_t>(4, std::min<int64_t>(4 * (int64_t)kred_steps, K));
+    if (K <= SK && K <= kmax) {
+        dim3 grid((N + 63) / 64, (M + 63) / 64);
+        hipExtLaunchKernelGGL((ffgemm_f64_k64_kernel<T>), grid, dim3(256), 0, s, ev0, ev1, 0, M, N, K,
+                              A, lda, B, ldb, C, ldc, mp, alpha);
+        CUP_HIP(hipGetLastError());
+        return;
+    }
     // 128 x 128 tiles when they give at least two workgroups per CU, else 64 x 64
     const bool big = (int64_t)((M + 127) / 128) * ((N + 127) / 128) >= 512;
     for (int64_t k0 = 0; k0 < K; k0 += kmax) {

@@ -56,7 +56,8 @@ def exact_gemm(C, A, B, p, alpha):
 
 
 @pytest.mark.parametrize("p", [2, 127, 65521, 8388593, 33554393])
-@pytest.mark.parametrize("shape", [(1, 1, 1), (7, 5, 3), (130, 129, 17), (257, 131, 200), (64, 300, 513)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (7, 5, 3), (130, 129, 17), (257, 131, 200), (64, 300, 513),
+                                   (300, 130, 64), (129, 65, 63), (4100, 64, 64), (65, 1000, 33)])
 def test_ffgemm_fp64_random(cup_lib, p, shape):
     M, N, K = shape
     rng = np.random.default_rng(M * 7 + N + K + p % 1000)
