@@ -176,7 +176,9 @@ int factor_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* ran
         if (m > 0 && n > 0) {
             Pl.reserve((size_t)std::min(m, n));
             Ql.reserve((size_t)std::min(m, n));
+            ucache_begin(c, A, lda, (int)std::min(m, n));
             r = cup_rec<T>(c, A, lda, (int)m, (int)n, Pl, Ql);
+            c.base = nullptr;
         }
         if (tail >= 1 && r > 0) {
             int* dq = ensure_list(g, (size_t)r);
@@ -439,6 +441,7 @@ int cup_finalize(void)
     if (g.d_list) (void)hipFree(g.d_list);
     if (g.d_order) (void)hipFree(g.d_order);
     if (g.ws.tri) (void)hipFree(g.ws.tri);
+    if (g.ws.uc) (void)hipFree(g.ws.uc);
     if (g.ws.pk) (void)hipFree(g.ws.pk);
     g.ws = Workspace{};
     g.d_small = nullptr;

@@ -112,6 +112,13 @@ void launch_diag_prep(hipStream_t s, T* A, int64_t lda, int n, int uplo, int uni
                       double* W, ModP mp);
 
 // B <- B W (side 1: B is other x nb) or W B (side 0: B is nb x other).
+// Two inversions in one launch (mode 0): the diagonal blocks of the n x n
+// triangle at A into W, and the single 64 x 64 triangle at A2 (same lda)
+// into W2.
+template <typename T>
+void launch_diag_prep2(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, double* W,
+                       T* A2, int uplo2, int unit2, double* W2, ModP mp);
+
 template <typename T>
 void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, int64_t ldb,
                       int other, ModP mp);

@@ -89,6 +89,8 @@ struct Profiler {
 struct Workspace {
     double* tri = nullptr;
     size_t tri_cap = 0;  // doubles
+    double* uc = nullptr;  // inverses of the 64 x 64 unit-upper diagonal blocks of U
+    size_t uc_cap = 0;     // blocks
     int8_t* pk = nullptr;  // packed ffgemm operands of the INT8 forms
     size_t pk_cap = 0;     // bytes
     size_t bytes = 0;
@@ -107,7 +109,57 @@ struct Ctx {
     int* h_small = nullptr; // pinned host mirror
     int log = 0;
     double i8_min_work = 1.0e9;  // M N K below which products stay on FP64
+    // The matrix being factored (its top-left and leading dimension) and
+    // which 64 x 64 diagonal blocks of its U have their inverse in ws->uc.
+    const void* base = nullptr;
+    int64_t base_lda = 0;
+    std::vector<char> uc_ok;
 };
+
+// Global diagonal index of the element at p (p on the diagonal of the matrix
+// being factored), or -1.
+template <typename T>
+inline int64_t diag_index(const Ctx& c, const T* p)
+{
+    if (!c.base) return -1;
+    const int64_t off = (int64_t)(p - static_cast<const T*>(c.base));
+    if (off < 0 || off % (c.base_lda + 1) != 0) return -1;
+    return off / (c.base_lda + 1);
+}
+
+// Slot for the inverse of the unit-upper diagonal block of U at global
+// diagonal index g (a multiple of 64), or null when there is none.
+inline double* ucache_slot(Ctx& c, int64_t g)
+{
+    if (g < 0 || g % kTriNB != 0) return nullptr;
+    const size_t blk = (size_t)(g / kTriNB);
+    return blk < c.uc_ok.size() ? c.ws->uc + blk * kTriNB * kTriNB : nullptr;
+}
+
+// Reserve the U-block cache of a factorization with at most `rmax` pivots.
+inline void ucache_begin(Ctx& c, const void* base, int64_t lda, int rmax)
+{
+    const size_t blocks = (size_t)(rmax / kTriNB);
+    Workspace& w = *c.ws;
+    if (blocks > w.uc_cap) {
+        if (w.uc) {
+            CUP_HIP(hipStreamSynchronize(c.s));
+            CUP_HIP(hipFree(w.uc));
+            w.bytes -= w.uc_cap * kTriNB * kTriNB * sizeof(double);
+            w.uc = nullptr;
+            w.uc_cap = 0;
+        }
+        if (hipMalloc((void**)&w.uc, blocks * kTriNB * kTriNB * sizeof(double)) != hipSuccess) {
+            w.uc = nullptr;
+            throw CupError{-2000};
+        }
+        w.uc_cap = blocks;
+        w.bytes += blocks * kTriNB * kTriNB * sizeof(double);
+    }
+    c.base = base;
+    c.base_lda = lda;
+    c.uc_ok.assign(blocks, 0);
+}
 
 constexpr int kSmallInts = 4096;
 
@@ -423,13 +475,27 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         pending = -1;
         if (d > 0) {
             const int tw = t + wc;
+            // A whole leaf decided by its first window (64 pivots in rows
+            // 0..63, which then never move) sits on the diagonal of U: its
+            // unit-upper 64 x 64 block is inverted in the same launch as the
+            // flush's lower block, for the Schur solves of the ancestors.
+            T* blk = A + (int64_t)i * lda + t;
+            double* ucs = (i == 0 && t == 0 && d == kLeafRows && b == kLeafRows)
+                              ? ucache_slot(c, diag_index(c, blk)) : nullptr;
             if (tw < N) {
-                trsm(c, LEFT, LOWER, 0, d, A + (int64_t)i * lda + t, lda,
-                     A + (int64_t)i * lda + tw, lda, N - tw);
+                double* W = tri_workspace(c, d);
+                if (ucs)
+                    launch_diag_prep2<T>(c.s, blk, lda, d, LOWER, 0, W, blk, UPPER, 1, ucs, c.mp);
+                else
+                    launch_diag_prep<T>(c.s, blk, lda, d, LOWER, 0, 0, W, c.mp);
+                tri_rec(c, SOLVE, LEFT, LOWER, d, blk, lda, A + (int64_t)i * lda + tw, lda, N - tw, W);
                 if (i + d < b)
                     gemm(c, b - i - d, N - tw, d, A + (int64_t)(i + d) * lda + t, lda,
                          A + (int64_t)i * lda + tw, lda, A + (int64_t)(i + d) * lda + tw, lda, -1);
+            } else if (ucs) {
+                launch_diag_prep<T>(c.s, blk, lda, kTriNB, UPPER, 1, 0, ucs, c.mp);
             }
+            if (ucs) c.uc_ok[(size_t)(diag_index(c, blk) / kTriNB)] = 1;
             i += d;
             t += d;
         }
@@ -482,7 +548,17 @@ int cup_rec(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& P,
     T* A2 = A + (int64_t)k * lda;
     if (r1 > 0) {
         apply_transpositions(c, A2, lda, m - k, P.data() + p0, r1);          // A2 <- A2 P1^T
-        trsm(c, RIGHT, UPPER, 1, r1, A, lda, A2, lda, m - k);               // G = A21 U1^-1
+        // G = A21 U1^-1, with the cached diagonal-block inverses when every
+        // block of U1 has one
+        const int64_t g0 = diag_index(c, A);
+        double* W1 = (r1 % kTriNB == 0) ? ucache_slot(c, g0) : nullptr;
+        for (int bb = 0; W1 && bb < r1 / kTriNB; ++bb)
+            if ((size_t)(g0 / kTriNB + bb) >= c.uc_ok.size() || !c.uc_ok[(size_t)(g0 / kTriNB + bb)])
+                W1 = nullptr;
+        if (W1)
+            tri_rec(c, SOLVE, RIGHT, UPPER, r1, A, lda, A2, lda, m - k, (const double*)W1);
+        else
+            trsm(c, RIGHT, UPPER, 1, r1, A, lda, A2, lda, m - k);
         if (r1 == n) return r1;
         gemm(c, m - k, n - r1, r1, A2, lda, A + r1, lda, A2 + r1, lda, -1); // H = A22 - G V1
     }

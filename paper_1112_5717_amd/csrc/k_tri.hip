@@ -146,16 +146,28 @@ __device__ void block_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 
 // place (the unit diagonal, if any, is left untouched).  One workgroup of
 // 256 threads per diagonal block; a lower triangle is handled as the
 // transpose of an upper one.
+// An optional second job (A2: one full 64 x 64 block, its own triangle and
+// diagonal kind, output W2) runs as the last workgroup of the same launch.
 template <typename T, bool BIG>
 __global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64_t lda, int n, int uplo,
                                                         int unit, int mode, double* __restrict__ W,
-                                                        ModP mp)
+                                                        ModP mp, T* __restrict__ A2, int uplo2,
+                                                        int unit2, double* __restrict__ W2)
 {
     __shared__ double M[NB][NB + 1];
     __shared__ double X[NB][NB + 1];
     __shared__ double S[NB][NB + 1];
     __shared__ double dinv[NB];
-    const int b = blockIdx.x, o = b * NB, nb = min(NB, n - o), tid = threadIdx.x;
+    int b = blockIdx.x;
+    if (A2 != nullptr && b == (int)gridDim.x - 1) {
+        A = A2;
+        n = NB;
+        uplo = uplo2;
+        unit = unit2;
+        W = W2;
+        b = 0;
+    }
+    const int o = b * NB, nb = min(NB, n - o), tid = threadIdx.x;
     const double P = mp.p, PI = mp.pinv;
     // M = T_bb (upper) or its transpose (lower), identity-padded.  Every
     // address is clamped into the block so the 16 loads of a thread issue
@@ -368,10 +380,25 @@ void launch_diag_prep(hipStream_t s, T* A, int64_t lda, int n, int uplo, int uni
     const int nblk = (mode == 2) ? 1 : (n + NB - 1) / NB;
     if (big_prime(mp))
         hipLaunchKernelGGL((diag_prep_kernel<T, true>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
-                           unit, mode, W, mp);
+                           unit, mode, W, mp, (T*)nullptr, 0, 0, (double*)nullptr);
     else
         hipLaunchKernelGGL((diag_prep_kernel<T, false>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
-                           unit, mode, W, mp);
+                           unit, mode, W, mp, (T*)nullptr, 0, 0, (double*)nullptr);
+    CUP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_diag_prep2(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, double* W,
+                       T* A2, int uplo2, int unit2, double* W2, ModP mp)
+{
+    if (n <= 0) return launch_diag_prep<T>(s, A2, lda, NB, uplo2, unit2, 0, W2, mp);
+    const int nblk = (n + NB - 1) / NB + 1;
+    if (big_prime(mp))
+        hipLaunchKernelGGL((diag_prep_kernel<T, true>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
+                           unit, 0, W, mp, A2, uplo2, unit2, W2);
+    else
+        hipLaunchKernelGGL((diag_prep_kernel<T, false>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
+                           unit, 0, W, mp, A2, uplo2, unit2, W2);
     CUP_HIP(hipGetLastError());
 }
 
@@ -417,6 +444,8 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
 #define CUP_INST(T)                                                                             \
     template void launch_diag_prep<T>(hipStream_t, T*, int64_t, int, int, int, int, double*,    \
                                       ModP);                                                    \
+    template void launch_diag_prep2<T>(hipStream_t, T*, int64_t, int, int, int, double*, T*,    \
+                                       int, int, double*, ModP);                                \
     template void launch_tri_apply<T>(hipStream_t, int, int, const double*, T*, int64_t, int,   \
                                       ModP);                                                    \
     template void launch_trulm_leaf<T>(hipStream_t, int, T*, int64_t, ModP, int64_t);           \
