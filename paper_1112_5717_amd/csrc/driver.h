@@ -555,9 +555,10 @@ int cup_rec(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& P,
         for (int bb = 0; W1 && bb < r1 / kTriNB; ++bb)
             if ((size_t)(g0 / kTriNB + bb) >= c.uc_ok.size() || !c.uc_ok[(size_t)(g0 / kTriNB + bb)])
                 W1 = nullptr;
-        if (W1)
-            tri_rec(c, SOLVE, RIGHT, UPPER, r1, A, lda, A2, lda, m - k, (const double*)W1);
-        else
+        if (W1) {
+            if (!launch_tri_slab<T>(c.s, r1, A, lda, W1, A2, lda, m - k, c.mp))
+                tri_rec(c, SOLVE, RIGHT, UPPER, r1, A, lda, A2, lda, m - k, (const double*)W1);
+        } else
             trsm(c, RIGHT, UPPER, 1, r1, A, lda, A2, lda, m - k);
         if (r1 == n) return r1;
         gemm(c, m - k, n - r1, r1, A2, lda, A + r1, lda, A2 + r1, lda, -1); // H = A22 - G V1

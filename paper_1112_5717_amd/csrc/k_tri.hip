@@ -305,6 +305,115 @@ __global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const 
     }
 }
 
+// Whole right solve X = B U^{-1} for a unit upper U of order n <= 512
+// (n a multiple of 64) whose 64 x 64 diagonal-block inverses W are known:
+// one workgroup per RV rows of B (16 for n <= 512, 8 for n <= 1024, so that
+// the rows fit in LDS), left-looking over the 64-column blocks,
+//     X_l = (B_l - sum_{j<l} X_j U_jl) W_l,
+// with the rows of B in LDS and each 64 x 64 tile of U (or W) staged
+// through LDS.  It replaces the n/64 leaf products and n/64 - 1 recursion
+// products of Algorithm 2 by one launch.  Each thread computes QN of the
+// RV x 64 outputs of a block; a 64-term sum of canonical products is exact
+// for p < 2^23.5 and is reduced after every tile (BIG: after every term).
+constexpr int SLAB_MAX = 1024;
+
+template <typename T, bool BIG, int RV>
+__global__ __launch_bounds__(256) void tri_slab_kernel(int n, const T* __restrict__ U, int64_t ldu,
+                                                       const double* __restrict__ W,
+                                                       T* __restrict__ B, int64_t ldb, int rows,
+                                                       ModP mp)
+{
+    constexpr int NMAX = 8192 / RV;          // 512 or 1024 columns
+    constexpr int TPR = 256 / RV;            // threads per row
+    constexpr int QN = NB / TPR;             // outputs per thread per block
+    __shared__ double Bs[RV][NMAX + 1];
+    __shared__ double Ts[NB][NB + 1];
+    const int tid = threadIdx.x;
+    const double P = mp.p, PI = mp.pinv;
+    const int v0 = blockIdx.x * RV;
+    const int nv = min(RV, rows - v0);
+    const int v = tid / TPR, e0 = tid % TPR;  // row v, outputs e0 + TPR q
+    // the rows of B (addresses clamped; rows past the end are zeros)
+    for (int idx = tid; idx < RV * n; idx += 256) {
+        const int r = idx / n, c = idx % n;
+        const double x = ld_res(B + (int64_t)(v0 + min(r, nv - 1)) * ldb + c);
+        Bs[r][c] = (r < nv) ? x : 0.0;
+    }
+    const int nbk = n / NB;
+    for (int l = 0; l < nbk; ++l) {
+        double acc[QN];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) acc[q] = 0.0;
+        for (int j = 0; j < l; ++j) {
+            __syncthreads();
+            // U_jl (rows 64 j.., columns 64 l..): 16 loads per thread, together
+            double tv[NB * NB / 256];
+#pragma unroll
+            for (int it = 0; it < NB * NB / 256; ++it) {
+                const int idx = tid + 256 * it;
+                tv[it] = ld_res(U + (int64_t)(NB * j + (idx >> 6)) * ldu + NB * l + (idx & 63));
+            }
+#pragma unroll
+            for (int it = 0; it < NB * NB / 256; ++it) {
+                const int idx = tid + 256 * it;
+                Ts[idx >> 6][idx & 63] = tv[it];
+            }
+            __syncthreads();
+            double part[QN];
+#pragma unroll
+            for (int q = 0; q < QN; ++q) part[q] = 0.0;
+#pragma unroll 8
+            for (int s = 0; s < NB; ++s) {
+                const double xv = Bs[v][NB * j + s];
+#pragma unroll
+                for (int q = 0; q < QN; ++q) {
+                    part[q] = fma(xv, Ts[s][e0 + TPR * q], part[q]);
+                    if (BIG) part[q] = mod_red(part[q], P, PI);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < QN; ++q) acc[q] = mod_red(acc[q] + mod_red(part[q], P, PI), P, PI);
+        }
+        __syncthreads();
+        // B_l - sum, then the W_l product
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const double b = Bs[v][NB * l + e0 + TPR * q] - acc[q];
+            Bs[v][NB * l + e0 + TPR * q] = (b < 0.0) ? b + P : b;
+        }
+        double wv[NB * NB / 256];
+        const double* Wl = W + (size_t)l * NB * NB;
+#pragma unroll
+        for (int it = 0; it < NB * NB / 256; ++it) wv[it] = Wl[tid + 256 * it];
+#pragma unroll
+        for (int it = 0; it < NB * NB / 256; ++it) {
+            const int idx = tid + 256 * it;
+            Ts[idx >> 6][idx & 63] = wv[it];
+        }
+        __syncthreads();
+        double x[QN];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) x[q] = 0.0;
+#pragma unroll 8
+        for (int s = 0; s < NB; ++s) {
+            const double bv = Bs[v][NB * l + s];
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                x[q] = fma(bv, Ts[s][e0 + TPR * q], x[q]);
+                if (BIG) x[q] = mod_red(x[q], P, PI);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QN; ++q) Bs[v][NB * l + e0 + TPR * q] = mod_red(x[q], P, PI);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < RV * n; idx += 256) {
+        const int r = idx / n, c = idx % n;
+        if (r < nv) st_res(B + (int64_t)(v0 + r) * ldb + c, Bs[r][c]);
+    }
+}
+
 // [N\T] <- T N on an nb x nb block (nb <= 64): T unit upper (strict upper
 // part stored), N lower with its diagonal.  Thread j holds column j of N.
 template <typename T, bool BIG>
@@ -418,6 +527,33 @@ void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, in
 }
 
 template <typename T>
+bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double* W, T* B,
+                     int64_t ldb, int rows, ModP mp)
+{
+    if (n <= 0 || n > SLAB_MAX || n % NB != 0 || rows <= 0) return false;
+    const bool big = big_prime(mp);
+    if (n <= 512) {
+        dim3 grid((rows + 15) / 16);
+        if (big)
+            hipLaunchKernelGGL((tri_slab_kernel<T, true, 16>), grid, dim3(256), 0, s, n, U, ldu, W, B,
+                               ldb, rows, mp);
+        else
+            hipLaunchKernelGGL((tri_slab_kernel<T, false, 16>), grid, dim3(256), 0, s, n, U, ldu, W, B,
+                               ldb, rows, mp);
+    } else {
+        dim3 grid((rows + 7) / 8);
+        if (big)
+            hipLaunchKernelGGL((tri_slab_kernel<T, true, 8>), grid, dim3(256), 0, s, n, U, ldu, W, B,
+                               ldb, rows, mp);
+        else
+            hipLaunchKernelGGL((tri_slab_kernel<T, false, 8>), grid, dim3(256), 0, s, n, U, ldu, W, B,
+                               ldb, rows, mp);
+    }
+    CUP_HIP(hipGetLastError());
+    return true;
+}
+
+template <typename T>
 void launch_trulm_leaf(hipStream_t s, int nb, T* A, int64_t lda, ModP mp, int64_t kred)
 {
     (void)kred;
@@ -449,6 +585,8 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
     template void launch_tri_apply<T>(hipStream_t, int, int, const double*, T*, int64_t, int,   \
                                       ModP);                                                    \
     template void launch_trulm_leaf<T>(hipStream_t, int, T*, int64_t, ModP, int64_t);           \
+    template bool launch_tri_slab<T>(hipStream_t, int, const T*, int64_t, const double*, T*,    \
+                                     int64_t, int, ModP);                                       \
     template void launch_negate<T>(hipStream_t, T*, int64_t, int, int, ModP);
 CUP_INST(int64_t)
 CUP_INST(int8_t)

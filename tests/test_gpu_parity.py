@@ -2,7 +2,7 @@
 bit for bit (integer arithmetic in GF(p): the tolerance is zero).
 
 Inputs are seeded (paper_1112_5717_amd.inputs and the structured generator
-of the oracle pins); sizes span several 64-row leaves, 128-column windows
+of the oracle pins); sizes span several 64-row leaves, 64-column windows
 and 128 x 128 ffgemm tiles with ragged tails.
 """
 from __future__ import annotations
@@ -108,6 +108,10 @@ CUP_CASES = [
     (100, 150, 3, None, True), (150, 100, 65521, 40, True), (200, 300, 65521, None, True),
     (257, 129, 127, None, True), (128, 520, 2, None, True), (333, 333, 8388593, None, False),
     (400, 260, 65521, 130, False), (300, 300, 33554393, 250, True), (129, 700, 101, None, True),
+    # full-rank squares: cached diagonal-block inverses and the fused right
+    # solve (orders 64..1024), with a prime past the 64-term bound
+    (1100, 1100, 65521, None, False), (2100, 2100, 33554393, None, False),
+    (1500, 1300, 8388593, None, False), (1088, 1200, 2, None, False),
 ]
 
 
