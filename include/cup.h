@@ -56,6 +56,9 @@ extern "C" {
 #define CUP_SINGULAR 1
 #define CUP_ERR_HIP (-1000)
 #define CUP_ERR_ALLOC (-2000)
+/* An internal consistency check of a kernel failed (a pivot row that a
+ * waiting wave never received); the matrix is then unspecified. */
+#define CUP_ERR_INTERNAL (-3000)
 
 /* Forms of the modular matrix product (ffgemm) used inside every call.
  *   FP64   : FP64 MFMA as an exact integer carrier, any p < 2^26.

@@ -386,6 +386,7 @@ const char* cup_strerror(int status)
     if (status == CUP_OK) return "success";
     if (status == CUP_SINGULAR) return "matrix is singular";
     if (status == CUP_ERR_ALLOC) return "allocation failure";
+    if (status == CUP_ERR_INTERNAL) return "internal kernel check failed";
     if (status <= CUP_ERR_HIP && status > CUP_ERR_ALLOC) return "HIP runtime error";
     switch (status) {
     case -1: return "argument 1 is invalid";

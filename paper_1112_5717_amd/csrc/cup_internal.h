@@ -35,7 +35,7 @@ constexpr int kWin = 64;        // window width of the leaf elimination
 constexpr int kTriNB = 64;      // order of a triangular leaf block
 
 // Stop reasons of the window elimination.
-enum WindowStop { STOP_ROWS = 0, STOP_WINDOW = 1, STOP_ZERO_ROW = 2 };
+enum WindowStop { STOP_ROWS = 0, STOP_WINDOW = 1, STOP_ZERO_ROW = 2, STOP_FAIL = 3 };
 
 // Rows passed by value to the row-move kernel.
 struct MoveList {

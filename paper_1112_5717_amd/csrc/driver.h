@@ -465,6 +465,7 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         if (prof) c.prof->end(c.s);
         const int* h = fetch_small(c, 2 + kLeafRows);
         const int d = h[0], stop = h[1];
+        if (stop == STOP_FAIL) throw CupError{-3000};  // CUP_ERR_INTERNAL
         for (int a = 0; a < d; ++a) {
             int col = h[2 + a];
             if (a == 0 && pending >= 0) col = pending;

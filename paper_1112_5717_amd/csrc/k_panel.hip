@@ -34,7 +34,7 @@ namespace cup {
 
 namespace {
 
-constexpr int WT = 512;             // threads of the window kernel (8 waves)
+constexpr int WT = 1024;            // threads of the window kernel (16 waves)
 constexpr int NWV = WT / 64;        // waves
 constexpr int KPW = kLeafRows / NWV; // tile rows per wave
 
@@ -59,18 +59,34 @@ __device__ __forceinline__ double pick(const double (&v)[WQ][KPW], int k, int q)
     return x;
 }
 
-// Register-resident tile: thread (wave w, lane l) holds rows w + 8k
-// (k = 0..7) of columns l + 64q (q < WQ).  The pivot row and the multiplier
-// column of each step are exchanged through LDS buffers alternating with
-// the step's parity, so one barrier per pivot suffices.
+__device__ __forceinline__ double readlane_d(double x, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Bound on the polls for a pivot row (about 0.1 s): a row that never comes is
+// reported as a failure instead of waiting forever.
+constexpr int kSpinMax = 1 << 22;
+
+// Register-resident tile: thread (wave w, lane l) holds rows w + 16k
+// (k = 0..3) of columns l + 64q (q < WQ).  Each step's pivot row goes to its
+// own LDS slot with a ready flag (release/acquire at workgroup scope): the
+// owner of row a + 1 updates that row first, publishes it, and only then
+// updates its other rows, while every other wave starts step a + 1 as soon
+// as the flag is up.  There is no barrier per step, and no slot is reused
+// within a window.  Each wave keeps its own multipliers (column a of its
+// rows) and applies every column exchange to its own registers.
 template <typename T, int WQ>
 __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t lda, int b, int N,
                                                     int i0, int t0, int wc, ModP mp,
                                                     int* __restrict__ out)
 {
-    __shared__ double rowbuf[2][64 * WQ];
-    __shared__ double colbuf[2][kLeafRows];
-    __shared__ int s_j[2];
+    __shared__ double rowslot[kLeafRows][64 * WQ];
+    __shared__ int s_jv[kLeafRows];
+    __shared__ int s_flag[kLeafRows];
+    __shared__ int s_fail;
     __shared__ int s_swap[kLeafRows];
     __shared__ double s_piv[kLeafRows];
     __shared__ double s_isig[kLeafRows + 1];
@@ -89,12 +105,13 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             const int r = w + NWV * k, c = lane + 64 * q;
             v[q][k] = (r < R && c < wc) ? ld_res(A + (int64_t)(i0 + r) * lda + t0 + c) : 0.0;
         }
+    for (int x = tid; x < kLeafRows; x += WT) s_flag[x] = 0;
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
 
-    // Publish row a (its owner wave: rowbuf and the leftmost nonzero at
-    // positions >= a) and column a (its owner lane in every wave: colbuf)
-    // into the buffers of parity a & 1.
+    // The owner wave of row a publishes it: the row, its leftmost nonzero at
+    // positions >= a (or -1), then the flag.
     auto publish = [&](int a) {
-        const int par = a & 1, qa = a >> 6, la = a & 63;
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
             if (w + NWV * k == a) {
@@ -103,38 +120,57 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 for (int q = WQ - 1; q >= 0; --q) {
                     const int c = lane + 64 * q;
                     const unsigned long long mq = __ballot(c >= a && c < wc && v[q][k] != 0.0);
-                    rowbuf[par][c] = v[q][k];
+                    rowslot[a][c] = v[q][k];
                     if (mq) jj = 64 * q + __ffsll((long long)mq) - 1;
                 }
-                if (lane == 0) s_j[par] = jj;
+                if (lane == 0) {
+                    s_jv[a] = jj;
+                    __hip_atomic_store(&s_flag[a], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
             }
         }
-        if (lane == la) {
+    };
+    // fraction-free update of own row k by pivot a (columns > a)
+    auto update = [&](int k, int a, double piv, double m, const double (&u)[WQ]) {
 #pragma unroll
-            for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = pick(v, k, qa);
+        for (int q = 0; q < WQ; ++q) {
+            const double nq = red_c(fma(piv, v[q][k], -m * u[q]), P, PI);
+            v[q][k] = (lane + 64 * q > a) ? nq : v[q][k];
         }
     };
 
     int d = 0, stop = STOP_ROWS;
     if (R > 0 && wc > 0) publish(0);
-    __syncthreads();
     for (int a = 0;; ++a) {
         if (a >= R) { stop = STOP_ROWS; break; }
         if (a >= wc) { stop = STOP_WINDOW; break; }
-        const int par = a & 1, qa = a >> 6, la = a & 63;
-        // every LDS read of the step issued together (no swap assumed)
-        const int j = s_j[par];
-        double piv = rowbuf[par][a];
+        int f = 0;
+        for (int it = 0; it < kSpinMax; ++it) {
+            f = __hip_atomic_load(&s_flag[a], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (f) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (!f) {
+            if (lane == 0) s_fail = 1;
+            stop = STOP_FAIL;
+            break;
+        }
+        const int qa = a >> 6, la = a & 63;
+        const int j = s_jv[a];
+        if (j < 0) { stop = STOP_ZERO_ROW; break; }
         double u[WQ];
 #pragma unroll
-        for (int q = 0; q < WQ; ++q) u[q] = rowbuf[par][lane + 64 * q];
-        double mlt[KPW];
-#pragma unroll
-        for (int k = 0; k < KPW; ++k) mlt[k] = colbuf[par][w + NWV * k];
-        if (j < 0) { stop = STOP_ZERO_ROW; break; }
+        for (int q = 0; q < WQ; ++q) u[q] = rowslot[a][lane + 64 * q];
+        const double piv = rowslot[a][j];
         if (j != a) {
-            // swap columns a and j: both live in the same lanes of every wave
+            // positions a and j exchange, in the pivot row and in every own row
+            const double ua = rowslot[a][a];
             const int qj = j >> 6, lj = j & 63;
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) {
+                const int c = lane + 64 * q;
+                u[q] = (c == a) ? piv : ((c == j) ? ua : u[q]);
+            }
 #pragma unroll
             for (int k = 0; k < KPW; ++k) {
                 const double ca = pick(v, k, qa);
@@ -147,44 +183,26 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                     if (lane == lj && q == qj) v[q][k] = from_a;
                 }
             }
-            __syncthreads();  // every wave has read the step's buffers
-            if (lane == la) {
-#pragma unroll
-                for (int k = 0; k < KPW; ++k) colbuf[par][w + NWV * k] = pick(v, k, qa);
-            }
-            if (tid == 0) {
-                double x = rowbuf[par][a];
-                rowbuf[par][a] = rowbuf[par][j];
-                rowbuf[par][j] = x;
-            }
-            __syncthreads();
-            piv = rowbuf[par][a];
-#pragma unroll
-            for (int q = 0; q < WQ; ++q) u[q] = rowbuf[par][lane + 64 * q];
-#pragma unroll
-            for (int k = 0; k < KPW; ++k) mlt[k] = colbuf[par][w + NWV * k];
         }
         if (tid == 0) {
             s_swap[a] = j;
             s_piv[a] = mod_red(piv, P, PI);
         }
-        // fraction-free update of rows > a, columns > a: rows skipped per
-        // wave, columns masked per lane
+        double mlt[KPW];
 #pragma unroll
-        for (int k = 0; k < KPW; ++k) {
-            if (w + NWV * k > a) {
+        for (int k = 0; k < KPW; ++k) mlt[k] = readlane_d(pick(v, k, qa), la);
+        // row a + 1 first (then published), then the other own rows > a + 1
 #pragma unroll
-                for (int q = 0; q < WQ; ++q) {
-                    const double nq = red_c(fma(piv, v[q][k], -mlt[k] * u[q]), P, PI);
-                    v[q][k] = (lane + 64 * q > a) ? nq : v[q][k];
-                }
-            }
-        }
-        d = a + 1;
+        for (int k = 0; k < KPW; ++k)
+            if (w + NWV * k == a + 1) update(k, a, piv, mlt[k], u);
         if (a + 1 < R && a + 1 < wc) publish(a + 1);
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KPW; ++k)
+            if (w + NWV * k > a + 1) update(k, a, piv, mlt[k], u);
+        d = a + 1;
     }
     __syncthreads();
+    if (s_fail) stop = STOP_FAIL;
 
     // Sigma_{s+1} = prod_{s' <= s} piv_{s'}: inclusive scan in wave 0.
     if (w == 0) {

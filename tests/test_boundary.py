@@ -58,5 +58,5 @@ def test_argument_validation():
     assert lib.cup_ffgemm(4, 4, 4, fake, 4, fake, 4, fake, 4, 7, 2) == -11
     assert lib.cup_ffgemm(4, 4, 4, fake, 2, fake, 4, fake, 4, 7, 1) == -5
     assert lib.cup_set_form(9) == -1
-    for code in (0, 1, -1, -5, -1001, -2000):
+    for code in (0, 1, -1, -5, -1001, -2000, -3000):
         assert cup.strerror(code)
