@@ -119,8 +119,8 @@ template <typename T>
 void launch_diag_prep2(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, double* W,
                        T* A2, int uplo2, int unit2, double* W2, ModP mp);
 
-// X = B U^{-1} in place for a unit upper U of order n (n <= 1024, a multiple
-// of 64) with its 64 x 64 diagonal-block inverses in W; B is rows x n.
+// X = B U^{-1} in place for an upper U of order n (n <= 512, a multiple of
+// 64) with its 64 x 64 diagonal-block inverses in W; B is rows x n.
 // Returns false (nothing launched) outside those limits.
 template <typename T>
 bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double* W, T* B,

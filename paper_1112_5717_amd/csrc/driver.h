@@ -295,6 +295,10 @@ template <typename T>
 void tri_rec(Ctx& c, int op, int side, int uplo, int n, const T* Tm, int64_t ldt, T* B,
              int64_t ldb, int other, const double* W)
 {
+    // right solves with an upper triangle of order <= 512: one fused launch
+    if (op == SOLVE && side == RIGHT && uplo == UPPER && n > kTriNB &&
+        launch_tri_slab<T>(c.s, n, Tm, ldt, W, B, ldb, other, c.mp))
+        return;
     if (n <= kTriNB) {
         launch_tri_apply<T>(c.s, side, n, W, B, ldb, other, c.mp);
         return;
@@ -556,10 +560,9 @@ int cup_rec(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& P,
         for (int bb = 0; W1 && bb < r1 / kTriNB; ++bb)
             if ((size_t)(g0 / kTriNB + bb) >= c.uc_ok.size() || !c.uc_ok[(size_t)(g0 / kTriNB + bb)])
                 W1 = nullptr;
-        if (W1) {
-            if (!launch_tri_slab<T>(c.s, r1, A, lda, W1, A2, lda, m - k, c.mp))
-                tri_rec(c, SOLVE, RIGHT, UPPER, r1, A, lda, A2, lda, m - k, (const double*)W1);
-        } else
+        if (W1)
+            tri_rec(c, SOLVE, RIGHT, UPPER, r1, A, lda, A2, lda, m - k, (const double*)W1);
+        else
             trsm(c, RIGHT, UPPER, 1, r1, A, lda, A2, lda, m - k);
         if (r1 == n) return r1;
         gemm(c, m - k, n - r1, r1, A2, lda, A + r1, lda, A2 + r1, lda, -1); // H = A22 - G V1

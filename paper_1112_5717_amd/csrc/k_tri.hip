@@ -305,8 +305,8 @@ __global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const 
     }
 }
 
-// Whole right solve X = B U^{-1} for a unit upper U of order n <= 512
-// (n a multiple of 64) whose 64 x 64 diagonal-block inverses W are known:
+// Whole right solve X = B U^{-1} for an upper U of order n <= 512 (n a
+// multiple of 64) whose 64 x 64 diagonal-block inverses W are known:
 // one workgroup per RV rows of B (16 for n <= 512, 8 for n <= 1024, so that
 // the rows fit in LDS), left-looking over the 64-column blocks,
 //     X_l = (B_l - sum_{j<l} X_j U_jl) W_l,
@@ -315,7 +315,8 @@ __global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const 
 // products of Algorithm 2 by one launch.  Each thread computes QN of the
 // RV x 64 outputs of a block; a 64-term sum of canonical products is exact
 // for p < 2^23.5 and is reduced after every tile (BIG: after every term).
-constexpr int SLAB_MAX = 1024;
+constexpr int SLAB_MAX = 1024;   // capacity of the kernel
+constexpr int SLAB_LIMIT = 512;  // largest order sent to it: above, two halves and one product are faster
 
 template <typename T, bool BIG, int RV>
 __global__ __launch_bounds__(256) void tri_slab_kernel(int n, const T* __restrict__ U, int64_t ldu,
@@ -339,26 +340,45 @@ __global__ __launch_bounds__(256) void tri_slab_kernel(int n, const T* __restric
         const double x = ld_res(B + (int64_t)(v0 + min(r, nv - 1)) * ldb + c);
         Bs[r][c] = (r < nv) ? x : 0.0;
     }
+    // Tiles in order: for each block l, U_0l .. U_(l-1)l, then W_l.  The
+    // next tile's 16 values per thread are loaded into registers while the
+    // current one is used.
     const int nbk = n / NB;
+    constexpr int TV = NB * NB / 256;
+    auto fetch = [&](int l, int j, double (&r)[TV]) {
+        if (j < l) {
+#pragma unroll
+            for (int it = 0; it < TV; ++it) {
+                const int idx = tid + 256 * it;
+                r[it] = ld_res(U + (int64_t)(NB * j + (idx >> 6)) * ldu + NB * l + (idx & 63));
+            }
+        } else {
+            const double* Wl = W + (size_t)l * NB * NB;
+#pragma unroll
+            for (int it = 0; it < TV; ++it) r[it] = Wl[tid + 256 * it];
+        }
+    };
+    auto stage = [&](const double (&r)[TV]) {
+        __syncthreads();  // every read of the previous tile is done
+#pragma unroll
+        for (int it = 0; it < TV; ++it) {
+            const int idx = tid + 256 * it;
+            Ts[idx >> 6][idx & 63] = r[it];
+        }
+    };
+    double cur[TV];
+    fetch(0, 0, cur);
+    // the rows of B were loaded by other threads than the ones that update
+    // them below (block 0 has no tile stage before its update)
+    __syncthreads();
     for (int l = 0; l < nbk; ++l) {
         double acc[QN];
 #pragma unroll
         for (int q = 0; q < QN; ++q) acc[q] = 0.0;
         for (int j = 0; j < l; ++j) {
+            stage(cur);
             __syncthreads();
-            // U_jl (rows 64 j.., columns 64 l..): 16 loads per thread, together
-            double tv[NB * NB / 256];
-#pragma unroll
-            for (int it = 0; it < NB * NB / 256; ++it) {
-                const int idx = tid + 256 * it;
-                tv[it] = ld_res(U + (int64_t)(NB * j + (idx >> 6)) * ldu + NB * l + (idx & 63));
-            }
-#pragma unroll
-            for (int it = 0; it < NB * NB / 256; ++it) {
-                const int idx = tid + 256 * it;
-                Ts[idx >> 6][idx & 63] = tv[it];
-            }
-            __syncthreads();
+            fetch(l, j + 1, cur);
             double part[QN];
 #pragma unroll
             for (int q = 0; q < QN; ++q) part[q] = 0.0;
@@ -374,23 +394,15 @@ __global__ __launch_bounds__(256) void tri_slab_kernel(int n, const T* __restric
 #pragma unroll
             for (int q = 0; q < QN; ++q) acc[q] = mod_red(acc[q] + mod_red(part[q], P, PI), P, PI);
         }
-        __syncthreads();
-        // B_l - sum, then the W_l product
+        // B_l - sum (own outputs), then the W_l product
 #pragma unroll
         for (int q = 0; q < QN; ++q) {
             const double b = Bs[v][NB * l + e0 + TPR * q] - acc[q];
             Bs[v][NB * l + e0 + TPR * q] = (b < 0.0) ? b + P : b;
         }
-        double wv[NB * NB / 256];
-        const double* Wl = W + (size_t)l * NB * NB;
-#pragma unroll
-        for (int it = 0; it < NB * NB / 256; ++it) wv[it] = Wl[tid + 256 * it];
-#pragma unroll
-        for (int it = 0; it < NB * NB / 256; ++it) {
-            const int idx = tid + 256 * it;
-            Ts[idx >> 6][idx & 63] = wv[it];
-        }
+        stage(cur);
         __syncthreads();
+        if (l + 1 < nbk) fetch(l + 1, 0, cur);
         double x[QN];
 #pragma unroll
         for (int q = 0; q < QN; ++q) x[q] = 0.0;
@@ -530,7 +542,7 @@ template <typename T>
 bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double* W, T* B,
                      int64_t ldb, int rows, ModP mp)
 {
-    if (n <= 0 || n > SLAB_MAX || n % NB != 0 || rows <= 0) return false;
+    if (n <= 0 || n > SLAB_LIMIT || n % NB != 0 || rows <= 0) return false;
     const bool big = big_prime(mp);
     if (n <= 512) {
         dim3 grid((rows + 15) / 16);
