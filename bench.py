@@ -150,7 +150,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ffgemm_i8_cup8192_gf65521_hbm_tra
 
 def measured_traffic():
     """HBM bytes per launch of the INT8 product kernel from the committed
-    counter summary, or None when the kernel source has changed since."""
+    counter summary, or None when the kernel source or the code that sizes
+    its launches has changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -160,9 +161,11 @@ def measured_traffic():
             if line.startswith(key):
                 vals[key[:-1]] = line[len(key):].strip()
     try:
-        src = os.path.join(ROOT, vals["kernel_source"])
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        return float(vals["traffic_bytes_per_launch"]) if sha == vals["kernel_source_sha256"] else None
+        # the kernel and the dispatch code that sizes its launches, in order
+        h = hashlib.sha256()
+        for rel in vals["kernel_source"].split():
+            h.update(open(os.path.join(ROOT, rel), "rb").read())
+        return float(vals["traffic_bytes_per_launch"]) if h.hexdigest() == vals["kernel_source_sha256"] else None
     except (KeyError, OSError, ValueError):
         return None
 

@@ -315,8 +315,7 @@ __global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const 
 // products of Algorithm 2 by one launch.  Each thread computes QN of the
 // RV x 64 outputs of a block; a 64-term sum of canonical products is exact
 // for p < 2^23.5 and is reduced after every tile (BIG: after every term).
-constexpr int SLAB_MAX = 1024;   // capacity of the kernel
-constexpr int SLAB_LIMIT = 512;  // largest order sent to it: above, two halves and one product are faster
+constexpr int SLAB_LIMIT = 512;  // largest order sent to the slab kernels (capacity: 1024)
 
 template <typename T, bool BIG, int RV>
 __global__ __launch_bounds__(256) void tri_slab_kernel(int n, const T* __restrict__ U, int64_t ldu,
@@ -423,6 +422,102 @@ __global__ __launch_bounds__(256) void tri_slab_kernel(int n, const T* __restric
     for (int idx = tid; idx < RV * n; idx += 256) {
         const int r = idx / n, c = idx % n;
         if (r < nv) st_res(B + (int64_t)(v0 + r) * ldb + c, Bs[r][c]);
+    }
+}
+
+// The same solve on the FP64 matrix cores, for p < 2^23.5 (a 64-term sum of
+// canonical products is exact).  One workgroup per 16 rows of B; wave w owns
+// columns 16w..16w+15 of every 64-column block and forms its 16 x 16 part of
+// a tile product with 16 v_mfma_f64_16x16x4f64 (K = 4 each).  The U and W
+// tiles go from global memory (every workgroup reads the same ones, so they
+// stay in L2) straight into the B operand, one tile ahead of use.  Solved
+// columns are kept in LDS in A-operand order, entry [s][lane] holding
+// X[lane % 16][4s + lane / 16], so that an operand read is one contiguous
+// 512-byte row; B_l - sum_j X_j U_jl is exchanged the same way before its
+// product with W_l.  Two barriers per 64-column block instead of two per
+// tile, and no LDS traffic for U.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T, int NMAXC>
+__global__ __launch_bounds__(256) void tri_slab_mfma_kernel(int n, const T* __restrict__ U, int64_t ldu,
+                                                            const double* __restrict__ W,
+                                                            T* __restrict__ B, int64_t ldb, int rows,
+                                                            ModP mp)
+{
+    __shared__ double Xa[NMAXC / 4][64];
+    __shared__ double Ea[NB / 4][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int hi = lane >> 4, lo = lane & 15;
+    const double P = mp.p, PI = mp.pinv;
+    const int v0 = blockIdx.x * 16;
+    const int nbk = n / NB;
+    // Result layout: this lane holds rows v0 + hi + 4e (e = 0..3) of column
+    // 16w + lo of a block (rows past the end are clamped and not stored).
+    int64_t roff[4];
+    bool rok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = v0 + hi + 4 * e;
+        rok[e] = r < rows;
+        roff[e] = (int64_t)min(r, rows - 1) * ldb;
+    }
+    // ... and its place in A-operand order: slot 4w + lo/4, lane hi + 4e + 16 (lo % 4)
+    const int es = 4 * w + (lo >> 2);
+    const int el = hi + 16 * (lo & 3);
+    // Tile stream: for each block l, U_0l .. U_(l-1)l, then W_l; this lane's
+    // B-operand entries are rows 4ks + hi, column 16w + lo of the tile.
+    auto fetch = [&](int l, int j, double (&r)[16]) {
+        if (j < l) {
+            const T* src = U + (int64_t)(NB * j + hi) * ldu + NB * l + 16 * w + lo;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) r[ks] = ld_res(src + (int64_t)(4 * ks) * ldu);
+        } else {
+            const double* src = W + (size_t)l * NB * NB + hi * NB + 16 * w + lo;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) r[ks] = src[4 * ks * NB];
+        }
+    };
+    double cur[16], nxt[16];
+    fetch(0, 0, cur);
+    for (int l = 0; l < nbk; ++l) {
+        const int col = NB * l + 16 * w + lo;
+        double b[4], tot[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            b[e] = ld_res(B + roff[e] + col);
+            tot[e] = 0.0;
+        }
+        for (int j = 0; j < l; ++j) {
+            fetch(l, j + 1, nxt);
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xa[16 * j + ks][lane], cur[ks], acc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tot[e] += mod_red(acc[e], P, PI);
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) cur[ks] = nxt[ks];
+        }
+        if (l + 1 < nbk) fetch(l + 1, 0, nxt);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double t = b[e] - mod_red(tot[e], P, PI);
+            Ea[es][el + 4 * e] = (t < 0.0) ? t + P : t;
+        }
+        __syncthreads();
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ea[ks][lane], cur[ks], acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double x = mod_red(acc[e], P, PI);
+            if (rok[e]) st_res(B + roff[e] + col, x);
+            Xa[16 * l + es][el + 4 * e] = x;
+        }
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) cur[ks] = nxt[ks];
+        __syncthreads();
     }
 }
 
@@ -544,22 +639,23 @@ bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double
 {
     if (n <= 0 || n > SLAB_LIMIT || n % NB != 0 || rows <= 0) return false;
     const bool big = big_prime(mp);
-    if (n <= 512) {
+    if (!big) {
         dim3 grid((rows + 15) / 16);
-        if (big)
-            hipLaunchKernelGGL((tri_slab_kernel<T, true, 16>), grid, dim3(256), 0, s, n, U, ldu, W, B,
+        if (n <= 256)
+            hipLaunchKernelGGL((tri_slab_mfma_kernel<T, 256>), grid, dim3(256), 0, s, n, U, ldu, W, B,
+                               ldb, rows, mp);
+        else if (n <= 512)
+            hipLaunchKernelGGL((tri_slab_mfma_kernel<T, 512>), grid, dim3(256), 0, s, n, U, ldu, W, B,
                                ldb, rows, mp);
         else
-            hipLaunchKernelGGL((tri_slab_kernel<T, false, 16>), grid, dim3(256), 0, s, n, U, ldu, W, B,
+            hipLaunchKernelGGL((tri_slab_mfma_kernel<T, 1024>), grid, dim3(256), 0, s, n, U, ldu, W, B,
                                ldb, rows, mp);
+    } else if (n <= 512) {
+        hipLaunchKernelGGL((tri_slab_kernel<T, true, 16>), dim3((rows + 15) / 16), dim3(256), 0, s, n, U,
+                           ldu, W, B, ldb, rows, mp);
     } else {
-        dim3 grid((rows + 7) / 8);
-        if (big)
-            hipLaunchKernelGGL((tri_slab_kernel<T, true, 8>), grid, dim3(256), 0, s, n, U, ldu, W, B,
-                               ldb, rows, mp);
-        else
-            hipLaunchKernelGGL((tri_slab_kernel<T, false, 8>), grid, dim3(256), 0, s, n, U, ldu, W, B,
-                               ldb, rows, mp);
+        hipLaunchKernelGGL((tri_slab_kernel<T, true, 8>), dim3((rows + 7) / 8), dim3(256), 0, s, n, U,
+                           ldu, W, B, ldb, rows, mp);
     }
     CUP_HIP(hipGetLastError());
     return true;
