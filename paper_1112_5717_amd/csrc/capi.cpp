@@ -21,6 +21,12 @@ struct Global {
     int form = FORM_AUTO;
     int* d_small = nullptr;
     int* h_small = nullptr;
+    // Result words of the window kernel in mapped, coherent host memory (kept
+    // until the process ends: GPU writes to it may still be in flight when a
+    // call fails), their device address, and the last sequence number used.
+    unsigned long long* h_mail = nullptr;
+    unsigned long long* d_mail = nullptr;
+    unsigned mail_seq = 0;
     int* d_list = nullptr;
     size_t list_cap = 0;  // ints
     int* d_order = nullptr;  // processing order of the batched entry point
@@ -69,6 +75,19 @@ void ensure_small(Global& g)
             g.h_small = nullptr;
             throw CupError{CUP_ERR_ALLOC};
         }
+    }
+    if (!g.h_mail) {
+        const size_t bytes = sizeof(unsigned long long) * (2 + kLeafRows);
+        unsigned long long* h = nullptr;
+        if (hipHostMalloc((void**)&h, bytes,
+                          hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable) !=
+            hipSuccess)
+            throw CupError{CUP_ERR_ALLOC};
+        std::memset(h, 0, bytes);
+        unsigned long long* d = nullptr;
+        if (hipHostGetDevicePointer((void**)&d, h, 0) != hipSuccess || !d) throw CupError{CUP_ERR_ALLOC};
+        g.h_mail = h;
+        g.d_mail = d;
     }
 }
 
@@ -149,6 +168,9 @@ Ctx make_ctx(Global& g, int64_t p, int form)
     c.form = form;
     c.d_small = g.d_small;
     c.h_small = g.h_small;
+    c.mail_h = g.h_mail;
+    c.mail_d = g.d_mail;
+    c.mail_seq = &g.mail_seq;
     c.log = env_flag("CUP_LOG") ? 1 : 0;
     if (const char* v = std::getenv("CUP_I8_MIN_WORK")) c.i8_min_work = std::atof(v);
     c.prof = &g.prof;

@@ -76,10 +76,13 @@ void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, 
                    ModP mp, int alpha, int limb, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Window elimination of a leaf (see k_panel.hip).  Writes d, stop and the
-// chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col).
+// chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col)
+// and, when `mail` is given (mapped host memory), the same values to
+// mail[0], mail[1], mail[2+a] as 64-bit words (seq << 32) | value, so that
+// the host can read them while later launches run.
 template <typename T>
 void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
-                   ModP mp, int* out);
+                   ModP mp, int* out, unsigned long long* mail = nullptr, unsigned seq = 0);
 
 // For each row r in [i0,b): leftmost nonzero column >= t0 (or N), into out[r-i0].
 template <typename T>
@@ -109,7 +112,7 @@ void launch_coltransp(hipStream_t s, T* A, int64_t lda, int rows, const TranspLi
 // block of order n <= 64 in place.
 template <typename T>
 void launch_diag_prep(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, int mode,
-                      double* W, ModP mp);
+                      double* W, ModP mp, const int* guard = nullptr, int expect = 0);
 
 // B <- B W (side 1: B is other x nb) or W B (side 0: B is nb x other).
 // Two inversions in one launch (mode 0): the diagonal blocks of the n x n
@@ -117,7 +120,8 @@ void launch_diag_prep(hipStream_t s, T* A, int64_t lda, int n, int uplo, int uni
 // into W2.
 template <typename T>
 void launch_diag_prep2(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, double* W,
-                       T* A2, int uplo2, int unit2, double* W2, ModP mp);
+                       T* A2, int uplo2, int unit2, double* W2, ModP mp, const int* guard = nullptr,
+                       int expect = 0);
 
 // X = B U^{-1} in place for an upper U of order n (n <= 512, a multiple of
 // 64) with its 64 x 64 diagonal-block inverses in W; B is rows x n.
@@ -128,7 +132,7 @@ bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double
 
 template <typename T>
 void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, int64_t ldb,
-                      int other, ModP mp);
+                      int other, ModP mp, const int* guard = nullptr, int expect = 0);
 
 // [N\T] (N lower with diagonal, T unit upper) <- T.N for an nb x nb block.
 template <typename T>

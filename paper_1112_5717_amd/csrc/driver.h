@@ -107,6 +107,11 @@ struct Ctx {
     int64_t kred = 1;       // canonical products per dot-product reduction
     int* d_small = nullptr; // device results of the leaf kernels
     int* h_small = nullptr; // pinned host mirror
+    // Mapped host words the window kernel posts its result to, their device
+    // address, and the sequence number of the last window launched.
+    unsigned long long* mail_h = nullptr;
+    unsigned long long* mail_d = nullptr;
+    unsigned* mail_seq = nullptr;
     int log = 0;
     double i8_min_work = 1.0e9;  // M N K below which products stay on FP64
     // The matrix being factored (its top-left and leading dimension) and
@@ -186,6 +191,43 @@ inline const int* fetch_small(Ctx& c, int count)
                            hipMemcpyDeviceToHost, c.s));
     CUP_HIP(hipStreamSynchronize(c.s));
     return c.h_small;
+}
+
+// Wait for the window launch tagged `seq` to post its result (d, stop, then
+// d pivot columns) without synchronising the stream, so that launches queued
+// behind it keep the GPU busy meanwhile.  The stream is queried now and then:
+// an error ends the wait with that error, and a drained stream without the
+// words is an internal error.
+inline void await_window(Ctx& c, unsigned seq, int* h)
+{
+    auto wait_word = [&](int k) -> int {
+        unsigned long long v = 0;
+        for (unsigned spin = 1;; ++spin) {
+            v = __atomic_load_n(c.mail_h + k, __ATOMIC_ACQUIRE);
+            if ((unsigned)(v >> 32) == seq) break;
+            if ((spin & 1023u) == 0) {
+                const hipError_t e = hipStreamQuery(c.s);
+                if (e == hipSuccess) {
+                    v = __atomic_load_n(c.mail_h + k, __ATOMIC_ACQUIRE);
+                    if ((unsigned)(v >> 32) == seq) break;
+                    throw CupError{-3000};
+                }
+                if (e != hipErrorNotReady) CUP_HIP(e);
+            }
+            __builtin_ia32_pause();
+        }
+        return (int)(unsigned)(v & 0xffffffffull);
+    };
+    h[0] = wait_word(0);
+    h[1] = wait_word(1);
+    for (int a = 0; a < h[0] && a < kLeafRows; ++a) h[2 + a] = wait_word(2 + a);
+}
+
+inline unsigned next_seq(Ctx& c)
+{
+    unsigned s = ++*c.mail_seq;
+    if (s == 0) s = ++*c.mail_seq;  // 0 is the tag of words never written
+    return s;
 }
 
 inline double* tri_workspace(Ctx& c, int n)
@@ -447,6 +489,51 @@ void apply_transpositions(Ctx& c, T* A, int64_t lda, int rows, const int64_t* pi
 }
 
 // ------------------------------------------------------------- CUP leaf
+// Global diagonal index of a leaf's 64 x 64 pivot block when the leaf is
+// decided by its first window (64 pivots in rows 0..63, which then never
+// move): that block is a diagonal block of U whose inverse is kept for the
+// Schur solves of the ancestors.  -1 otherwise.
+template <typename T>
+int64_t leaf_cache_index(Ctx& c, T* A, int64_t lda, int b, int i, int t, int d)
+{
+    if (!(i == 0 && t == 0 && d == kLeafRows && b == kLeafRows)) return -1;
+    const int64_t g = diag_index(c, A + (int64_t)i * lda + t);
+    return ucache_slot(c, g) ? g : -1;
+}
+
+// The launches after a window that chose d pivots in rows i.. and columns
+// t..t+d-1: the pivot rows' U entries beyond the window (one lower solve with
+// the d x d pivot block, whose inverse is formed first), the update of the
+// rows below, and the inverse of the unit-upper block for the cache.  With
+// `guard`, only for d = b = 64 at (0, 0), every kernel does nothing unless
+// *guard (the count the window leaves on the device) equals d.  Returns the
+// cache index filled, or -1.
+template <typename T>
+int64_t leaf_followup(Ctx& c, T* A, int64_t lda, int b, int N, int i, int t, int wc, int d,
+                      const int* guard)
+{
+    const int tw = t + wc;
+    T* blk = A + (int64_t)i * lda + t;
+    const int64_t g = leaf_cache_index(c, A, lda, b, i, t, d);
+    double* ucs = (g >= 0) ? ucache_slot(c, g) : nullptr;
+    if (tw < N) {
+        double* W = tri_workspace(c, d);
+        if (ucs)
+            launch_diag_prep2<T>(c.s, blk, lda, d, LOWER, 0, W, blk, UPPER, 1, ucs, c.mp, guard, d);
+        else
+            launch_diag_prep<T>(c.s, blk, lda, d, LOWER, 0, 0, W, c.mp, guard, d);
+        // the solve with the d x d lower pivot block (d <= 64: one leaf of
+        // the triangular recursion)
+        launch_tri_apply<T>(c.s, LEFT, d, W, A + (int64_t)i * lda + tw, lda, N - tw, c.mp, guard, d);
+        if (i + d < b)
+            gemm(c, b - i - d, N - tw, d, A + (int64_t)(i + d) * lda + t, lda,
+                 A + (int64_t)i * lda + tw, lda, A + (int64_t)(i + d) * lda + tw, lda, -1);
+    } else if (ucs) {
+        launch_diag_prep<T>(c.s, blk, lda, kTriNB, UPPER, 1, 0, ucs, c.mp, guard, d);
+    }
+    return g;
+}
+
 // Base case over a block of b <= 64 rows (Algorithm 6 with the row recursion
 // unrolled): window eliminations decide the pivots; after each window the
 // pivot rows' U entries beyond the window come from one lower-triangular
@@ -465,9 +552,16 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         const int wc = std::min(kWin, N - t);
         const bool prof = c.prof && c.prof->on;
         if (prof) c.prof->begin(c.s, 1, 0.0, 2.0 * (b - i) * wc * sizeof(T));
-        launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small);
+        const unsigned seq = next_seq(c);
+        launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small, c.mail_d, seq);
         if (prof) c.prof->end(c.s);
-        const int* h = fetch_small(c, 2 + kLeafRows);
+        // The usual outcome of a leaf's first window, 64 pivots, has its
+        // follow-up launched before the count is known, each kernel doing
+        // nothing unless the count the window left in device memory is 64.
+        const bool ahead = (i == 0 && t == 0 && b == kLeafRows && wc == kLeafRows);
+        if (ahead) leaf_followup(c, A, lda, b, N, 0, 0, wc, kLeafRows, c.d_small);
+        int h[2 + kLeafRows];
+        await_window(c, seq, h);
         const int d = h[0], stop = h[1];
         if (stop == STOP_FAIL) throw CupError{-3000};  // CUP_ERR_INTERNAL
         for (int a = 0; a < d; ++a) {
@@ -479,28 +573,10 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         }
         pending = -1;
         if (d > 0) {
-            const int tw = t + wc;
-            // A whole leaf decided by its first window (64 pivots in rows
-            // 0..63, which then never move) sits on the diagonal of U: its
-            // unit-upper 64 x 64 block is inverted in the same launch as the
-            // flush's lower block, for the Schur solves of the ancestors.
-            T* blk = A + (int64_t)i * lda + t;
-            double* ucs = (i == 0 && t == 0 && d == kLeafRows && b == kLeafRows)
-                              ? ucache_slot(c, diag_index(c, blk)) : nullptr;
-            if (tw < N) {
-                double* W = tri_workspace(c, d);
-                if (ucs)
-                    launch_diag_prep2<T>(c.s, blk, lda, d, LOWER, 0, W, blk, UPPER, 1, ucs, c.mp);
-                else
-                    launch_diag_prep<T>(c.s, blk, lda, d, LOWER, 0, 0, W, c.mp);
-                tri_rec(c, SOLVE, LEFT, LOWER, d, blk, lda, A + (int64_t)i * lda + tw, lda, N - tw, W);
-                if (i + d < b)
-                    gemm(c, b - i - d, N - tw, d, A + (int64_t)(i + d) * lda + t, lda,
-                         A + (int64_t)i * lda + tw, lda, A + (int64_t)(i + d) * lda + tw, lda, -1);
-            } else if (ucs) {
-                launch_diag_prep<T>(c.s, blk, lda, kTriNB, UPPER, 1, 0, ucs, c.mp);
-            }
-            if (ucs) c.uc_ok[(size_t)(diag_index(c, blk) / kTriNB)] = 1;
+            const int64_t g = (ahead && d == kLeafRows) ? leaf_cache_index(c, A, lda, b, 0, 0, d)
+                                                        : leaf_followup(c, A, lda, b, N, i, t, wc, d,
+                                                                        (const int*)nullptr);
+            if (g >= 0) c.uc_ok[(size_t)(g / kTriNB)] = 1;
             i += d;
             t += d;
         }

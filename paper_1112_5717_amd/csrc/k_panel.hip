@@ -59,6 +59,15 @@ __device__ __forceinline__ double pick(const double (&v)[WQ][KPW], int k, int q)
     return x;
 }
 
+// One result word for the host: a single 64-bit store, tagged with the
+// launch's sequence number, made at system scope so that it goes to host
+// memory without waiting for the end of the kernel.
+__device__ __forceinline__ void post_word(unsigned long long* w, unsigned seq, int v)
+{
+    __hip_atomic_store(w, ((unsigned long long)seq << 32) | (unsigned)v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __device__ __forceinline__ double readlane_d(double x, int l)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
@@ -81,7 +90,9 @@ constexpr int kSpinMax = 1 << 22;
 template <typename T, int WQ>
 __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t lda, int b, int N,
                                                     int i0, int t0, int wc, ModP mp,
-                                                    int* __restrict__ out)
+                                                    int* __restrict__ out,
+                                                    unsigned long long* __restrict__ mail,
+                                                    unsigned seq)
 {
     __shared__ double rowslot[kLeafRows][64 * WQ];
     __shared__ int s_jv[kLeafRows];
@@ -249,8 +260,15 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     if (tid == 0) {
         out[0] = d;
         out[1] = stop;
+        if (mail) {
+            post_word(mail + 1, seq, stop);
+            post_word(mail, seq, d);
+        }
     }
-    for (int a = tid; a < d; a += WT) out[2 + a] = t0 + s_swap[a];
+    for (int a = tid; a < d; a += WT) {
+        out[2 + a] = t0 + s_swap[a];
+        if (mail) post_word(mail + 2 + a, seq, t0 + s_swap[a]);
+    }
 }
 
 // out[r - i0] = leftmost column >= t0 with a nonzero in row r, or N.
@@ -289,11 +307,11 @@ __global__ void colswap_kernel(T* __restrict__ A, int64_t lda, int rows, int c0,
 
 template <typename T>
 void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
-                   ModP mp, int* out)
+                   ModP mp, int* out, unsigned long long* mail, unsigned seq)
 {
     static_assert(kWin % 64 == 0 && kWin <= 128, "window of 64 or 128 columns");
     hipLaunchKernelGGL((window_kernel<T, kWin / 64>), dim3(1), dim3(WT), 0, s, A, lda, b, N, i0, t0,
-                       wc, mp, out);
+                       wc, mp, out, mail, seq);
     CUP_HIP(hipGetLastError());
 }
 
@@ -317,7 +335,7 @@ void launch_colswap(hipStream_t s, T* A, int64_t lda, int rows, int c0, int c1)
 
 #define CUP_INST(T)                                                                            \
     template void launch_window<T>(hipStream_t, T*, int64_t, int, int, int, int, int, ModP,    \
-                                   int*);                                                      \
+                                   int*, unsigned long long*, unsigned);                       \
     template void launch_row_scan<T>(hipStream_t, const T*, int64_t, int, int, int, int, int*); \
     template void launch_colswap<T>(hipStream_t, T*, int64_t, int, int, int);
 CUP_INST(int64_t)

@@ -152,8 +152,10 @@ template <typename T, bool BIG>
 __global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64_t lda, int n, int uplo,
                                                         int unit, int mode, double* __restrict__ W,
                                                         ModP mp, T* __restrict__ A2, int uplo2,
-                                                        int unit2, double* __restrict__ W2)
+                                                        int unit2, double* __restrict__ W2,
+                                                        const int* __restrict__ guard, int expect)
 {
+    if (guard && *guard != expect) return;  // launched ahead of a pivot count that differs
     __shared__ double M[NB][NB + 1];
     __shared__ double X[NB][NB + 1];
     __shared__ double S[NB][NB + 1];
@@ -232,8 +234,10 @@ constexpr int AV = 16;  // vectors per workgroup
 template <typename T, bool BIG>
 __global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const double* __restrict__ W,
                                                         T* __restrict__ B, int64_t ldb, int other,
-                                                        ModP mp)
+                                                        ModP mp, const int* __restrict__ guard,
+                                                        int expect)
 {
+    if (guard && *guard != expect) return;  // launched ahead of a pivot count that differs
     __shared__ double Ws[NB][NB + 1];
     __shared__ double Bs[AV][NB + 1];
     const int tid = threadIdx.x;
@@ -590,46 +594,46 @@ inline bool big_prime(const ModP& mp) { return mp.p > 11863283.0; }  // 64 (p-1)
 
 template <typename T>
 void launch_diag_prep(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, int mode,
-                      double* W, ModP mp)
+                      double* W, ModP mp, const int* guard, int expect)
 {
     if (n <= 0) return;
     const int nblk = (mode == 2) ? 1 : (n + NB - 1) / NB;
     if (big_prime(mp))
         hipLaunchKernelGGL((diag_prep_kernel<T, true>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
-                           unit, mode, W, mp, (T*)nullptr, 0, 0, (double*)nullptr);
+                           unit, mode, W, mp, (T*)nullptr, 0, 0, (double*)nullptr, guard, expect);
     else
         hipLaunchKernelGGL((diag_prep_kernel<T, false>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
-                           unit, mode, W, mp, (T*)nullptr, 0, 0, (double*)nullptr);
+                           unit, mode, W, mp, (T*)nullptr, 0, 0, (double*)nullptr, guard, expect);
     CUP_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_diag_prep2(hipStream_t s, T* A, int64_t lda, int n, int uplo, int unit, double* W,
-                       T* A2, int uplo2, int unit2, double* W2, ModP mp)
+                       T* A2, int uplo2, int unit2, double* W2, ModP mp, const int* guard, int expect)
 {
-    if (n <= 0) return launch_diag_prep<T>(s, A2, lda, NB, uplo2, unit2, 0, W2, mp);
+    if (n <= 0) return launch_diag_prep<T>(s, A2, lda, NB, uplo2, unit2, 0, W2, mp, guard, expect);
     const int nblk = (n + NB - 1) / NB + 1;
     if (big_prime(mp))
         hipLaunchKernelGGL((diag_prep_kernel<T, true>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
-                           unit, 0, W, mp, A2, uplo2, unit2, W2);
+                           unit, 0, W, mp, A2, uplo2, unit2, W2, guard, expect);
     else
         hipLaunchKernelGGL((diag_prep_kernel<T, false>), dim3(nblk), dim3(256), 0, s, A, lda, n, uplo,
-                           unit, 0, W, mp, A2, uplo2, unit2, W2);
+                           unit, 0, W, mp, A2, uplo2, unit2, W2, guard, expect);
     CUP_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, int64_t ldb, int other,
-                      ModP mp)
+                      ModP mp, const int* guard, int expect)
 {
     if (nb <= 0 || other <= 0) return;
     dim3 grid((other + AV - 1) / AV);
     if (big_prime(mp))
         hipLaunchKernelGGL((tri_apply_kernel<T, true>), grid, dim3(256), 0, s, side, nb, W, B, ldb,
-                           other, mp);
+                           other, mp, guard, expect);
     else
         hipLaunchKernelGGL((tri_apply_kernel<T, false>), grid, dim3(256), 0, s, side, nb, W, B, ldb,
-                           other, mp);
+                           other, mp, guard, expect);
     CUP_HIP(hipGetLastError());
 }
 
@@ -687,11 +691,11 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
 
 #define CUP_INST(T)                                                                             \
     template void launch_diag_prep<T>(hipStream_t, T*, int64_t, int, int, int, int, double*,    \
-                                      ModP);                                                    \
+                                      ModP, const int*, int);                                   \
     template void launch_diag_prep2<T>(hipStream_t, T*, int64_t, int, int, int, double*, T*,    \
-                                       int, int, double*, ModP);                                \
+                                       int, int, double*, ModP, const int*, int);               \
     template void launch_tri_apply<T>(hipStream_t, int, int, const double*, T*, int64_t, int,   \
-                                      ModP);                                                    \
+                                      ModP, const int*, int);                                   \
     template void launch_trulm_leaf<T>(hipStream_t, int, T*, int64_t, ModP, int64_t);           \
     template bool launch_tri_slab<T>(hipStream_t, int, const T*, int64_t, const double*, T*,    \
                                      int64_t, int, ModP);                                       \
