@@ -59,6 +59,16 @@ __device__ __forceinline__ double pick(const double (&v)[WQ][KPW], int k, int q)
     return x;
 }
 
+// u[q] for a wave-uniform q
+template <int WQ>
+__device__ __forceinline__ double pick1(const double (&u)[WQ], int q)
+{
+    double x = u[0];
+#pragma unroll
+    for (int e = 1; e < WQ; ++e) x = (q == e) ? u[e] : x;
+    return x;
+}
+
 // One result word for the host: a single 64-bit store, tagged with the
 // launch's sequence number, made at system scope so that it goes to host
 // memory without waiting for the end of the kernel.
@@ -79,14 +89,22 @@ __device__ __forceinline__ double readlane_d(double x, int l)
 // reported as a failure instead of waiting forever.
 constexpr int kSpinMax = 1 << 22;
 
-// Register-resident tile: thread (wave w, lane l) holds rows w + 16k
-// (k = 0..3) of columns l + 64q (q < WQ).  Each step's pivot row goes to its
-// own LDS slot with a ready flag (release/acquire at workgroup scope): the
-// owner of row a + 1 updates that row first, publishes it, and only then
-// updates its other rows, while every other wave starts step a + 1 as soon
-// as the flag is up.  There is no barrier per step, and no slot is reused
-// within a window.  Each wave keeps its own multipliers (column a of its
-// rows) and applies every column exchange to its own registers.
+// Register-resident tile: thread (wave w, lane l) holds the consecutive rows
+// KPW w + k (k < KPW) of columns l + 64q (q < WQ).  So the pivot of step a + 1
+// usually comes from the same wave as that of step a, and a wave takes its
+// own KPW steps without waiting on anyone: leftmost nonzero by ballot, pivot
+// and multipliers by readlane, update of its later rows in registers.  The
+// multiplier of each row at each step (its frozen C entry) is copied aside
+// in registers, so the update itself runs on every lane without a select
+// (entries left of the pivot become don't-care values in (-p, p)).  Each
+// pivot row goes to its own LDS slot; its pivot column, written last with
+// release order into a slot that holds -2 until then, is the ready flag.
+// The slot of a wave's row is released at the start of the wave's next step
+// (its writes have long completed by then), that of its last row at once.
+// The waves below follow the slots in order, applying every pivot to their
+// rows as it arrives; a wave whose rows are all pivots stops following and
+// applies the later column exchanges after the final barrier.  No barrier
+// per step, and no slot is reused within a window.
 template <typename T, int WQ>
 __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t lda, int b, int N,
                                                     int i0, int t0, int wc, ModP mp,
@@ -95,9 +113,9 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                                                     unsigned seq)
 {
     __shared__ double rowslot[kLeafRows][64 * WQ];
-    __shared__ int s_jv[kLeafRows];
-    __shared__ int s_flag[kLeafRows];
+    __shared__ int s_jv[kLeafRows];              // pivot column of step a; -2 until published
     __shared__ int s_fail;
+    __shared__ int s_d;  // pivots found (the step of a zero row, else min(rows, window))
     __shared__ int s_swap[kLeafRows];
     __shared__ double s_piv[kLeafRows];
     __shared__ double s_isig[kLeafRows + 1];
@@ -106,118 +124,153 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
     const int R = b - i0;
+    const int aend = max(0, min(R, wc));  // steps that can have a pivot
     const double P = mp.p, PI = mp.pinv;
 
     double v[WQ][KPW];
+    double cm[WQ][KPW];  // multipliers: row k's value at column a, kept at lane a
 #pragma unroll
     for (int q = 0; q < WQ; ++q)
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
-            const int r = w + NWV * k, c = lane + 64 * q;
+            const int r = KPW * w + k, c = lane + 64 * q;
             v[q][k] = (r < R && c < wc) ? ld_res(A + (int64_t)(i0 + r) * lda + t0 + c) : 0.0;
+            cm[q][k] = 0.0;
         }
-    for (int x = tid; x < kLeafRows; x += WT) s_flag[x] = 0;
-    if (tid == 0) s_fail = 0;
+    for (int x = tid; x < kLeafRows; x += WT) s_jv[x] = -2;
+    if (tid == 0) {
+        s_fail = 0;
+        s_d = aend;
+    }
     __syncthreads();
 
-    // The owner wave of row a publishes it: the row, its leftmost nonzero at
-    // positions >= a (or -1), then the flag.
-    auto publish = [&](int a) {
+    const int own0 = KPW * w;
+    auto release = [&](int a, int j) {
+        if (lane == 0) __hip_atomic_store(&s_jv[a], j, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    // columns a and j (> a) exchange in every own row
+    auto swap_cols = [&](int a, int j) {
+        const int qa = a >> 6, la = a & 63, qj = j >> 6, lj = j & 63;
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
-            if (w + NWV * k == a) {
-                int jj = -1;
+            const double from_j = __shfl(pick(v, k, qj), lj, 64);
+            const double from_a = __shfl(pick(v, k, qa), la, 64);
 #pragma unroll
-                for (int q = WQ - 1; q >= 0; --q) {
-                    const int c = lane + 64 * q;
-                    const unsigned long long mq = __ballot(c >= a && c < wc && v[q][k] != 0.0);
-                    rowslot[a][c] = v[q][k];
-                    if (mq) jj = 64 * q + __ffsll((long long)mq) - 1;
-                }
-                if (lane == 0) {
-                    s_jv[a] = jj;
-                    __hip_atomic_store(&s_flag[a], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
+            for (int q = 0; q < WQ; ++q) {
+                if (lane == la && q == qa) v[q][k] = from_j;
+                if (lane == lj && q == qj) v[q][k] = from_a;
             }
         }
     };
-    // fraction-free update of own row k by pivot a (columns > a)
-    auto update = [&](int k, int a, double piv, double m, const double (&u)[WQ]) {
+    // fraction-free update of own row k by pivot row u of step a (the
+    // multiplier is kept first; it is not on the update's dependency chain)
+    auto update = [&](int k, int a, double piv, const double (&u)[WQ]) {
+        const double m = readlane_d(pick(v, k, a >> 6), a & 63);
 #pragma unroll
         for (int q = 0; q < WQ; ++q) {
-            const double nq = red_c(fma(piv, v[q][k], -m * u[q]), P, PI);
-            v[q][k] = (lane + 64 * q > a) ? nq : v[q][k];
+            cm[q][k] = (lane + 64 * q == a) ? v[q][k] : cm[q][k];
+            v[q][k] = red_c(fma(piv, v[q][k], -m * u[q]), P, PI);
         }
     };
 
-    int d = 0, stop = STOP_ROWS;
-    if (R > 0 && wc > 0) publish(0);
-    for (int a = 0;; ++a) {
-        if (a >= R) { stop = STOP_ROWS; break; }
-        if (a >= wc) { stop = STOP_WINDOW; break; }
-        int f = 0;
+    // Steps of the waves above: follow them in order (rows past the block
+    // need no pivots; rows past the window need all of them).
+    const int follow_end = (own0 < R) ? min(own0, aend) : 0;
+    bool stopped = false;
+    for (int a = 0; a < follow_end; ++a) {
+        int j = -2;
         for (int it = 0; it < kSpinMax; ++it) {
-            f = __hip_atomic_load(&s_flag[a], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (f) break;
+            j = __hip_atomic_load(&s_jv[a], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (j != -2) break;
             __builtin_amdgcn_s_sleep(1);
         }
-        if (!f) {
+        j = __builtin_amdgcn_readfirstlane(j);
+        if (j == -2) {
             if (lane == 0) s_fail = 1;
-            stop = STOP_FAIL;
+            stopped = true;
             break;
         }
-        const int qa = a >> 6, la = a & 63;
-        const int j = s_jv[a];
-        if (j < 0) { stop = STOP_ZERO_ROW; break; }
+        if (j < 0) {
+            stopped = true;
+            break;
+        }
         double u[WQ];
 #pragma unroll
         for (int q = 0; q < WQ; ++q) u[q] = rowslot[a][lane + 64 * q];
-        const double piv = rowslot[a][j];
-        if (j != a) {
-            // positions a and j exchange, in the pivot row and in every own row
-            const double ua = rowslot[a][a];
-            const int qj = j >> 6, lj = j & 63;
+        const double piv = readlane_d(pick1(u, a >> 6), a & 63);
+        if (j != a) swap_cols(a, j);
+#pragma unroll
+        for (int k = 0; k < KPW; ++k) update(k, a, piv, u);
+    }
+    // Own steps.
+    if (!stopped) {
+        int pend_a = -1, pend_j = 0;  // a published row whose slot is not released yet
+#pragma unroll
+        for (int k = 0; k < KPW; ++k) {
+            const int a = own0 + k;
+            if (a >= aend) break;
+            int j = -1;
+#pragma unroll
+            for (int q = WQ - 1; q >= 0; --q) {
+                const int c = lane + 64 * q;
+                const unsigned long long mq = __ballot(c >= a && c < wc && v[q][k] != 0.0);
+                if (mq) j = 64 * q + __ffsll((long long)mq) - 1;
+            }
+            if (pend_a >= 0) {
+                release(pend_a, pend_j);
+                pend_a = -1;
+            }
+            if (j < 0) {  // zero residual on the window: the phase ends at a
+                if (lane == 0) s_d = a;
+                release(a, -1);
+                break;
+            }
+            if (j != a) swap_cols(a, j);
+            double u[WQ];
 #pragma unroll
             for (int q = 0; q < WQ; ++q) {
-                const int c = lane + 64 * q;
-                u[q] = (c == a) ? piv : ((c == j) ? ua : u[q]);
+                u[q] = v[q][k];
+                rowslot[a][lane + 64 * q] = u[q];
+            }
+            const double piv = readlane_d(pick1(u, a >> 6), a & 63);
+            if (lane == 0) {
+                s_swap[a] = j;
+                s_piv[a] = piv;
             }
 #pragma unroll
-            for (int k = 0; k < KPW; ++k) {
-                const double ca = pick(v, k, qa);
-                const double cj = pick(v, k, qj);
-                const double from_j = __shfl(cj, lj, 64);
-                const double from_a = __shfl(ca, la, 64);
-#pragma unroll
-                for (int q = 0; q < WQ; ++q) {
-                    if (lane == la && q == qa) v[q][k] = from_j;
-                    if (lane == lj && q == qj) v[q][k] = from_a;
-                }
+            for (int k2 = k + 1; k2 < KPW; ++k2) update(k2, a, piv, u);
+            if (k + 1 < KPW && a + 1 < aend) {
+                pend_a = a;
+                pend_j = j;
+            } else {
+                release(a, j);
             }
         }
-        if (tid == 0) {
-            s_swap[a] = j;
-            s_piv[a] = mod_red(piv, P, PI);
-        }
-        double mlt[KPW];
-#pragma unroll
-        for (int k = 0; k < KPW; ++k) mlt[k] = readlane_d(pick(v, k, qa), la);
-        // row a + 1 first (then published), then the other own rows > a + 1
-#pragma unroll
-        for (int k = 0; k < KPW; ++k)
-            if (w + NWV * k == a + 1) update(k, a, piv, mlt[k], u);
-        if (a + 1 < R && a + 1 < wc) publish(a + 1);
-#pragma unroll
-        for (int k = 0; k < KPW; ++k)
-            if (w + NWV * k > a + 1) update(k, a, piv, mlt[k], u);
-        d = a + 1;
     }
     __syncthreads();
+    const int d = s_d;
+    int stop = (d < aend) ? STOP_ZERO_ROW : ((R <= wc) ? STOP_ROWS : STOP_WINDOW);
     if (s_fail) stop = STOP_FAIL;
+    // column exchanges of the steps after this wave's rows (rows that
+    // followed every step have them already)
+    if (stop != STOP_FAIL && own0 < R && own0 + KPW <= aend) {
+        const int a0 = own0 + KPW;
+        for (int base = a0; base < d; base += 64) {
+            const int a = base + lane;
+            const bool sw = a < d && s_swap[min(a, kLeafRows - 1)] != a;
+            unsigned long long mask = __ballot(sw);
+            while (mask) {
+                const int x = __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                const int aa = base + x;
+                swap_cols(aa, __builtin_amdgcn_readfirstlane(s_swap[aa]));
+            }
+        }
+    }
 
     // Sigma_{s+1} = prod_{s' <= s} piv_{s'}: inclusive scan in wave 0.
     if (w == 0) {
-        double x = (lane < d) ? s_piv[lane] : 1.0;
+        double x = (lane < d) ? mod_red(s_piv[lane], P, PI) : 1.0;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             double o = __shfl_up(x, off, 64);
@@ -238,11 +291,15 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     for (int q = 0; q < WQ; ++q)
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
-            const int r = w + NWV * k, c = lane + 64 * q;
+            const int r = KPW * w + k, c = lane + 64 * q;
             if (r < R && c < wc) {
-                const int lim = (r + 1 < d) ? r + 1 : d;
-                const double f = (c < lim) ? s_isig[c] : ((r < d) ? s_ipiv[r] : s_isig[d]);
-                st_res(A + (int64_t)(i0 + r) * lda + t0 + c, mod_mul(v[q][k], f, P, PI));
+                // C below the diagonal from the kept multipliers (divided by
+                // Sigma_c), the pivot itself (Sigma_c), the U part of a pivot
+                // row (its pivot), or a residual entry (Sigma_d)
+                const bool low = c < r && c < d;
+                const double x = low ? cm[q][k] : v[q][k];
+                const double f = (c <= r && c < d) ? s_isig[c] : ((r < d) ? s_ipiv[r] : s_isig[d]);
+                st_res(A + (int64_t)(i0 + r) * lda + t0 + c, mod_mul(x, f, P, PI));
             }
         }
     // the same column swaps on the leaf rows above the window block
