@@ -50,7 +50,7 @@ __device__ void load_triangle(double (*M)[NB + 1], const T* A, int64_t lda, int 
 // Column j of the inverse of the triangle in M (solves M x = e_j) for
 // p >= 2^23.5: rolled loops, the column in LDS (X[.][j]), the partial sum
 // reduced after every product.
-__device__ void inverse_column_big(const double (*M)[NB + 1], const double* dinv, int uplo,
+__device__ __forceinline__ void inverse_column_big(const double (*M)[NB + 1], const double* dinv, int uplo,
                                    int j, double (*X)[NB + 1], double P, double PI)
 {
     for (int i = 0; i < NB; ++i) X[i][j] = 0.0;
@@ -79,64 +79,87 @@ __device__ __forceinline__ double red_near(double x, double p, double pinv)
 
 __device__ __forceinline__ double canon(double x, double p) { return (x < 0.0) ? x + p : x; }
 
-// Inverse of the upper triangle held in M (64 x 64, identity-padded), into X,
-// by 16 x 16 blocks: the four diagonal blocks are inverted column-parallel
-// (a chain of 16 steps), then the off-diagonal blocks follow by increasing
-// block distance d = b - a:  X_ab = -D_a (sum_{a < k <= b} M_ak X_kb).
-// 256 threads.  X and S hold residues in (-p, p); every product is below
-// p^2 and a sum of at most 48 of them stays exact for p < 2^23.5.  Sums run
-// in four independent partial accumulators to shorten the dependent chains.
-__device__ void block_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 1],
-                                    double (*S)[NB + 1], const double* dinv, int unit, double P,
-                                    double PI)
+// Inverse of a unit upper triangle U (64 x 64; its strict upper part in M),
+// into X, by 16 x 16 blocks.  The four diagonal blocks are inverted
+// column-parallel by wave 0 (lane 16a + j solves for column j of block a,
+// with the block's entries of U loaded into registers first, so each of the
+// 16 steps is one rounding and one fused multiply-add).  The off-diagonal
+// blocks follow by increasing block distance on the FP64 matrix cores, one
+// block per wave:  X_ab = -X_aa (sum_{a<k<=b} U_ak X_kb),  each 16 x 16 x 16
+// product four v_mfma_f64_16x16x4f64.  The partial sum's result layout (lane
+// l holds rows l/16 + 4e of column l%16) is already the B operand of the
+// second product, so nothing moves between the two.  Run by the four waves
+// wbase..wbase+3 of the workgroup (every thread takes the barriers); entries
+// stay in (-p, p), so a sum of at most 48 products is exact for p < 2^23.5.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void unit_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 1], double P,
+                                   double PI, int wbase = 0)
 {
-    const int tid = threadIdx.x;
-    if (tid < NB) {
-        const int a = tid >> 4, j = tid & 15, o = 16 * a;  // column o + j of block a
+    const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) - wbase;
+    const int hi = lane >> 4, lo = lane & 15;
+    if (w == 0) {
+        const int a = lane >> 4, j = lane & 15, o = 16 * a;
+        // Column i of the block (rows above the diagonal) is loaded three
+        // steps before it is used, so that the chain need not wait on LDS.
+        double u[16][16];
+        auto fetch = [&](int i) {
+#pragma unroll
+            for (int t = 0; t < 15; ++t)
+                if (t < i) u[t][i] = M[o + t][o + i];
+        };
+        fetch(15);
+        fetch(14);
+        fetch(13);
         double acc[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[i] = (i == j) ? 1.0 : 0.0;
 #pragma unroll
         for (int i = 15; i >= 0; --i) {
-            const double r = red_near(acc[i], P, PI);
-            const double x = unit ? r : red_near(r * dinv[o + i], P, PI);
+            if (i >= 4) fetch(i - 3);
+            const double x = red_near(acc[i], P, PI);
             X[o + i][o + j] = x;
 #pragma unroll
-            for (int t = 0; t < i; ++t) acc[t] = fma(M[o + t][o + i], -x, acc[t]);
+            for (int t = 0; t < i; ++t) acc[t] = fma(u[t][i], -x, acc[t]);
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            for (int b = 0; b < 4; ++b)
-                if (b != a) X[o + i][16 * b + j] = 0.0;
     }
+    // blocks below the diagonal are zero
+    if (w >= 0 && w < 4)
+        for (int idx = tid - 64 * wbase; idx < NB * NB; idx += 256) {
+            const int i = idx >> 6, s = idx & 63;
+            if ((s >> 4) < (i >> 4)) X[i][s] = 0.0;
+        }
     __syncthreads();
-    // every loop below has constant bounds once d is unrolled: thread tid
-    // owns element (i, j) = (tid / 16, tid % 16) of each block (a, a + d)
-    const int i = tid >> 4, j = tid & 15;
 #pragma unroll
     for (int d = 1; d < 4; ++d) {
-        // S_ab = sum_{k=a+1..b} M_ak X_kb
+        if (w >= 0 && w + d < 4) {
+            const int a = w, b = w + d;
+            double ma[3][4], xb[3][4], xa[4];
 #pragma unroll
-        for (int a = 0; a + d < 4; ++a) {
-            const int b = a + d;
-            double pa[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < d; ++k)
 #pragma unroll
-            for (int kb = a + 1; kb <= b; ++kb)
+                for (int ks = 0; ks < 4; ++ks) {
+                    ma[k][ks] = M[16 * a + lo][16 * (a + 1 + k) + 4 * ks + hi];
+                    xb[k][ks] = X[16 * (a + 1 + k) + 4 * ks + hi][16 * b + lo];
+                }
 #pragma unroll
-                for (int s = 0; s < 16; ++s)
-                    pa[s & 3] = fma(M[16 * a + i][16 * kb + s], X[16 * kb + s][16 * b + j], pa[s & 3]);
-            S[16 * a + i][16 * b + j] = red_near((pa[0] + pa[1]) + (pa[2] + pa[3]), P, PI);
-        }
-        __syncthreads();
-        // X_ab = -D_a S_ab
+            for (int ks = 0; ks < 4; ++ks) xa[ks] = X[16 * a + lo][16 * a + 4 * ks + hi];
+            __builtin_amdgcn_sched_barrier(0);  // operands loaded before the products
+            v4d sacc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int a = 0; a + d < 4; ++a) {
-            const int b = a + d;
-            double pa[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < d; ++k)
 #pragma unroll
-            for (int s = 0; s < 16; ++s)
-                pa[s & 3] = fma(X[16 * a + i][16 * a + s], S[16 * a + s][16 * b + j], pa[s & 3]);
-            X[16 * a + i][16 * b + j] = -red_near((pa[0] + pa[1]) + (pa[2] + pa[3]), P, PI);
+                for (int ks = 0; ks < 4; ++ks)
+                    sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[k][ks], xb[k][ks], sacc, 0, 0, 0);
+            double sv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sv[e] = red_near(sacc[e], P, PI);
+            v4d xacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                xacc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks], sv[ks], xacc, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) X[16 * a + hi + 4 * e][16 * b + lo] = -red_near(xacc[e], P, PI);
         }
         __syncthreads();
     }
@@ -158,7 +181,6 @@ __global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64
     if (guard && *guard != expect) return;  // launched ahead of a pivot count that differs
     __shared__ double M[NB][NB + 1];
     __shared__ double X[NB][NB + 1];
-    __shared__ double S[NB][NB + 1];
     __shared__ double dinv[NB];
     int b = blockIdx.x;
     if (A2 != nullptr && b == (int)gridDim.x - 1) {
@@ -207,7 +229,38 @@ __global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64
         if (tid < NB) inverse_column_big(M, dinv, 0, tid, X, P, PI);
         __syncthreads();
     } else {
-        block_upper_inverse(M, X, S, dinv, unit, P, PI);
+        // T = D T' with T' unit (rows scaled by the diagonal's inverses), so
+        // T^{-1} = T'^{-1} D^{-1}: the unit inverse, then its columns scaled
+        if (!unit) {
+            double mv[NB * NB / 256];
+#pragma unroll
+            for (int it = 0; it < NB * NB / 256; ++it) {
+                const int idx = tid + 256 * it, i = idx >> 6, s2 = idx & 63;
+                mv[it] = red_near(M[i][s2] * dinv[i], P, PI);
+            }
+#pragma unroll
+            for (int it = 0; it < NB * NB / 256; ++it) {
+                const int idx = tid + 256 * it, i = idx >> 6, s2 = idx & 63;
+                if (s2 > i) M[i][s2] = mv[it];
+            }
+            __syncthreads();
+        }
+        unit_upper_inverse(M, X, P, PI);
+        if (!unit) {
+            double xv[NB * NB / 256];
+#pragma unroll
+            for (int it = 0; it < NB * NB / 256; ++it) {
+                const int idx = tid + 256 * it, i = idx >> 6, s2 = idx & 63;
+                xv[it] = red_near(X[i][s2] * dinv[s2], P, PI);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < NB * NB / 256; ++it) {
+                const int idx = tid + 256 * it, i = idx >> 6, s2 = idx & 63;
+                X[i][s2] = xv[it];
+            }
+            __syncthreads();
+        }
     }
     // X holds the inverse of the upper form; the lower inverse is its transpose
     if (mode == 0) {
@@ -440,7 +493,6 @@ __global__ __launch_bounds__(256) void tri_slab_kernel(int n, const T* __restric
 // 512-byte row; B_l - sum_j X_j U_jl is exchanged the same way before its
 // product with W_l.  Two barriers per 64-column block instead of two per
 // tile, and no LDS traffic for U.
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <typename T, int NMAXC>
 __global__ __launch_bounds__(256) void tri_slab_mfma_kernel(int n, const T* __restrict__ U, int64_t ldu,
