@@ -18,6 +18,10 @@ struct ModP {
 
 enum Form { FORM_AUTO = 0, FORM_FP64 = 1, FORM_I8 = 2, FORM_I8LIMB = 3 };
 
+// Largest p for which a sum of 64 products of canonical residues stays
+// below 2^53, i.e. is exact in FP64: 64 (p - 1)^2 < 2^53.
+constexpr double kExact64 = 11863283.0;
+
 // Internal failure: unwinds to the C-ABI boundary, which returns `code`.
 struct CupError {
     int code;
@@ -79,10 +83,14 @@ void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, 
 // chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col)
 // and, when `mail` is given (mapped host memory), the same values to
 // mail[0], mail[1], mail[2+a] as 64-bit words (seq << 32) | value, so that
-// the host can read them while later launches run.
+// the host can read them while later launches run.  When a full 64 x 64
+// block is decided (64 pivots, 64 rows, 64 columns; p <= kExact64), it also
+// writes the dense inverse of its lower pivot block to `winv` and that of
+// its unit upper block to `uinv` (each 64 x 64 row-major, either may be null).
 template <typename T>
 void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
-                   ModP mp, int* out, unsigned long long* mail = nullptr, unsigned seq = 0);
+                   ModP mp, int* out, unsigned long long* mail = nullptr, unsigned seq = 0,
+                   double* winv = nullptr, double* uinv = nullptr);
 
 // For each row r in [i0,b): leftmost nonzero column >= t0 (or N), into out[r-i0].
 template <typename T>

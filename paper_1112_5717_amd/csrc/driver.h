@@ -553,13 +553,30 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         const bool prof = c.prof && c.prof->on;
         if (prof) c.prof->begin(c.s, 1, 0.0, 2.0 * (b - i) * wc * sizeof(T));
         const unsigned seq = next_seq(c);
-        launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small, c.mail_d, seq);
-        if (prof) c.prof->end(c.s);
         // The usual outcome of a leaf's first window, 64 pivots, has its
         // follow-up launched before the count is known, each kernel doing
         // nothing unless the count the window left in device memory is 64.
+        // Where the products are exact in FP64, the window itself also
+        // inverts the two triangles of the decided block (the solve's
+        // inverse and the cached one), so only the solve follows it.
         const bool ahead = (i == 0 && t == 0 && b == kLeafRows && wc == kLeafRows);
-        if (ahead) leaf_followup(c, A, lda, b, N, 0, 0, wc, kLeafRows, c.d_small);
+        const bool fused = ahead && c.mp.p <= kExact64;
+        double* winv = nullptr;
+        double* uinv = nullptr;
+        if (fused) {
+            if (t + wc < N) winv = tri_workspace(c, kLeafRows);
+            const int64_t g = leaf_cache_index(c, A, lda, b, 0, 0, kLeafRows);
+            if (g >= 0) uinv = ucache_slot(c, g);
+        }
+        launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small, c.mail_d, seq, winv, uinv);
+        if (prof) c.prof->end(c.s);
+        if (fused) {
+            if (winv)
+                launch_tri_apply<T>(c.s, LEFT, kLeafRows, winv, A + wc, lda, N - wc, c.mp, c.d_small,
+                                    kLeafRows);
+        } else if (ahead) {
+            leaf_followup(c, A, lda, b, N, 0, 0, wc, kLeafRows, c.d_small);
+        }
         int h[2 + kLeafRows];
         await_window(c, seq, h);
         const int d = h[0], stop = h[1];

@@ -29,6 +29,7 @@
 // window or the rows are exhausted.  Pivot rows never move here; the host
 // compacts the U rows at the end of the leaf.
 #include "modarith.h"
+#include "tri64.h"
 
 namespace cup {
 
@@ -110,9 +111,13 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                                                     int i0, int t0, int wc, ModP mp,
                                                     int* __restrict__ out,
                                                     unsigned long long* __restrict__ mail,
-                                                    unsigned seq)
+                                                    unsigned seq, double* __restrict__ winv,
+                                                    double* __restrict__ uinv)
 {
-    __shared__ double rowslot[kLeafRows][64 * WQ];
+    // The pivot-row slots during the elimination; afterwards the two unit
+    // triangles and their inverses (padded rows).
+    __shared__ double wbuf[4][kLeafRows][kTriNB + 1];
+    double (*rowslot)[64 * WQ] = reinterpret_cast<double (*)[64 * WQ]>(&wbuf[0][0][0]);
     __shared__ int s_jv[kLeafRows];              // pivot column of step a; -2 until published
     __shared__ int s_fail;
     __shared__ int s_d;  // pivots found (the step of a zero row, else min(rows, window))
@@ -120,6 +125,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     __shared__ double s_piv[kLeafRows];
     __shared__ double s_isig[kLeafRows + 1];
     __shared__ double s_ipiv[kLeafRows];
+    __shared__ double s_dl[kLeafRows];  // inverses of the diagonal of C
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
@@ -251,6 +257,19 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     const int d = s_d;
     int stop = (d < aend) ? STOP_ZERO_ROW : ((R <= wc) ? STOP_ROWS : STOP_WINDOW);
     if (s_fail) stop = STOP_FAIL;
+    // the result, for the host, as soon as it is known
+    if (tid == 0) {
+        out[0] = d;
+        out[1] = stop;
+        if (mail) {
+            post_word(mail + 1, seq, stop);
+            post_word(mail, seq, d);
+        }
+    }
+    for (int a = tid; a < d; a += WT) {
+        out[2 + a] = t0 + s_swap[a];
+        if (mail) post_word(mail + 2 + a, seq, t0 + s_swap[a]);
+    }
     // column exchanges of the steps after this wave's rows (rows that
     // followed every step have them already)
     if (stop != STOP_FAIL && own0 < R && own0 + KPW <= aend) {
@@ -281,12 +300,17 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         if (lane < d) {
             double isig_next = mod_inv(x, P, PI);  // 1 / Sigma_{lane+1}
             s_isig[lane + 1] = isig_next;
-            s_ipiv[lane] = mod_mul(sig_prev, isig_next, P, PI);  // 1 / piv_lane
+            const double ipiv = mod_mul(sig_prev, isig_next, P, PI);  // 1 / piv_lane
+            s_ipiv[lane] = ipiv;
+            s_dl[lane] = mod_mul(sig_prev, ipiv, P, PI);  // 1 / C[lane][lane]
         }
         if (lane == 0) s_isig[0] = 1.0;
     }
     __syncthreads();
 
+    // a full block is decided: its two triangles are inverted here as well
+    const bool inv = WQ == 1 && d == kLeafRows && R == kLeafRows && wc == kLeafRows &&
+                     (winv != nullptr || uinv != nullptr) && P <= kExact64;
 #pragma unroll
     for (int q = 0; q < WQ; ++q)
 #pragma unroll
@@ -299,9 +323,28 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 const bool low = c < r && c < d;
                 const double x = low ? cm[q][k] : v[q][k];
                 const double f = (c <= r && c < d) ? s_isig[c] : ((r < d) ? s_ipiv[r] : s_isig[d]);
-                st_res(A + (int64_t)(i0 + r) * lda + t0 + c, mod_mul(x, f, P, PI));
+                const double y = mod_mul(x, f, P, PI);
+                st_res(A + (int64_t)(i0 + r) * lda + t0 + c, y);
+                if (inv && q == 0) {
+                    // the unit upper U, and L^T scaled to a unit triangle:
+                    // C[r][c] / C[c][c] = multiplier / stored pivot
+                    if (c > r) wbuf[0][r][c] = y;
+                    if (c < r) wbuf[1][c][r] = mod_mul(cm[q][k], s_ipiv[c], P, PI);
+                }
             }
         }
+    if (inv) {
+        // waves 0-3 invert U, waves 4-7 the scaled L^T; then
+        // U^{-1} as is, and L^{-1}[i][s] = (L^T scaled)^{-1}[s][i] / C[i][i]
+        __syncthreads();
+        const bool second = w >= 4;
+        unit_upper_inverse<1>(wbuf[second ? 1 : 0], wbuf[second ? 3 : 2], P, PI, second ? 4 : 0);
+        for (int idx = tid; idx < kLeafRows * kLeafRows; idx += WT) {
+            const int i = idx >> 6, s = idx & 63;
+            if (uinv) uinv[idx] = canon(wbuf[2][i][s], P);
+            if (winv) winv[idx] = canon(red_near(wbuf[3][s][i] * s_dl[i], P, PI), P);
+        }
+    }
     // the same column swaps on the leaf rows above the window block
     for (int r = tid; r < i0; r += WT) {
         T* row = A + (int64_t)r * lda + t0;
@@ -313,18 +356,6 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 row[j] = x;
             }
         }
-    }
-    if (tid == 0) {
-        out[0] = d;
-        out[1] = stop;
-        if (mail) {
-            post_word(mail + 1, seq, stop);
-            post_word(mail, seq, d);
-        }
-    }
-    for (int a = tid; a < d; a += WT) {
-        out[2 + a] = t0 + s_swap[a];
-        if (mail) post_word(mail + 2 + a, seq, t0 + s_swap[a]);
     }
 }
 
@@ -364,11 +395,12 @@ __global__ void colswap_kernel(T* __restrict__ A, int64_t lda, int rows, int c0,
 
 template <typename T>
 void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
-                   ModP mp, int* out, unsigned long long* mail, unsigned seq)
+                   ModP mp, int* out, unsigned long long* mail, unsigned seq, double* winv,
+                   double* uinv)
 {
     static_assert(kWin % 64 == 0 && kWin <= 128, "window of 64 or 128 columns");
     hipLaunchKernelGGL((window_kernel<T, kWin / 64>), dim3(1), dim3(WT), 0, s, A, lda, b, N, i0, t0,
-                       wc, mp, out, mail, seq);
+                       wc, mp, out, mail, seq, winv, uinv);
     CUP_HIP(hipGetLastError());
 }
 
@@ -392,7 +424,7 @@ void launch_colswap(hipStream_t s, T* A, int64_t lda, int rows, int c0, int c1)
 
 #define CUP_INST(T)                                                                            \
     template void launch_window<T>(hipStream_t, T*, int64_t, int, int, int, int, int, ModP,    \
-                                   int*, unsigned long long*, unsigned);                       \
+                                   int*, unsigned long long*, unsigned, double*, double*);     \
     template void launch_row_scan<T>(hipStream_t, const T*, int64_t, int, int, int, int, int*); \
     template void launch_colswap<T>(hipStream_t, T*, int64_t, int, int, int);
 CUP_INST(int64_t)

@@ -19,6 +19,7 @@
 // partial sum is reduced after every term (the BIG instantiations), since a
 // reduced sum plus one product stays below p + p^2 < 2^53.
 #include "modarith.h"
+#include "tri64.h"
 
 namespace cup {
 
@@ -65,105 +66,6 @@ __device__ __forceinline__ void inverse_column_big(const double (*M)[NB + 1], co
     }
 }
 
-// Residue in (-p, p): x - round(x / p) p, exact for |x| < 2^53 with
-// |x / p| < 2^51 (the rounding adds and subtracts 1.5 * 2^52; the quotient
-// from the rounded reciprocal is within one of x / p, so |x - q p| < p).
-// Three dependent operations, against six for the canonical reduction, on
-// the latency-bound chains below.
-__device__ __forceinline__ double red_near(double x, double p, double pinv)
-{
-    const double magic = 6755399441055744.0;  // 1.5 * 2^52
-    const double q = fma(x, pinv, magic) - magic;
-    return fma(-q, p, x);
-}
-
-__device__ __forceinline__ double canon(double x, double p) { return (x < 0.0) ? x + p : x; }
-
-// Inverse of a unit upper triangle U (64 x 64; its strict upper part in M),
-// into X, by 16 x 16 blocks.  The four diagonal blocks are inverted
-// column-parallel by wave 0 (lane 16a + j solves for column j of block a,
-// with the block's entries of U loaded into registers first, so each of the
-// 16 steps is one rounding and one fused multiply-add).  The off-diagonal
-// blocks follow by increasing block distance on the FP64 matrix cores, one
-// block per wave:  X_ab = -X_aa (sum_{a<k<=b} U_ak X_kb),  each 16 x 16 x 16
-// product four v_mfma_f64_16x16x4f64.  The partial sum's result layout (lane
-// l holds rows l/16 + 4e of column l%16) is already the B operand of the
-// second product, so nothing moves between the two.  Run by the four waves
-// wbase..wbase+3 of the workgroup (every thread takes the barriers); entries
-// stay in (-p, p), so a sum of at most 48 products is exact for p < 2^23.5.
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void unit_upper_inverse(const double (*M)[NB + 1], double (*X)[NB + 1], double P,
-                                   double PI, int wbase = 0)
-{
-    const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) - wbase;
-    const int hi = lane >> 4, lo = lane & 15;
-    if (w == 0) {
-        const int a = lane >> 4, j = lane & 15, o = 16 * a;
-        // Column i of the block (rows above the diagonal) is loaded three
-        // steps before it is used, so that the chain need not wait on LDS.
-        double u[16][16];
-        auto fetch = [&](int i) {
-#pragma unroll
-            for (int t = 0; t < 15; ++t)
-                if (t < i) u[t][i] = M[o + t][o + i];
-        };
-        fetch(15);
-        fetch(14);
-        fetch(13);
-        double acc[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-            if (i >= 4) fetch(i - 3);
-            const double x = red_near(acc[i], P, PI);
-            X[o + i][o + j] = x;
-#pragma unroll
-            for (int t = 0; t < i; ++t) acc[t] = fma(u[t][i], -x, acc[t]);
-        }
-    }
-    // blocks below the diagonal are zero
-    if (w >= 0 && w < 4)
-        for (int idx = tid - 64 * wbase; idx < NB * NB; idx += 256) {
-            const int i = idx >> 6, s = idx & 63;
-            if ((s >> 4) < (i >> 4)) X[i][s] = 0.0;
-        }
-    __syncthreads();
-#pragma unroll
-    for (int d = 1; d < 4; ++d) {
-        if (w >= 0 && w + d < 4) {
-            const int a = w, b = w + d;
-            double ma[3][4], xb[3][4], xa[4];
-#pragma unroll
-            for (int k = 0; k < d; ++k)
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    ma[k][ks] = M[16 * a + lo][16 * (a + 1 + k) + 4 * ks + hi];
-                    xb[k][ks] = X[16 * (a + 1 + k) + 4 * ks + hi][16 * b + lo];
-                }
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) xa[ks] = X[16 * a + lo][16 * a + 4 * ks + hi];
-            __builtin_amdgcn_sched_barrier(0);  // operands loaded before the products
-            v4d sacc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int k = 0; k < d; ++k)
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks)
-                    sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[k][ks], xb[k][ks], sacc, 0, 0, 0);
-            double sv[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) sv[e] = red_near(sacc[e], P, PI);
-            v4d xacc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-                xacc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks], sv[ks], xacc, 0, 0, 0);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) X[16 * a + hi + 4 * e][16 * b + lo] = -red_near(xacc[e], P, PI);
-        }
-        __syncthreads();
-    }
-}
 
 // mode 0: W[b] = T_bb^{-1}; mode 1: W[b] = T_bb; mode 2: T_bb <- T_bb^{-1} in
 // place (the unit diagonal, if any, is left untouched).  One workgroup of
@@ -640,7 +542,7 @@ __global__ void negate_kernel(T* __restrict__ B, int64_t ldb, int rows, int cols
     }
 }
 
-inline bool big_prime(const ModP& mp) { return mp.p > 11863283.0; }  // 64 (p-1)^2 >= 2^53
+inline bool big_prime(const ModP& mp) { return mp.p > kExact64; }
 
 }  // namespace
 
