@@ -90,6 +90,9 @@ __device__ __forceinline__ double readlane_d(double x, int l)
 // reported as a failure instead of waiting forever.
 constexpr int kSpinMax = 1 << 22;
 
+// Bit pattern of an LDS row slot not written yet (a NaN, which no residue is).
+constexpr unsigned long long kEmpty = ~0ull;
+
 // Register-resident tile: thread (wave w, lane l) holds the consecutive rows
 // KPW w + k (k < KPW) of columns l + 64q (q < WQ).  So the pivot of step a + 1
 // usually comes from the same wave as that of step a, and a wave takes its
@@ -98,10 +101,11 @@ constexpr int kSpinMax = 1 << 22;
 // multiplier of each row at each step (its frozen C entry) is copied aside
 // in registers, so the update itself runs on every lane without a select
 // (entries left of the pivot become don't-care values in (-p, p)).  Each
-// pivot row goes to its own LDS slot; its pivot column, written last with
-// release order into a slot that holds -2 until then, is the ready flag.
-// The slot of a wave's row is released at the start of the wave's next step
-// (its writes have long completed by then), that of its last row at once.
+// pivot row goes to its own LDS slot, which holds a NaN pattern until then,
+// and its pivot column to a word that holds -2 until then; every entry is
+// written once, with one 64-bit store, so a reader loads the column and the
+// row together and retries until the column is set and no entry of the row
+// is still empty: one LDS round trip per pivot and no fence for the writer.
 // The waves below follow the slots in order, applying every pivot to their
 // rows as it arrives; a wave whose rows are all pivots stops following and
 // applies the later column exchanges after the final barrier.  No barrier
@@ -144,6 +148,8 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             cm[q][k] = 0.0;
         }
     for (int x = tid; x < kLeafRows; x += WT) s_jv[x] = -2;
+    for (int x = tid; x < kLeafRows * 64 * WQ; x += WT)
+        rowslot[x / (64 * WQ)][x % (64 * WQ)] = __longlong_as_double((long long)kEmpty);
     if (tid == 0) {
         s_fail = 0;
         s_d = aend;
@@ -151,8 +157,8 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     __syncthreads();
 
     const int own0 = KPW * w;
-    auto release = [&](int a, int j) {
-        if (lane == 0) __hip_atomic_store(&s_jv[a], j, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    auto publish_j = [&](int a, int j) {
+        if (lane == 0) __hip_atomic_store(&s_jv[a], j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     // columns a and j (> a) exchange in every own row
     auto swap_cols = [&](int a, int j) {
@@ -184,14 +190,28 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     const int follow_end = (own0 < R) ? min(own0, aend) : 0;
     bool stopped = false;
     for (int a = 0; a < follow_end; ++a) {
+        // the pivot column and the row in one round trip, until the column
+        // is set and no entry of the row still holds the empty pattern
         int j = -2;
+        double u[WQ];
+        bool ready = false;
         for (int it = 0; it < kSpinMax; ++it) {
-            j = __hip_atomic_load(&s_jv[a], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (j != -2) break;
+            j = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(&s_jv[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            bool empty = false;
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) {
+                const unsigned long long bits = __hip_atomic_load(
+                    reinterpret_cast<unsigned long long*>(&rowslot[a][lane + 64 * q]), __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_WORKGROUP);
+                empty |= bits == kEmpty;
+                u[q] = __longlong_as_double((long long)bits);
+            }
+            ready = j == -1 || (j >= 0 && __ballot(empty) == 0);
+            if (ready) break;
             __builtin_amdgcn_s_sleep(1);
         }
-        j = __builtin_amdgcn_readfirstlane(j);
-        if (j == -2) {
+        if (!ready) {
             if (lane == 0) s_fail = 1;
             stopped = true;
             break;
@@ -200,9 +220,6 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             stopped = true;
             break;
         }
-        double u[WQ];
-#pragma unroll
-        for (int q = 0; q < WQ; ++q) u[q] = rowslot[a][lane + 64 * q];
         const double piv = readlane_d(pick1(u, a >> 6), a & 63);
         if (j != a) swap_cols(a, j);
 #pragma unroll
@@ -210,7 +227,6 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     }
     // Own steps.
     if (!stopped) {
-        int pend_a = -1, pend_j = 0;  // a published row whose slot is not released yet
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
             const int a = own0 + k;
@@ -222,13 +238,9 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 const unsigned long long mq = __ballot(c >= a && c < wc && v[q][k] != 0.0);
                 if (mq) j = 64 * q + __ffsll((long long)mq) - 1;
             }
-            if (pend_a >= 0) {
-                release(pend_a, pend_j);
-                pend_a = -1;
-            }
             if (j < 0) {  // zero residual on the window: the phase ends at a
                 if (lane == 0) s_d = a;
-                release(a, -1);
+                publish_j(a, -1);
                 break;
             }
             if (j != a) swap_cols(a, j);
@@ -238,6 +250,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 u[q] = v[q][k];
                 rowslot[a][lane + 64 * q] = u[q];
             }
+            publish_j(a, j);
             const double piv = readlane_d(pick1(u, a >> 6), a & 63);
             if (lane == 0) {
                 s_swap[a] = j;
@@ -245,12 +258,6 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             }
 #pragma unroll
             for (int k2 = k + 1; k2 < KPW; ++k2) update(k2, a, piv, u);
-            if (k + 1 < KPW && a + 1 < aend) {
-                pend_a = a;
-                pend_j = j;
-            } else {
-                release(a, j);
-            }
         }
     }
     __syncthreads();
@@ -338,7 +345,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         // U^{-1} as is, and L^{-1}[i][s] = (L^T scaled)^{-1}[s][i] / C[i][i]
         __syncthreads();
         const bool second = w >= 4;
-        unit_upper_inverse<1>(wbuf[second ? 1 : 0], wbuf[second ? 3 : 2], P, PI, second ? 4 : 0);
+        unit_upper_inverse<(WT >= 1024 ? 1 : 3)>(wbuf[second ? 1 : 0], wbuf[second ? 3 : 2], P, PI, second ? 4 : 0);
         for (int idx = tid; idx < kLeafRows * kLeafRows; idx += WT) {
             const int i = idx >> 6, s = idx & 63;
             if (uinv) uinv[idx] = canon(wbuf[2][i][s], P);
