@@ -60,6 +60,21 @@ __device__ __forceinline__ double pick(const double (&v)[WQ][KPW], int k, int q)
     return x;
 }
 
+// Leftmost position >= a (and < wc) of a nonzero entry of the row held one
+// column per lane in u, or -1: one ballot per 64 columns.
+template <int WQ>
+__device__ __forceinline__ int leftmost(const double (&u)[WQ], int a, int wc)
+{
+    int j = -1;
+#pragma unroll
+    for (int q = WQ - 1; q >= 0; --q) {
+        const int c = (int)(threadIdx.x & 63) + 64 * q;
+        const unsigned long long mq = __ballot(c >= a && c < wc && u[q] != 0.0);
+        if (mq) j = 64 * q + __ffsll((long long)mq) - 1;
+    }
+    return j;
+}
+
 // u[q] for a wave-uniform q
 template <int WQ>
 __device__ __forceinline__ double pick1(const double (&u)[WQ], int q)
@@ -101,11 +116,12 @@ constexpr unsigned long long kEmpty = ~0ull;
 // multiplier of each row at each step (its frozen C entry) is copied aside
 // in registers, so the update itself runs on every lane without a select
 // (entries left of the pivot become don't-care values in (-p, p)).  Each
-// pivot row goes to its own LDS slot, which holds a NaN pattern until then,
-// and its pivot column to a word that holds -2 until then; every entry is
-// written once, with one 64-bit store, so a reader loads the column and the
-// row together and retries until the column is set and no entry of the row
-// is still empty: one LDS round trip per pivot and no fence for the writer.
+// pivot row goes, as it stands before its column exchange, to its own LDS
+// slot, which holds a NaN pattern until then; every entry is written once,
+// with one 64-bit store, so a reader polls the row itself until no entry is
+// still empty and finds the pivot column from it as the owner did: one LDS
+// round trip per pivot, no flag and no fence.  Pivot columns and pivots go
+// to LDS once, after the wave's last step.
 // The waves below follow the slots in order, applying every pivot to their
 // rows as it arrives; a wave whose rows are all pivots stops following and
 // applies the later column exchanges after the final barrier.  No barrier
@@ -122,7 +138,6 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     // triangles and their inverses (padded rows).
     __shared__ double wbuf[4][kLeafRows][kTriNB + 1];
     double (*rowslot)[64 * WQ] = reinterpret_cast<double (*)[64 * WQ]>(&wbuf[0][0][0]);
-    __shared__ int s_jv[kLeafRows];              // pivot column of step a; -2 until published
     __shared__ int s_fail;
     __shared__ int s_d;  // pivots found (the step of a zero row, else min(rows, window))
     __shared__ int s_swap[kLeafRows];
@@ -147,7 +162,6 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             v[q][k] = (r < R && c < wc) ? ld_res(A + (int64_t)(i0 + r) * lda + t0 + c) : 0.0;
             cm[q][k] = 0.0;
         }
-    for (int x = tid; x < kLeafRows; x += WT) s_jv[x] = -2;
     for (int x = tid; x < kLeafRows * 64 * WQ; x += WT)
         rowslot[x / (64 * WQ)][x % (64 * WQ)] = __longlong_as_double((long long)kEmpty);
     if (tid == 0) {
@@ -157,9 +171,6 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     __syncthreads();
 
     const int own0 = KPW * w;
-    auto publish_j = [&](int a, int j) {
-        if (lane == 0) __hip_atomic_store(&s_jv[a], j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    };
     // columns a and j (> a) exchange in every own row
     auto swap_cols = [&](int a, int j) {
         const int qa = a >> 6, la = a & 63, qj = j >> 6, lj = j & 63;
@@ -190,14 +201,16 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     const int follow_end = (own0 < R) ? min(own0, aend) : 0;
     bool stopped = false;
     for (int a = 0; a < follow_end; ++a) {
-        // the pivot column and the row in one round trip, until the column
-        // is set and no entry of the row still holds the empty pattern
-        int j = -2;
+        // the steps of the wave just above lead into this wave's own: they
+        // are on the chain, so this wave is issued ahead of the others
+        if (a == own0 - KPW) __builtin_amdgcn_s_setprio(2);
+        // Row a as it stood before its column exchange, polled until no
+        // entry holds the empty pattern; its pivot column is found here as
+        // by its owner (leftmost nonzero at positions >= a; none: the
+        // phase ends at a).
         double u[WQ];
         bool ready = false;
         for (int it = 0; it < kSpinMax; ++it) {
-            j = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(&s_jv[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
             bool empty = false;
 #pragma unroll
             for (int q = 0; q < WQ; ++q) {
@@ -207,7 +220,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 empty |= bits == kEmpty;
                 u[q] = __longlong_as_double((long long)bits);
             }
-            ready = j == -1 || (j >= 0 && __ballot(empty) == 0);
+            ready = __ballot(empty) == 0;
             if (ready) break;
             __builtin_amdgcn_s_sleep(1);
         }
@@ -216,50 +229,74 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             stopped = true;
             break;
         }
+        const int j = leftmost(u, a, wc);
         if (j < 0) {
             stopped = true;
             break;
         }
-        const double piv = readlane_d(pick1(u, a >> 6), a & 63);
-        if (j != a) swap_cols(a, j);
+        double piv;
+        if (j != a) {
+            // the exchange of positions a and j, in the pivot row and in
+            // every own row
+            const double ua = readlane_d(pick1(u, a >> 6), a & 63);
+            piv = readlane_d(pick1(u, j >> 6), j & 63);
+#pragma unroll
+            for (int q = 0; q < WQ; ++q) {
+                const int c = lane + 64 * q;
+                u[q] = (c == a) ? piv : ((c == j) ? ua : u[q]);
+            }
+            swap_cols(a, j);
+        } else {
+            piv = readlane_d(pick1(u, a >> 6), a & 63);
+        }
 #pragma unroll
         for (int k = 0; k < KPW; ++k) update(k, a, piv, u);
     }
-    // Own steps.
+    // Own steps, at the highest issue priority: they are the chain, and the
+    // waves below share the SIMDs with updates that can wait.  Pivot
+    // columns and pivots stay in registers until the end.
+    __builtin_amdgcn_s_setprio(3);
+    int own_j[KPW];
+    double own_piv[KPW];
+    int nown = 0;
     if (!stopped) {
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
             const int a = own0 + k;
             if (a >= aend) break;
-            int j = -1;
-#pragma unroll
-            for (int q = WQ - 1; q >= 0; --q) {
-                const int c = lane + 64 * q;
-                const unsigned long long mq = __ballot(c >= a && c < wc && v[q][k] != 0.0);
-                if (mq) j = 64 * q + __ffsll((long long)mq) - 1;
-            }
-            if (j < 0) {  // zero residual on the window: the phase ends at a
-                if (lane == 0) s_d = a;
-                publish_j(a, -1);
-                break;
-            }
-            if (j != a) swap_cols(a, j);
             double u[WQ];
 #pragma unroll
             for (int q = 0; q < WQ; ++q) {
                 u[q] = v[q][k];
-                rowslot[a][lane + 64 * q] = u[q];
+                rowslot[a][lane + 64 * q] = u[q];  // published before the exchange
             }
-            publish_j(a, j);
+            const int j = leftmost(u, a, wc);
+            if (j < 0) {  // zero residual on the window: the phase ends at a
+                if (lane == 0) s_d = a;
+                break;
+            }
+            if (j != a) {
+                swap_cols(a, j);
+#pragma unroll
+                for (int q = 0; q < WQ; ++q) u[q] = v[q][k];
+            }
             const double piv = readlane_d(pick1(u, a >> 6), a & 63);
-            if (lane == 0) {
-                s_swap[a] = j;
-                s_piv[a] = piv;
-            }
+            own_j[k] = j;
+            own_piv[k] = piv;
+            nown = k + 1;
 #pragma unroll
             for (int k2 = k + 1; k2 < KPW; ++k2) update(k2, a, piv, u);
         }
     }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < KPW; ++k)
+            if (k < nown) {
+                s_swap[own0 + k] = own_j[k];
+                s_piv[own0 + k] = own_piv[k];
+            }
+    }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     const int d = s_d;
     int stop = (d < aend) ? STOP_ZERO_ROW : ((R <= wc) ? STOP_ROWS : STOP_WINDOW);
