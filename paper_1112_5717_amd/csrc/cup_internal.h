@@ -86,11 +86,25 @@ void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, 
 // the host can read them while later launches run.  When a full 64 x 64
 // block is decided (64 pivots, 64 rows, 64 columns; p <= kExact64), it also
 // writes the dense inverse of its lower pivot block to `winv` and that of
-// its unit upper block to `uinv` (each 64 x 64 row-major, either may be null).
+// its unit upper block to `uinv` (each 64 x 64 row-major, either may be null),
+// and, when `below` is given and no column was exchanged, G = B U^{-1} for
+// the 64 x 64 block B at `below` (the rows under the leaf), in place.  It
+// also writes the number of column exchanges to out[kSwapWord].
 template <typename T>
 void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
                    ModP mp, int* out, unsigned long long* mail = nullptr, unsigned seq = 0,
-                   double* winv = nullptr, double* uinv = nullptr);
+                   double* winv = nullptr, double* uinv = nullptr, T* below = nullptr);
+
+// Index in the window's `out` of the number of column exchanges it made.
+constexpr int kSwapWord = 2 + kLeafRows;
+
+// Two-leaf node (see k_tri.hip): after the first leaf's window decided a full
+// block with no exchange, U12 = L^{-1} T and H = B - G U12 for every column
+// right of the block, in one launch; nothing unless guard[0] == 64 and
+// guard[kSwapWord] == 0.
+template <typename T>
+void launch_pair_update(hipStream_t s, T* A, int64_t lda, int N, const double* WL, const int* guard,
+                        ModP mp);
 
 // For each row r in [i0,b): leftmost nonzero column >= t0 (or N), into out[r-i0].
 template <typename T>

@@ -112,6 +112,11 @@ struct Ctx {
     unsigned long long* mail_h = nullptr;
     unsigned long long* mail_d = nullptr;
     unsigned* mail_seq = nullptr;
+    // Two-leaf node: the 64 rows under the leaf about to be factored (set by
+    // the node, taken by the leaf), and whether the leaf has already done
+    // the node's G and Schur update.
+    void* pair_below = nullptr;
+    bool pair_done = false;
     int log = 0;
     double i8_min_work = 1.0e9;  // M N K below which products stay on FP64
     // The matrix being factored (its top-left and leading dimension) and
@@ -548,6 +553,8 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
     int i = 0, t = 0;
     int pending = -1;  // column brought to position t by a full-width scan
     std::vector<int> piv_rows;
+    T* below = static_cast<T*>(c.pair_below);
+    c.pair_below = nullptr;
     while (i < b && t < N) {
         const int wc = std::min(kWin, N - t);
         const bool prof = c.prof && c.prof->on;
@@ -568,9 +575,16 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
             const int64_t g = leaf_cache_index(c, A, lda, b, 0, 0, kLeafRows);
             if (g >= 0) uinv = ucache_slot(c, g);
         }
-        launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small, c.mail_d, seq, winv, uinv);
+        // A leaf with 64 rows below it in a two-leaf node also forms the
+        // node's G (in the window) and, with its own solve, the Schur update
+        // of those rows (one launch), when the window exchanges no column.
+        const bool pair = fused && below != nullptr && winv != nullptr;
+        launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small, c.mail_d, seq, winv, uinv,
+                         pair ? below : nullptr);
         if (prof) c.prof->end(c.s);
-        if (fused) {
+        if (pair) {
+            launch_pair_update<T>(c.s, A, lda, N, winv, c.d_small, c.mp);
+        } else if (fused) {
             if (winv)
                 launch_tri_apply<T>(c.s, LEFT, kLeafRows, winv, A + wc, lda, N - wc, c.mp, c.d_small,
                                     kLeafRows);
@@ -590,9 +604,20 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         }
         pending = -1;
         if (d > 0) {
-            const int64_t g = (ahead && d == kLeafRows) ? leaf_cache_index(c, A, lda, b, 0, 0, d)
-                                                        : leaf_followup(c, A, lda, b, N, i, t, wc, d,
-                                                                        (const int*)nullptr);
+            int64_t g;
+            if (ahead && d == kLeafRows) {
+                g = leaf_cache_index(c, A, lda, b, 0, 0, d);
+                if (pair) {
+                    bool exchanged = false;
+                    for (int a = 0; a < d; ++a) exchanged |= h[2 + a] != a;
+                    if (exchanged)  // the pair launch did nothing: the leaf's own solve
+                        launch_tri_apply<T>(c.s, LEFT, kLeafRows, winv, A + wc, lda, N - wc, c.mp);
+                    else
+                        c.pair_done = true;
+                }
+            } else {
+                g = leaf_followup(c, A, lda, b, N, i, t, wc, d, (const int*)nullptr);
+            }
             if (g >= 0) c.uc_ok[(size_t)(g / kTriNB)] = 1;
             i += d;
             t += d;
@@ -642,9 +667,15 @@ int cup_rec(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& P,
     const int k = split_at(m, kLeafRows);
     const size_t p0 = P.size(), q0 = Q.size();
     if (c.log) std::fprintf(stderr, "[cup] node m=%d n=%d k=%d\n", m, n, k);
+    // a node of two full leaves: the first may do G and H (cup_leaf)
+    if (k == kLeafRows && m - k == kLeafRows && n > kLeafRows) c.pair_below = A + (int64_t)k * lda;
     const int r1 = cup_rec(c, A, lda, k, n, P, Q);
+    c.pair_below = nullptr;
     T* A2 = A + (int64_t)k * lda;
-    if (r1 > 0) {
+    if (c.pair_done) {
+        // G and H are formed and the bottom rows' column order is unchanged
+        c.pair_done = false;
+    } else if (r1 > 0) {
         apply_transpositions(c, A2, lda, m - k, P.data() + p0, r1);          // A2 <- A2 P1^T
         // G = A21 U1^-1, with the cached diagonal-block inverses when every
         // block of U1 has one

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                                                     int* __restrict__ out,
                                                     unsigned long long* __restrict__ mail,
                                                     unsigned seq, double* __restrict__ winv,
-                                                    double* __restrict__ uinv)
+                                                    double* __restrict__ uinv, T* __restrict__ below)
 {
     // The pivot-row slots during the elimination; afterwards the two unit
     // triangles and their inverses (padded rows).
@@ -145,6 +145,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     __shared__ double s_isig[kLeafRows + 1];
     __shared__ double s_ipiv[kLeafRows];
     __shared__ double s_dl[kLeafRows];  // inverses of the diagonal of C
+    __shared__ int s_nswap;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
@@ -302,6 +303,14 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     int stop = (d < aend) ? STOP_ZERO_ROW : ((R <= wc) ? STOP_ROWS : STOP_WINDOW);
     if (s_fail) stop = STOP_FAIL;
     // the result, for the host, as soon as it is known
+    if (w == 0) {
+        const bool sw = lane < d && s_swap[lane] != lane;
+        const int nswap = __popcll(__ballot(sw));
+        if (lane == 0) {
+            s_nswap = nswap;
+            out[kSwapWord] = nswap;
+        }
+    }
     if (tid == 0) {
         out[0] = d;
         out[1] = stop;
@@ -388,6 +397,22 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             if (uinv) uinv[idx] = canon(wbuf[2][i][s], P);
             if (winv) winv[idx] = canon(red_near(wbuf[3][s][i] * s_dl[i], P, PI), P);
         }
+        if (below != nullptr && s_nswap == 0) {
+            // G = B U^{-1} for the block under the leaf (Algorithm 6's G
+            // for a two-leaf node), one 16 x 16 tile per wave, in place
+            const int hi = lane >> 4, lo = lane & 15, tr = w >> 2, tc = w & 3;
+            double bv[16];
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) bv[ks] = ld_res(below + (int64_t)(16 * tr + lo) * lda + 4 * ks + hi);
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[ks], wbuf[2][4 * ks + hi][16 * tc + lo], acc, 0, 0, 0);
+            __syncthreads();  // every wave has read its rows of B before any is overwritten
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                st_res(below + (int64_t)(16 * tr + hi + 4 * e) * lda + 16 * tc + lo, mod_red(acc[e], P, PI));
+        }
     }
     // the same column swaps on the leaf rows above the window block
     for (int r = tid; r < i0; r += WT) {
@@ -440,11 +465,11 @@ __global__ void colswap_kernel(T* __restrict__ A, int64_t lda, int rows, int c0,
 template <typename T>
 void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, int wc,
                    ModP mp, int* out, unsigned long long* mail, unsigned seq, double* winv,
-                   double* uinv)
+                   double* uinv, T* below)
 {
     static_assert(kWin % 64 == 0 && kWin <= 128, "window of 64 or 128 columns");
     hipLaunchKernelGGL((window_kernel<T, kWin / 64>), dim3(1), dim3(WT), 0, s, A, lda, b, N, i0, t0,
-                       wc, mp, out, mail, seq, winv, uinv);
+                       wc, mp, out, mail, seq, winv, uinv, below);
     CUP_HIP(hipGetLastError());
 }
 
@@ -468,7 +493,7 @@ void launch_colswap(hipStream_t s, T* A, int64_t lda, int rows, int c0, int c1)
 
 #define CUP_INST(T)                                                                            \
     template void launch_window<T>(hipStream_t, T*, int64_t, int, int, int, int, int, ModP,    \
-                                   int*, unsigned long long*, unsigned, double*, double*);     \
+                                   int*, unsigned long long*, unsigned, double*, double*, T*); \
     template void launch_row_scan<T>(hipStream_t, const T*, int64_t, int, int, int, int, int*); \
     template void launch_colswap<T>(hipStream_t, T*, int64_t, int, int, int);
 CUP_INST(int64_t)

@@ -479,6 +479,90 @@ __global__ __launch_bounds__(256) void tri_slab_mfma_kernel(int n, const T* __re
     }
 }
 
+// Two-leaf node whose first leaf (rows 0..63, the pivots in columns 0..63)
+// was decided as a full block with no column exchange, and whose second leaf
+// is the 64 rows below.  The leaf's solve of its other columns, Algorithm 6's
+// G (already formed in place by the window) and the Schur update are all
+// column-parallel then, so one launch does them:  per 32-column block c
+// right of the pivots,  U12_c = L^{-1} T_c  (top rows) and
+// H_c = B_c - G U12_c  (bottom rows), on the FP64 matrix cores.  Wave w
+// forms rows 16w..16w+15 of both products; T_c and U12_c pass through LDS as
+// B operands, L^{-1} and G rows are read from global memory (every
+// workgroup reads the same ones) as A operands.  A 64-term sum of canonical
+// products is exact for p <= kExact64.  Does nothing unless the window
+// found 64 pivots and exchanged no column.
+constexpr int PC = 32;  // columns per workgroup
+
+template <typename T>
+__global__ __launch_bounds__(256) void pair_update_kernel(T* __restrict__ A, int64_t lda, int N,
+                                                          const double* __restrict__ WL,
+                                                          const int* __restrict__ guard, ModP mp)
+{
+    __shared__ double Ts[NB][PC + 1];
+    __shared__ double Us[NB][PC + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hi = lane >> 4, lo = lane & 15;
+    const double P = mp.p, PI = mp.pinv;
+    const int c0 = NB + PC * blockIdx.x;
+    T* Bm = A + (int64_t)NB * lda;
+    // (the guard is loaded with the operands and checked before anything is
+    // written)
+    const int g0 = guard[0], g1 = guard[kSwapWord];
+    // T_c (columns past N clamped; not stored), B_c rows of this wave in
+    // result layout, and the A operands: rows 16w.. of L^{-1} and G
+    double tv[NB * PC / 256];
+#pragma unroll
+    for (int it = 0; it < NB * PC / 256; ++it) {
+        const int idx = tid + 256 * it, r = idx / PC, cc = idx % PC;
+        tv[it] = ld_res(A + (int64_t)r * lda + min(c0 + cc, N - 1));
+    }
+    double bv[2][4], wl[16], gv[16];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            bv[ct][e] = ld_res(Bm + (int64_t)(16 * w + hi + 4 * e) * lda + min(c0 + 16 * ct + lo, N - 1));
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+        wl[ks] = WL[(16 * w + lo) * NB + 4 * ks + hi];
+        gv[ks] = ld_res(Bm + (int64_t)(16 * w + lo) * lda + 4 * ks + hi);
+    }
+    if (g0 != kLeafRows || g1 != 0) return;
+#pragma unroll
+    for (int it = 0; it < NB * PC / 256; ++it) {
+        const int idx = tid + 256 * it;
+        Ts[idx / PC][idx % PC] = tv[it];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wl[ks], Ts[4 * ks + hi][16 * ct + lo], acc, 0, 0, 0);
+        const int c = c0 + 16 * ct + lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double u = mod_red(acc[e], P, PI);
+            Us[16 * w + hi + 4 * e][16 * ct + lo] = u;
+            if (c < N) st_res(A + (int64_t)(16 * w + hi + 4 * e) * lda + c, u);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[ks], Us[4 * ks + hi][16 * ct + lo], acc, 0, 0, 0);
+        const int c = c0 + 16 * ct + lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double h = bv[ct][e] - mod_red(acc[e], P, PI);
+            if (c < N) st_res(Bm + (int64_t)(16 * w + hi + 4 * e) * lda + c, (h < 0.0) ? h + P : h);
+        }
+    }
+}
+
 // [N\T] <- T N on an nb x nb block (nb <= 64): T unit upper (strict upper
 // part stored), N lower with its diagonal.  Thread j holds column j of N.
 template <typename T, bool BIG>
@@ -620,6 +704,16 @@ bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double
 }
 
 template <typename T>
+void launch_pair_update(hipStream_t s, T* A, int64_t lda, int N, const double* WL, const int* guard,
+                        ModP mp)
+{
+    if (N <= NB) return;
+    hipLaunchKernelGGL(pair_update_kernel<T>, dim3((N - NB + PC - 1) / PC), dim3(256), 0, s, A, lda, N,
+                       WL, guard, mp);
+    CUP_HIP(hipGetLastError());
+}
+
+template <typename T>
 void launch_trulm_leaf(hipStream_t s, int nb, T* A, int64_t lda, ModP mp, int64_t kred)
 {
     (void)kred;
@@ -651,6 +745,8 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
     template void launch_tri_apply<T>(hipStream_t, int, int, const double*, T*, int64_t, int,   \
                                       ModP, const int*, int);                                   \
     template void launch_trulm_leaf<T>(hipStream_t, int, T*, int64_t, ModP, int64_t);           \
+    template void launch_pair_update<T>(hipStream_t, T*, int64_t, int, const double*, const int*, \
+                                        ModP);                                                    \
     template bool launch_tri_slab<T>(hipStream_t, int, const T*, int64_t, const double*, T*,    \
                                      int64_t, int, ModP);                                       \
     template void launch_negate<T>(hipStream_t, T*, int64_t, int, int, ModP);
