@@ -57,7 +57,8 @@ def exact_gemm(C, A, B, p, alpha):
 
 @pytest.mark.parametrize("p", [2, 127, 65521, 8388593, 33554393])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (7, 5, 3), (130, 129, 17), (257, 131, 200), (64, 300, 513),
-                                   (300, 130, 64), (129, 65, 63), (4100, 64, 64), (65, 1000, 33)])
+                                   (300, 130, 64), (129, 65, 63), (4100, 64, 64), (65, 1000, 33),
+                                   (150, 300, 128), (64, 700, 256), (200, 90, 129)])
 def test_ffgemm_fp64_random(cup_lib, p, shape):
     M, N, K = shape
     rng = np.random.default_rng(M * 7 + N + K + p % 1000)
@@ -72,12 +73,14 @@ def test_ffgemm_fp64_random(cup_lib, p, shape):
 
 
 @pytest.mark.parametrize("p", [127, 65521, 8388593, 33554393])
-def test_ffgemm_fp64_worst_magnitude(cup_lib, p):
+@pytest.mark.parametrize("K", [2100, 256, 128])
+def test_ffgemm_fp64_worst_magnitude(cup_lib, p, K):
     """All operands at p-1 and at the centring threshold: the largest
-    products, at and beyond the delayed-reduction interval."""
+    products, at and beyond the delayed-reduction interval (K = 2100), and
+    through the single-stage 128-deep launches (K = 128, 256)."""
     h = p // 2
     for val_a, val_b in [(p - 1, p - 1), (h, h), (h + 1, h + 1), (h, h + 1)]:
-        M, N, K = 96, 80, 2100
+        M, N = 96, 80
         A = np.full((M, K), val_a, dtype=np.int64)
         B = np.full((K, N), val_b, dtype=np.int64)
         C = np.full((M, N), p - 1, dtype=np.int64)
