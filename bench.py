@@ -13,8 +13,11 @@ classical matrix products, F = 2mnr - (m+n) r^2 + 2/3 r^3 (Section 4.2).
 
 Besides the headline form, the same steps run in the plain FP64-carrier
 form, once on the rank-6000 variant X(8192x6000) Y(6000x8192) mod p
-(seed 20), and on the multi-modular batch (4096 matrices of up to 512 x 512,
-one prime below 2^23 each, one batched call per step).  Every timed result is checked against the CPU oracle's SHA-256
+(seed 20), on the multi-modular batch (4096 matrices of up to 512 x 512,
+one prime below 2^23 each, one batched call per step), and on the other
+full-size workloads (GF(127) in int8 storage: CUP of 16384 x 16384 of rank
+12000 and the inverse of 8192 x 8192; GF(65521): CUP and reduced echelon
+form of a 32768 x 8192 staircase of rank 2048).  Every timed result is checked against the CPU oracle's SHA-256
 digest when tests/golden/full_size_hashes.json has it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -49,6 +52,75 @@ def digest(packed, r, P, Q) -> str:
         h.update(np.ascontiguousarray(a, dtype=np.int64).tobytes())
     h.update(np.int64(r).tobytes())
     return h.hexdigest()
+
+
+def rref_ops(m: int, n: int, r: int) -> float:
+    """Algorithms 7 and 8 on top of the CUP: r^2 (n-r) + (m-r) r^2 + 4/3 r^3."""
+    return r * r * (n - r) + (m - r) * r * r + 4.0 * r ** 3 / 3.0
+
+
+def config_variants(cup, torch, inputs, gold, steps):
+    """The other full-size workloads, each restored from a pristine device
+    copy before every call (outside the timed interval), median of `steps`
+    calls after one warm-up, checked against the oracle's digest:
+    CUP of X(16384x12000) Y(12000x16384) mod 127 in int8 storage (seed 3),
+    the inverse of a uniform 8192x8192 over GF(127) (int8), and CUP and RREF
+    of the 32768x8192 rank-2048 staircase over GF(65521) (seed 5)."""
+    import numpy as np
+
+    def timed(fn, pristine):
+        times, out, work = [], None, None
+        for i in range(steps + 1):
+            work = pristine.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn(work)
+            torch.cuda.synchronize()
+            if i > 0:
+                times.append(time.perf_counter() - t0)
+        return sorted(times)[len(times) // 2], out, work
+
+    def check(key, dg):
+        if key not in gold:
+            return "no oracle digest at this size"
+        return "oracle digest match" if gold[key]["digest"] == dg else "ORACLE DIGEST MISMATCH"
+
+    res = {}
+    p = 127
+    A = inputs.low_rank(16384, 16384, 12000, p, seed=3, device="cuda")
+    d0 = torch.from_numpy(A.astype(np.int8)).cuda()
+    del A
+    t, (r, P, Q), work = timed(lambda x: cup.cup_factor_i8(x, p), d0)
+    res["cup_16384_rank12000_p127_int8"] = {
+        "ms": t * 1e3, "rank": r, "field_ops_per_s": field_ops(16384, 16384, r) / t,
+        "parity": check("cup_16384_rank12000_p127_seed3",
+                        digest(work.cpu().numpy().astype(np.int64), r, P.cpu().numpy(), Q.cpu().numpy()))}
+    del d0, work
+    g = gold.get("inverse_8192_p127_seed30", {"seed": 30})
+    d0 = torch.from_numpy(inputs.uniform((8192, 8192), p, seed=g["seed"]).astype(np.int8)).cuda()
+    t, (ok, r), work = timed(lambda x: cup.cup_inverse_inplace_i8(x, p), d0)
+    dg = hashlib.sha256(np.ascontiguousarray(work.cpu().numpy().astype(np.int64)).tobytes()).hexdigest()
+    res["inverse_8192_p127_int8"] = {
+        "ms": t * 1e3, "rank": r, "field_ops_per_s": 2.0 * 8192 ** 3 / t,
+        "parity": check("inverse_8192_p127_seed30", dg) if ok else "singular"}
+    del d0, work
+    p = P16
+    A, _ = inputs.staircase(32768, 8192, 2048, p, seed=5, device="cuda")
+    d0 = torch.from_numpy(A).cuda()
+    del A
+    t, (r, P, Q), work = timed(lambda x: cup.cup_factor(x, p), d0)
+    res["cup_32768x8192_staircase2048_p65521"] = {
+        "ms": t * 1e3, "rank": r, "field_ops_per_s": field_ops(32768, 8192, r) / t,
+        "parity": check("cup_32768x8192_staircase2048_p65521_seed5",
+                        digest(work.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()))}
+    t, (r, P, Q), work = timed(lambda x: cup.cup_rref_inplace(x, p), d0)
+    res["rref_32768x8192_staircase2048_p65521"] = {
+        "ms": t * 1e3, "rank": r,
+        "field_ops_per_s": (field_ops(32768, 8192, r) + rref_ops(32768, 8192, r)) / t,
+        "parity": check("rref_32768x8192_staircase2048_p65521_seed5",
+                        digest(work.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()))}
+    del d0, work
+    return res
 
 
 def golden():
@@ -268,6 +340,8 @@ def main():
     if not args.no_variants:
         print("[bench] multi-modular batch (4096 matrices)", file=sys.stderr, flush=True)
         extra["batched"] = batched_variant(cup, torch, inputs, max(1, args.steps), 1, gold)
+        print("[bench] int8 GF(127) and staircase workloads", file=sys.stderr, flush=True)
+        extra["other_workloads"] = config_variants(cup, torch, inputs, gold, 3)
 
     cpu = None
     if not args.no_cpu_baseline:
