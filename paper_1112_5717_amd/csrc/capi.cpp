@@ -77,7 +77,7 @@ void ensure_small(Global& g)
         }
     }
     if (!g.h_mail) {
-        const size_t bytes = sizeof(unsigned long long) * (2 + kLeafRows);
+        const size_t bytes = sizeof(unsigned long long) * kMailWords;
         unsigned long long* h = nullptr;
         if (hipHostMalloc((void**)&h, bytes,
                           hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable) !=

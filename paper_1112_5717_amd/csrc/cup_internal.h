@@ -106,10 +106,17 @@ template <typename T>
 void launch_pair_update(hipStream_t s, T* A, int64_t lda, int N, const double* WL, const int* guard,
                         ModP mp);
 
-// For each row r in [i0,b): leftmost nonzero column >= t0 (or N), into out[r-i0].
+// For each row r in [i0,b): leftmost nonzero column >= t0 (or N), into out[r-i0]
+// and, when `mail` is given, into mail[kMailScan + r - i0] as a word tagged
+// with `seq` (as the window's result).
 template <typename T>
 void launch_row_scan(hipStream_t s, const T* A, int64_t lda, int i0, int b, int t0, int N,
-                     int* out);
+                     int* out, unsigned long long* mail = nullptr, unsigned seq = 0);
+
+// Words of the host mailbox: the window's result (2 + kLeafRows), then the
+// row scan's (kLeafRows).
+constexpr int kMailScan = 2 + kLeafRows;
+constexpr int kMailWords = kMailScan + kLeafRows;
 
 // Swap columns c0 and c1 of rows [0,rows).
 template <typename T>

@@ -198,34 +198,37 @@ inline const int* fetch_small(Ctx& c, int count)
     return c.h_small;
 }
 
-// Wait for the window launch tagged `seq` to post its result (d, stop, then
-// d pivot columns) without synchronising the stream, so that launches queued
+// Wait for word k of the host mailbox to carry the tag `seq` of the launch
+// that posts it, without synchronising the stream, so that launches queued
 // behind it keep the GPU busy meanwhile.  The stream is queried now and then:
 // an error ends the wait with that error, and a drained stream without the
-// words is an internal error.
+// word is an internal error.
+inline int await_word(Ctx& c, unsigned seq, int k)
+{
+    unsigned long long v = 0;
+    for (unsigned spin = 1;; ++spin) {
+        v = __atomic_load_n(c.mail_h + k, __ATOMIC_ACQUIRE);
+        if ((unsigned)(v >> 32) == seq) break;
+        if ((spin & 1023u) == 0) {
+            const hipError_t e = hipStreamQuery(c.s);
+            if (e == hipSuccess) {
+                v = __atomic_load_n(c.mail_h + k, __ATOMIC_ACQUIRE);
+                if ((unsigned)(v >> 32) == seq) break;
+                throw CupError{-3000};
+            }
+            if (e != hipErrorNotReady) CUP_HIP(e);
+        }
+        __builtin_ia32_pause();
+    }
+    return (int)(unsigned)(v & 0xffffffffull);
+}
+
+// A window's result: d, stop, then d pivot columns.
 inline void await_window(Ctx& c, unsigned seq, int* h)
 {
-    auto wait_word = [&](int k) -> int {
-        unsigned long long v = 0;
-        for (unsigned spin = 1;; ++spin) {
-            v = __atomic_load_n(c.mail_h + k, __ATOMIC_ACQUIRE);
-            if ((unsigned)(v >> 32) == seq) break;
-            if ((spin & 1023u) == 0) {
-                const hipError_t e = hipStreamQuery(c.s);
-                if (e == hipSuccess) {
-                    v = __atomic_load_n(c.mail_h + k, __ATOMIC_ACQUIRE);
-                    if ((unsigned)(v >> 32) == seq) break;
-                    throw CupError{-3000};
-                }
-                if (e != hipErrorNotReady) CUP_HIP(e);
-            }
-            __builtin_ia32_pause();
-        }
-        return (int)(unsigned)(v & 0xffffffffull);
-    };
-    h[0] = wait_word(0);
-    h[1] = wait_word(1);
-    for (int a = 0; a < h[0] && a < kLeafRows; ++a) h[2 + a] = wait_word(2 + a);
+    h[0] = await_word(c, seq, 0);
+    h[1] = await_word(c, seq, 1);
+    for (int a = 0; a < h[0] && a < kLeafRows; ++a) h[2 + a] = await_word(c, seq, 2 + a);
 }
 
 inline unsigned next_seq(Ctx& c)
@@ -511,11 +514,12 @@ int64_t leaf_cache_index(Ctx& c, T* A, int64_t lda, int b, int i, int t, int d)
 // the d x d pivot block, whose inverse is formed first), the update of the
 // rows below, and the inverse of the unit-upper block for the cache.  With
 // `guard`, only for d = b = 64 at (0, 0), every kernel does nothing unless
-// *guard (the count the window leaves on the device) equals d.  Returns the
-// cache index filled, or -1.
+// *guard (the count the window leaves on the device) equals d.  `w_ready`:
+// the window has left the pivot block's inverse in the triangular workspace.
+// Returns the cache index filled, or -1.
 template <typename T>
 int64_t leaf_followup(Ctx& c, T* A, int64_t lda, int b, int N, int i, int t, int wc, int d,
-                      const int* guard)
+                      const int* guard, bool w_ready = false)
 {
     const int tw = t + wc;
     T* blk = A + (int64_t)i * lda + t;
@@ -523,10 +527,14 @@ int64_t leaf_followup(Ctx& c, T* A, int64_t lda, int b, int N, int i, int t, int
     double* ucs = (g >= 0) ? ucache_slot(c, g) : nullptr;
     if (tw < N) {
         double* W = tri_workspace(c, d);
-        if (ucs)
+        if (w_ready) {
+            // the window left the pivot block's inverse in W
+            if (ucs) launch_diag_prep<T>(c.s, blk, lda, kTriNB, UPPER, 1, 0, ucs, c.mp, guard, d);
+        } else if (ucs) {
             launch_diag_prep2<T>(c.s, blk, lda, d, LOWER, 0, W, blk, UPPER, 1, ucs, c.mp, guard, d);
-        else
+        } else {
             launch_diag_prep<T>(c.s, blk, lda, d, LOWER, 0, 0, W, c.mp, guard, d);
+        }
         // the solve with the d x d lower pivot block (d <= 64: one leaf of
         // the triangular recursion)
         launch_tri_apply<T>(c.s, LEFT, d, W, A + (int64_t)i * lda + tw, lda, N - tw, c.mp, guard, d);
@@ -570,8 +578,9 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         const bool fused = ahead && c.mp.p <= kExact64;
         double* winv = nullptr;
         double* uinv = nullptr;
+        // every window inverts its pivot block when the products are exact
+        if (c.mp.p <= kExact64 && t + wc < N) winv = tri_workspace(c, kLeafRows);
         if (fused) {
-            if (t + wc < N) winv = tri_workspace(c, kLeafRows);
             const int64_t g = leaf_cache_index(c, A, lda, b, 0, 0, kLeafRows);
             if (g >= 0) uinv = ucache_slot(c, g);
         }
@@ -616,22 +625,26 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
                         c.pair_done = true;
                 }
             } else {
-                g = leaf_followup(c, A, lda, b, N, i, t, wc, d, (const int*)nullptr);
+                g = leaf_followup(c, A, lda, b, N, i, t, wc, d, (const int*)nullptr, winv != nullptr);
             }
             if (g >= 0) c.uc_ok[(size_t)(g / kTriNB)] = 1;
             i += d;
             t += d;
         }
         if (stop == STOP_ZERO_ROW && i < b && t < N) {
-            launch_row_scan<T>(c.s, A, lda, i, b, t, N, c.d_small);
-            const int* hs = fetch_small(c, b - i);
+            // the rows' results in order, as they arrive, up to the first
+            // row with a nonzero
+            const unsigned sseq = next_seq(c);
+            launch_row_scan<T>(c.s, A, lda, i, b, t, N, c.d_small, c.mail_d, sseq);
             int found = -1, j = N;
-            for (int r = 0; r < b - i; ++r)
-                if (hs[r] < N) {
+            for (int r = 0; r < b - i; ++r) {
+                const int hr = await_word(c, sseq, kMailScan + r);
+                if (hr < N) {
                     found = i + r;
-                    j = hs[r];
+                    j = hr;
                     break;
                 }
+            }
             if (found < 0) break;  // every remaining row is zero
             i = found;
             if (j != t) {

@@ -356,14 +356,19 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             const double ipiv = mod_mul(sig_prev, isig_next, P, PI);  // 1 / piv_lane
             s_ipiv[lane] = ipiv;
             s_dl[lane] = mod_mul(sig_prev, ipiv, P, PI);  // 1 / C[lane][lane]
+        } else {
+            s_dl[lane] = 1.0;  // identity padding of the inverse below
         }
         if (lane == 0) s_isig[0] = 1.0;
     }
     __syncthreads();
 
-    // a full block is decided: its two triangles are inverted here as well
-    const bool inv = WQ == 1 && d == kLeafRows && R == kLeafRows && wc == kLeafRows &&
-                     (winv != nullptr || uinv != nullptr) && P <= kExact64;
+    // The pivot block's triangles are inverted here as well (padded with the
+    // identity to 64 x 64): L^{-1} for any pivot count when `winv` is given,
+    // U^{-1} (the cached one) and G only for a full 64 x 64 block.
+    const bool full = d == kLeafRows && R == kLeafRows && wc == kLeafRows;
+    const bool inv = WQ == 1 && d > 0 && P <= kExact64 &&
+                     (winv != nullptr || (full && uinv != nullptr));
 #pragma unroll
     for (int q = 0; q < WQ; ++q)
 #pragma unroll
@@ -378,15 +383,20 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 const double f = (c <= r && c < d) ? s_isig[c] : ((r < d) ? s_ipiv[r] : s_isig[d]);
                 const double y = mod_mul(x, f, P, PI);
                 st_res(A + (int64_t)(i0 + r) * lda + t0 + c, y);
-                if (inv && q == 0) {
-                    // the unit upper U, and L^T scaled to a unit triangle:
-                    // C[r][c] / C[c][c] = multiplier / stored pivot
-                    if (c > r) wbuf[0][r][c] = y;
-                    if (c < r) wbuf[1][c][r] = mod_mul(cm[q][k], s_ipiv[c], P, PI);
-                }
             }
         }
     if (inv) {
+        // the unit upper U, and L^T scaled to a unit triangle
+        // (C[r][c] / C[c][c] = multiplier / stored pivot), zero outside the
+        // d x d pivot block
+        const int c = lane;
+#pragma unroll
+        for (int k = 0; k < KPW; ++k) {
+            const int r = KPW * w + k;
+            const bool in = r < d && c < d;
+            wbuf[0][r][c] = (in && c > r) ? mod_mul(v[0][k], s_ipiv[r], P, PI) : 0.0;
+            wbuf[1][c][r] = (in && c < r) ? mod_mul(cm[0][k], s_ipiv[c], P, PI) : 0.0;
+        }
         // waves 0-3 invert U, waves 4-7 the scaled L^T; then
         // U^{-1} as is, and L^{-1}[i][s] = (L^T scaled)^{-1}[s][i] / C[i][i]
         __syncthreads();
@@ -394,10 +404,10 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         unit_upper_inverse<(WT >= 1024 ? 1 : 3)>(wbuf[second ? 1 : 0], wbuf[second ? 3 : 2], P, PI, second ? 4 : 0);
         for (int idx = tid; idx < kLeafRows * kLeafRows; idx += WT) {
             const int i = idx >> 6, s = idx & 63;
-            if (uinv) uinv[idx] = canon(wbuf[2][i][s], P);
+            if (uinv && full) uinv[idx] = canon(wbuf[2][i][s], P);
             if (winv) winv[idx] = canon(red_near(wbuf[3][s][i] * s_dl[i], P, PI), P);
         }
-        if (below != nullptr && s_nswap == 0) {
+        if (below != nullptr && full && s_nswap == 0) {
             // G = B U^{-1} for the block under the leaf (Algorithm 6's G
             // for a two-leaf node), one 16 x 16 tile per wave, in place
             const int hi = lane >> 4, lo = lane & 15, tr = w >> 2, tc = w & 3;
@@ -431,7 +441,9 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
 // out[r - i0] = leftmost column >= t0 with a nonzero in row r, or N.
 template <typename T>
 __global__ __launch_bounds__(256) void row_scan_kernel(const T* __restrict__ A, int64_t lda,
-                                                       int i0, int t0, int N, int* __restrict__ out)
+                                                       int i0, int t0, int N, int* __restrict__ out,
+                                                       unsigned long long* __restrict__ mail,
+                                                       unsigned seq)
 {
     __shared__ int best;
     const int r = i0 + blockIdx.x;
@@ -445,7 +457,10 @@ __global__ __launch_bounds__(256) void row_scan_kernel(const T* __restrict__ A, 
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) out[blockIdx.x] = best;
+    if (threadIdx.x == 0) {
+        out[blockIdx.x] = best;
+        if (mail) post_word(mail + kMailScan + blockIdx.x, seq, best);
+    }
 }
 
 template <typename T>
@@ -475,10 +490,11 @@ void launch_window(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t
 
 template <typename T>
 void launch_row_scan(hipStream_t s, const T* A, int64_t lda, int i0, int b, int t0, int N,
-                     int* out)
+                     int* out, unsigned long long* mail, unsigned seq)
 {
     if (b <= i0) return;
-    hipLaunchKernelGGL(row_scan_kernel<T>, dim3(b - i0), dim3(256), 0, s, A, lda, i0, t0, N, out);
+    hipLaunchKernelGGL(row_scan_kernel<T>, dim3(b - i0), dim3(256), 0, s, A, lda, i0, t0, N, out, mail,
+                       seq);
     CUP_HIP(hipGetLastError());
 }
 
@@ -494,7 +510,8 @@ void launch_colswap(hipStream_t s, T* A, int64_t lda, int rows, int c0, int c1)
 #define CUP_INST(T)                                                                            \
     template void launch_window<T>(hipStream_t, T*, int64_t, int, int, int, int, int, ModP,    \
                                    int*, unsigned long long*, unsigned, double*, double*, T*); \
-    template void launch_row_scan<T>(hipStream_t, const T*, int64_t, int, int, int, int, int*); \
+    template void launch_row_scan<T>(hipStream_t, const T*, int64_t, int, int, int, int, int*,  \
+                                     unsigned long long*, unsigned);                            \
     template void launch_colswap<T>(hipStream_t, T*, int64_t, int, int, int);
 CUP_INST(int64_t)
 CUP_INST(int8_t)
