@@ -564,7 +564,8 @@ __global__ __launch_bounds__(256) void pair_update_kernel(T* __restrict__ A, int
 }
 
 // [N\T] <- T N on an nb x nb block (nb <= 64): T unit upper (strict upper
-// part stored), N lower with its diagonal.  Thread j holds column j of N.
+// part stored), N lower with its diagonal.  Thread j holds column j of N;
+// used for p > kExact64 (every product reduced as it is added).
 template <typename T, bool BIG>
 __global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ A, int64_t lda, ModP mp)
 {
@@ -585,26 +586,17 @@ __global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ 
     double x[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) x[q] = 0.0;
-    if constexpr (BIG) {
-        for (int i = 0; i < NB; ++i) {
-            double acc = 0.0;
-            for (int s = i; s < NB; ++s) {
-                double nv = 0.0;
+    for (int i = 0; i < NB; ++i) {
+        double acc = 0.0;
+        for (int s = i; s < NB; ++s) {
+            double nv = 0.0;
 #pragma unroll
-                for (int q = 0; q < NB; ++q) nv = (q == s) ? ncol[q] : nv;
-                acc = mod_red(fma(Tu[i][s], nv, acc), P, PI);
-            }
-#pragma unroll
-            for (int q = 0; q < NB; ++q) x[q] = (q == i) ? acc : x[q];
+            for (int q = 0; q < NB; ++q) nv = (q == s) ? ncol[q] : nv;
+            acc = BIG ? mod_red(fma(Tu[i][s], nv, acc), P, PI) : fma(Tu[i][s], nv, acc);
         }
-    } else {
+        acc = mod_red(acc, P, PI);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            double acc = 0.0;
-#pragma unroll
-            for (int s = i; s < NB; ++s) acc = fma(Tu[i][s], ncol[s], acc);
-            x[i] = mod_red(acc, P, PI);
-        }
+        for (int q = 0; q < NB; ++q) x[q] = (q == i) ? acc : x[q];
     }
     __syncthreads();  // every read of the block is done before it is overwritten
     if (j < nb) {
@@ -612,6 +604,52 @@ __global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ 
         for (int i = 0; i < NB; ++i)
             if (i < nb) st_res(A + (int64_t)i * lda + j, x[i]);
     }
+}
+
+// The same product on the FP64 matrix cores for p <= kExact64: T (unit
+// upper, identity-padded) and N (lower with its diagonal, zero-padded) are
+// staged in LDS as dense 64 x 64 triangles, and wave w forms rows
+// 16w..16w+15 of T N with 64 v_mfma_f64_16x16x4f64 (a sum of at most 64
+// canonical products is exact).  Every read of the block precedes the
+// barrier before the block is overwritten.
+template <typename T>
+__global__ __launch_bounds__(256) void trulm_mfma_kernel(int nb, T* __restrict__ A, int64_t lda, ModP mp)
+{
+    __shared__ double Tu[NB][NB + 1];
+    __shared__ double Nl[NB][NB + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hi = lane >> 4, lo = lane & 15;
+    const double P = mp.p, PI = mp.pinv;
+    double ev[NB * NB / 256];
+#pragma unroll
+    for (int it = 0; it < NB * NB / 256; ++it) {
+        const int idx = tid + 256 * it, i = idx >> 6, s = idx & 63;
+        ev[it] = ld_res(A + (int64_t)min(i, nb - 1) * lda + min(s, nb - 1));
+    }
+#pragma unroll
+    for (int it = 0; it < NB * NB / 256; ++it) {
+        const int idx = tid + 256 * it, i = idx >> 6, s = idx & 63;
+        const bool in = i < nb && s < nb;
+        Tu[i][s] = (i == s) ? 1.0 : ((in && s > i) ? ev[it] : 0.0);
+        Nl[i][s] = (in && s <= i) ? ev[it] : 0.0;
+    }
+    __syncthreads();
+    v4d acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+        const double a = Tu[16 * w + lo][4 * ks + hi];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Nl[4 * ks + hi][16 * ct + lo], acc[ct], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = 16 * w + hi + 4 * e, j = 16 * ct + lo;
+            if (i < nb && j < nb) st_res(A + (int64_t)i * lda + j, mod_red(acc[ct][e], P, PI));
+        }
 }
 
 template <typename T>
@@ -721,7 +759,7 @@ void launch_trulm_leaf(hipStream_t s, int nb, T* A, int64_t lda, ModP mp, int64_
     if (big_prime(mp))
         hipLaunchKernelGGL((trulm_leaf_kernel<T, true>), dim3(1), dim3(NB), 0, s, nb, A, lda, mp);
     else
-        hipLaunchKernelGGL((trulm_leaf_kernel<T, false>), dim3(1), dim3(NB), 0, s, nb, A, lda, mp);
+        hipLaunchKernelGGL(trulm_mfma_kernel<T>, dim3(1), dim3(256), 0, s, nb, A, lda, mp);
     CUP_HIP(hipGetLastError());
 }
 
