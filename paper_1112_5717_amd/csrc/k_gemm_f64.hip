@@ -11,9 +11,11 @@
 // p < 2^23), one launch per chunk.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup (4 wave64s, 64 x 64
-// each as 4 x 4 blocks of v_mfma_f64_16x16x4f64), or 64 x 64 tiles for
-// products too small to give two workgroups per CU; K tiles of 16 staged
-// through LDS (double-buffered, register prefetch of the next tile).
+// each as 4 x 4 blocks of v_mfma_f64_16x16x4f64), K tiles of 16 staged
+// through LDS (double-buffered, register prefetch of the next tile); products
+// too small to give two such workgroups per CU take 64 x 64 tiles with K in
+// steps of 128 (or all of K <= 64 at once), each step's loads in flight
+// together.
 #include <hip/hip_ext.h>
 
 #include "modarith.h"
@@ -36,6 +38,50 @@ __device__ __forceinline__ double centre(double v, double half, double p)
     return v > half ? v - p : v;
 }
 
+// The epilogue of the lane's outputs in TM x TN 16 x 16 blocks (rows
+// gm0 + 16 i + 4 e, columns gn0 + 16 j): epi_load reads every C entry from a
+// clamped, always valid address, so that all the loads are in flight
+// together (a load under the bounds test would wait on each one in turn);
+// epi_store reduces the sums to canonical residues and stores
+// C + alpha S mod p, predicated on the bounds.
+template <typename T, int TM, int TN>
+__device__ __forceinline__ void epi_load(int (&cv)[TM][TN][4], int gm0, int gn0, int M, int N,
+                                         const T* C, int64_t ldc)
+{
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = min(gm0 + i * 16 + 4 * e, M - 1), gn = min(gn0 + j * 16, N - 1);
+                cv[i][j][e] = ld_raw(C + (int64_t)gm * ldc + gn);
+            }
+}
+
+template <typename T, int TM, int TN>
+__device__ __forceinline__ void epi_store(const v4d (&acc)[TM][TN], const int (&cv)[TM][TN][4],
+                                          int gm0, int gn0, int M, int N, T* C, int64_t ldc,
+                                          ModP mp, int alpha)
+{
+    const int ip = (int)mp.p;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = gm0 + i * 16 + 4 * e, gn = gn0 + j * 16;
+                const int sv = (int)mod_red(acc[i][j][e], mp.p, mp.pinv);
+                if (gm < M && gn < N) {
+                    int r = (alpha < 0) ? cv[i][j][e] - sv : cv[i][j][e] + sv;
+                    r = (r < 0) ? r + ip : r;
+                    r = (r >= ip) ? r - ip : r;
+                    C[(int64_t)gm * ldc + gn] = (T)r;
+                }
+            }
+}
+
 // Workgroup tile BM x BN computed by 4 waves arranged 2 x 2, each a
 // (BM/2) x (BN/2) block of 16x16 MFMA tiles.
 template <typename T, int BM, int BN>
@@ -56,7 +102,7 @@ __global__ __launch_bounds__(256, 2) void ffgemm_f64_kernel(int M, int N, int K,
     const int wn = (wave & 1) * (BN / 2);
     const int m0 = blockIdx.y * BM;
     const int n0 = blockIdx.x * BN;
-    const double P = mp.p, PI = mp.pinv, half = floor(mp.p * 0.5);
+    const double P = mp.p, half = floor(mp.p * 0.5);
 
     v4d acc[TM][TN];
 #pragma unroll
@@ -139,31 +185,12 @@ __global__ __launch_bounds__(256, 2) void ffgemm_f64_kernel(int M, int N, int K,
     }
 
     // Epilogue: in each 16x16 block, lane l holds column l%16 of rows
-    // l/16 + 4e, e = 0..3 (the v_mfma_f64_16x16x4f64 result layout).  One
-    // block at a time, so the C loads of all 64 outputs are not hoisted
-    // together.
+    // l/16 + 4e, e = 0..3 (the v_mfma_f64_16x16x4f64 result layout).
     const int gn0 = n0 + wn + (lane & 15);
     const int gm0 = m0 + wm + (lane >> 4);
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int gn = gn0 + j * 16;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gm = gm0 + i * 16 + 4 * e;
-                if (gm < M && gn < N) {
-                    T* cp = C + (int64_t)gm * ldc + gn;
-                    double s = mod_red(acc[i][j][e], P, PI);
-                    double c = ld_res(cp);
-                    double r = (alpha < 0) ? c - s : c + s;
-                    r = (r < 0.0) ? r + P : r;
-                    r = (r >= P) ? r - P : r;
-                    st_res(cp, r);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
+    int cv[TM][TN][4];
+    epi_load<T, TM, TN>(cv, gm0, gn0, M, N, C, ldc);
+    epi_store<T, TM, TN>(acc, cv, gm0, gn0, M, N, C, ldc, mp, alpha);
 }
 
 // Products with K <= 64 (the thin updates of the triangular recursion and of
@@ -186,21 +213,13 @@ __global__ __launch_bounds__(256) void ffgemm_f64_k64_kernel(int M, int N, int K
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const double P = mp.p, PI = mp.pinv, half = floor(mp.p * 0.5);
+    const double P = mp.p, half = floor(mp.p * 0.5);
 
     // C entries of this thread's outputs (the MFMA result layout: lane l
     // holds column l % 16 of rows l / 16 + 4e of each 16 x 16 block)
     const int gn0 = n0 + wn + (lane & 15), gm0 = m0 + wm + (lane >> 4);
     int rc[TM][TN][4];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gm = min(gm0 + i * 16 + 4 * e, M - 1), gn = min(gn0 + j * 16, N - 1);
-                rc[i][j][e] = ld_raw(C + (int64_t)gm * ldc + gn);
-            }
+    epi_load<T, TM, TN>(rc, gm0, gn0, M, N, C, ldc);
     // A: 64 rows x 64 k, thread (row ar + 16 i, k = ac + 16 u); B: 64 k x 64 cols
     const int ac = tid & 15, ar = tid >> 4;
     int ra[4][4], rb[16];
@@ -248,24 +267,103 @@ __global__ __launch_bounds__(256) void ffgemm_f64_k64_kernel(int M, int N, int K
                 acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
 
+    epi_store<T, TM, TN>(acc, rc, gm0, gn0, M, N, C, ldc, mp, alpha);
+}
+
+// Products too small for two 128 x 128 workgroups per CU, with K > 64 (the
+// Schur complement updates of the low CUP levels, K = 128 to 512): 64 x 64
+// tiles, K in steps of 128.  All the loads of the next step are in flight
+// while the current step's 128 MFMAs per wave run, so a step pays its memory
+// latency once; the residues are staged in LDS as centred 32-bit integers
+// (80 KB for both operands) and converted to doubles as they are read.
+constexpr int DK = 128;
+constexpr int DPAD = 16;  // LDS row stride 64 + 16 ints: adjacent k-rows 16 banks apart
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void ffgemm_f64_deep_kernel(int M, int N, int K,
+                                                               const T* __restrict__ A, int64_t lda,
+                                                               const T* __restrict__ B, int64_t ldb,
+                                                               T* __restrict__ C, int64_t ldc, ModP mp,
+                                                               int alpha)
+{
+    constexpr int BM = 64, BN = 64, TM = 2, TN = 2;
+    __shared__ int As[DK][BM + DPAD];
+    __shared__ int Bs[DK][BN + DPAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int ip = (int)mp.p, ihalf = ip / 2;
+
+    // A: thread (row ar + 16 i, k = ac + 16 u); B: (k = br + 4 u, column bc).
+    // Rows beyond M and columns beyond N read a clamped (valid) address and
+    // feed only outputs that are never stored; k beyond K is zeroed.
+    const int ac = tid & 15, ar = tid >> 4, bc = tid & 63, br = tid >> 6;
+    const T* pa[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pa[i] = A + (int64_t)min(m0 + ar + 16 * i, M - 1) * lda;
+    const T* pb = B + min(n0 + bc, N - 1);
+    int ra[4][8], rb[32];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ra[i][u] = ld_raw(pa[i] + min(k0 + ac + 16 * u, K - 1));
+#pragma unroll
+        for (int u = 0; u < 32; ++u) rb[u] = ld_raw(pb + (int64_t)min(k0 + br + 4 * u, K - 1) * ldb);
+    };
+    auto centre_i = [&](int x, bool in) { return in ? ((x > ihalf) ? x - ip : x) : 0; };
+    auto store = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = ac + 16 * u;
+                As[k][ar + 16 * i] = centre_i(ra[i][u], k0 + k < K);
+            }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int k = br + 4 * u;
+            Bs[k][bc] = centre_i(rb[u], k0 + k < K);
+        }
+    };
+
+    v4d acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int gn = gn0 + j * 16;
+        for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    const int nk = (K + DK - 1) / DK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load((kt + 1) * DK);
+#pragma unroll 8
+        for (int ks = 0; ks < DK / 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            double a[TM], b[TN];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int gm = gm0 + i * 16 + 4 * e;
-                if (gm < M && gn < N) {
-                    const double sv = mod_red(acc[i][j][e], P, PI);
-                    const double c = (double)rc[i][j][e];
-                    double r = (alpha < 0) ? c - sv : c + sv;
-                    r = (r < 0.0) ? r + P : r;
-                    r = (r >= P) ? r - P : r;
-                    st_res(C + (int64_t)gm * ldc + gn, r);
-                }
-            }
+            for (int i = 0; i < TM; ++i) a[i] = (double)As[kk][wm + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[j] = (double)Bs[kk][wn + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        if (kt + 1 < nk) {
+            __syncthreads();
+            store((kt + 1) * DK);
+            __syncthreads();
+        }
+    }
+
+    const int gn0 = n0 + wn + (lane & 15), gm0 = m0 + wm + (lane >> 4);
+    int cv[TM][TN][4];
+    epi_load<T, TM, TN>(cv, gm0, gn0, M, N, C, ldc);
+    epi_store<T, TM, TN>(acc, cv, gm0, gn0, M, N, C, ldc, mp, alpha);
 }
 
 }  // namespace
@@ -299,7 +397,7 @@ void launch_ffgemm_f64(hipStream_t s, int M, int N, int K, const T* A, int64_t l
                                   N, kc, A + k0, lda, B + k0 * ldb, ldb, C, ldc, mp, alpha);
         } else {
             dim3 grid((N + 63) / 64, (M + 63) / 64);
-            hipExtLaunchKernelGGL((ffgemm_f64_kernel<T, 64, 64>), grid, dim3(256), 0, s, a, b, 0, M, N,
+            hipExtLaunchKernelGGL((ffgemm_f64_deep_kernel<T>), grid, dim3(256), 0, s, a, b, 0, M, N,
                                   kc, A + k0, lda, B + k0 * ldb, ldb, C, ldc, mp, alpha);
         }
         CUP_HIP(hipGetLastError());

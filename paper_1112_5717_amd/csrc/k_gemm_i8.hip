@@ -15,10 +15,13 @@
 // the paper's in-place definition allows, Section 3.1, Definition 1): A as
 // [M][Kp] bytes and B transposed as [N][Kp] bytes per limb, zero-padded to
 // tile multiples, so every MFMA operand is 16 contiguous bytes of k.  The
-// product kernel tiles 128 x 128 outputs per 256-thread workgroup (4 wave64s
-// of 64 x 64, as 4 x 4 blocks of v_mfma_i32_16x16x64_i8), K in steps of 64
+// product kernel tiles 128 x 128 outputs per 512-thread workgroup (8 wave64s
+// of 32 x 64, as 2 x 4 blocks of v_mfma_i32_16x16x64_i8), K in steps of 64
 // staged through LDS with double buffering; the epilogue reduces mod p in
-// FP64 and adds alpha S to C.
+// FP64 and adds alpha S to C.  With 8 waves of 32 x 64 the three limb
+// accumulators take 96 registers per lane, so two waves share each SIMD and
+// one hides the other's memory latency (four waves of 64 x 64 needed 192
+// accumulator registers, which left room for a single wave per SIMD).
 #include <hip/hip_ext.h>
 
 #include "modarith.h"
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(256) void pack_cols_kernel(const T* __restrict__ S,
 }
 
 template <typename T, int LIMB>
-__global__ __launch_bounds__(256) void ffgemm_i8_kernel(int M, int N, int Kp,
+__global__ __launch_bounds__(512) void ffgemm_i8_kernel(int M, int N, int Kp,
                                                         const int8_t* __restrict__ Ah,
                                                         const int8_t* __restrict__ Al,
                                                         const int8_t* __restrict__ Bh,
@@ -105,10 +108,10 @@ __global__ __launch_bounds__(256) void ffgemm_i8_kernel(int M, int N, int Kp,
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][NL][IBN * LROW];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
     const int m0 = blockIdx.y * IBM, n0 = blockIdx.x * IBN;
 
-    // global -> LDS: each thread moves 2 x 16 bytes per limb per operand
+    // global -> LDS: each thread moves 16 bytes per limb per operand
     const int lr = tid >> 2, lc = (tid & 3) * 16;
     const int8_t* gA[NL];
     const int8_t* gB[NL];
@@ -118,35 +121,31 @@ __global__ __launch_bounds__(256) void ffgemm_i8_kernel(int M, int N, int Kp,
         gA[NL - 1] = Al + (int64_t)(m0 + lr) * Kp + lc;
         gB[NL - 1] = Bl + (int64_t)(n0 + lr) * Kp + lc;
     }
-    const int64_t half_rows = (int64_t)64 * Kp;
-    v4i ra[NL][2], rb[NL][2];
+    v4i ra[NL], rb[NL];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < NL; ++q)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                ra[q][h] = *reinterpret_cast<const v4i*>(gA[q] + h * half_rows + k0);
-                rb[q][h] = *reinterpret_cast<const v4i*>(gB[q] + h * half_rows + k0);
-            }
+        for (int q = 0; q < NL; ++q) {
+            ra[q] = *reinterpret_cast<const v4i*>(gA[q] + k0);
+            rb[q] = *reinterpret_cast<const v4i*>(gB[q] + k0);
+        }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < NL; ++q)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                *reinterpret_cast<v4i*>(&As[buf][q][(lr + 64 * h) * LROW + lc]) = ra[q][h];
-                *reinterpret_cast<v4i*>(&Bs[buf][q][(lr + 64 * h) * LROW + lc]) = rb[q][h];
-            }
+        for (int q = 0; q < NL; ++q) {
+            *reinterpret_cast<v4i*>(&As[buf][q][lr * LROW + lc]) = ra[q];
+            *reinterpret_cast<v4i*>(&Bs[buf][q][lr * LROW + lc]) = rb[q];
+        }
     };
 
     constexpr int NACC = LIMB ? 3 : 1;
-    v4i acc[NACC][4][4];
+    constexpr int TM = 2, TN = 4;  // 16 x 16 blocks per wave
+    v4i acc[NACC][TM][TN];
 #pragma unroll
     for (int s = 0; s < NACC; ++s)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+            for (int j = 0; j < TN; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
 
     const int nk = Kp / IBK;
     load(0);
@@ -156,20 +155,20 @@ __global__ __launch_bounds__(256) void ffgemm_i8_kernel(int M, int N, int Kp,
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) load((kt + 1) * IBK);
-        v4i a[NL][4], b[NL][4];
+        v4i a[NL][TM], b[NL][TN];
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TM; ++i)
                 a[q][i] = *reinterpret_cast<const v4i*>(&As[buf][q][(wm + i * 16 + fr) * LROW + fk]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < TN; ++j)
                 b[q][j] = *reinterpret_cast<const v4i*>(&Bs[buf][q][(wn + j * 16 + fr) * LROW + fk]);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < TN; ++j) {
                 if (LIMB) {
                     acc[0][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][i], b[0][j], acc[0][i][j], 0, 0, 0);
                     acc[1][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][i], b[NL - 1][j], acc[1][i][j], 0, 0, 0);
@@ -184,34 +183,53 @@ __global__ __launch_bounds__(256) void ffgemm_i8_kernel(int M, int N, int Kp,
     }
 
     // Epilogue: lane l holds rows 4 (l/16) + e, column l % 16 of each block.
+    // The sums are reduced to canonical residues first (freeing the
+    // accumulators), then every C entry of the lane is loaded from a clamped,
+    // always valid address so that all 32 loads are in flight together (a
+    // load under the bounds test would wait on each one in turn); only the
+    // stores are predicated.
     const double P = mp.p, PI = mp.pinv;
+    const int ip = (int)mp.p;
     const int gm0 = m0 + wm + 4 * (lane >> 4), gn0 = n0 + wn + (lane & 15);
+    int sv[TM][TN][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int gn = gn0 + j * 16;
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gm = gm0 + i * 16 + e;
+                double s;
+                if (LIMB)
+                    s = 65536.0 * (double)acc[0][i][j][e] + 256.0 * (double)acc[1][i][j][e] +
+                        (double)acc[NACC - 1][i][j][e];
+                else
+                    s = (double)acc[0][i][j][e];
+                sv[i][j][e] = (int)mod_red(s, P, PI);
+            }
+    int cv[TM][TN][4];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = min(gm0 + i * 16 + e, M - 1), gn = min(gn0 + j * 16, N - 1);
+                cv[i][j][e] = res_int(C + (int64_t)gm * ldc + gn);
+            }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = gm0 + i * 16 + e, gn = gn0 + j * 16;
                 if (gm < M && gn < N) {
-                    double s;
-                    if (LIMB)
-                        s = 65536.0 * (double)acc[0][i][j][e] + 256.0 * (double)acc[1][i][j][e] +
-                            (double)acc[NACC - 1][i][j][e];
-                    else
-                        s = (double)acc[0][i][j][e];
-                    s = mod_red(s, P, PI);
-                    T* cp = C + (int64_t)gm * ldc + gn;
-                    const double c = ld_res(cp);
-                    double r = (alpha < 0) ? c - s : c + s;
-                    r = (r < 0.0) ? r + P : r;
-                    r = (r >= P) ? r - P : r;
-                    st_res(cp, r);
+                    int r = (alpha < 0) ? cv[i][j][e] - sv[i][j][e] : cv[i][j][e] + sv[i][j][e];
+                    r = (r < 0) ? r + ip : r;
+                    r = (r >= ip) ? r - ip : r;
+                    C[(int64_t)gm * ldc + gn] = (T)r;
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);
-        }
 }
 
 }  // namespace
@@ -276,10 +294,10 @@ void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, 
     const dim3 grid((unsigned)(Np / IBN), (unsigned)(Mp / IBM));
     // the events (timing only) are recorded by the dispatch itself
     if (limb)
-        hipExtLaunchKernelGGL((ffgemm_i8_kernel<T, 1>), grid, dim3(256), 0, s, ev0, ev1, 0, M, N, Kp,
+        hipExtLaunchKernelGGL((ffgemm_i8_kernel<T, 1>), grid, dim3(512), 0, s, ev0, ev1, 0, M, N, Kp,
                               q.Ah, q.Al, q.Bh, q.Bl, C, ldc, mp, alpha);
     else
-        hipExtLaunchKernelGGL((ffgemm_i8_kernel<T, 0>), grid, dim3(256), 0, s, ev0, ev1, 0, M, N, Kp,
+        hipExtLaunchKernelGGL((ffgemm_i8_kernel<T, 0>), grid, dim3(512), 0, s, ev0, ev1, 0, M, N, Kp,
                               q.Ah, q.Al, q.Bh, q.Bl, C, ldc, mp, alpha);
     CUP_HIP(hipGetLastError());
 }
