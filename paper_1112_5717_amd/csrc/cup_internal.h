@@ -79,6 +79,14 @@ template <typename T>
 void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, int64_t ldc,
                    ModP mp, int alpha, int limb, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// C(MxN) <- C + alpha A(MxK) B(KxN) mod p in I8LIMB arithmetic (p <= 2^16)
+// straight from the residue matrices, without packing launches: for the
+// products below the packed kernel's work threshold.
+template <typename T>
+void launch_mma_i8_direct(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, const T* B,
+                          int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr);
+
 // Window elimination of a leaf (see k_panel.hip).  Writes d, stop and the
 // chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col)
 // and, when `mail` is given (mapped host memory), the same values to

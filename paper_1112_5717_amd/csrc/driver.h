@@ -296,8 +296,9 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
           int64_t ldc, int alpha)
 {
     if (M <= 0 || N <= 0 || K <= 0) return;
-    // The INT8 forms pay two packing launches per product: small products
-    // stay on the FP64 carrier (the results are identical either way).
+    // The packed INT8 kernel pays two packing launches per product, so only
+    // large products take it; the others take the direct INT8-limb kernel or
+    // the FP64 carrier below (the results are identical either way).
     const bool i8 = (c.form == FORM_I8 || c.form == FORM_I8LIMB) && M >= 128 && N >= 128 &&
                     K >= 64 && (double)M * N * K >= c.i8_min_work;
     const bool prof = c.prof && c.prof->on;
@@ -331,7 +332,15 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
             e0 = r.a;
             e1 = r.b;
         }
-        launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps, e0, e1);
+        // In the INT8 forms (p <= 2^16) the smaller products with K > 64 take
+        // the INT8-limb kernel that reads the residues directly (no packing
+        // launches); K <= 64 stays on the FP64 carrier, whose single-step
+        // kernel pays one memory latency.
+        if ((c.form == FORM_I8 || c.form == FORM_I8LIMB) && K > 64)
+            launch_mma_i8_direct<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, e0, e1);
+        else
+            launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps, e0,
+                                 e1);
     }
 }
 

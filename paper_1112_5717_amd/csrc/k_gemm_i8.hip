@@ -232,6 +232,148 @@ __global__ __launch_bounds__(512) void ffgemm_i8_kernel(int M, int N, int Kp,
             }
 }
 
+// Products too small to repay the packing launches (below the work
+// threshold of the packed kernel: the Schur updates of the low CUP levels):
+// I8LIMB arithmetic straight from the residue matrices.  64 x 64 output tile
+// per 256-thread workgroup (4 waves of 32 x 32), K in steps of 128.  Every
+// load of a step is issued together; each thread loads four consecutive k of
+// one row of A (or one column of B), splits them into limbs and writes each
+// limb's four bytes as one 32-bit LDS word in MFMA operand order ([row][k]
+// and [column][k] per limb), so no packing launch is needed.
+constexpr int DKB = 128;         // K step
+constexpr int DROW = DKB + 16;   // LDS row stride in bytes (conflict-free 16-byte reads)
+
+__device__ __forceinline__ unsigned byte4(int b0, int b1, int b2, int b3)
+{
+    return (unsigned)(b0 & 0xff) | ((unsigned)(b1 & 0xff) << 8) | ((unsigned)(b2 & 0xff) << 16) |
+           ((unsigned)(b3 & 0xff) << 24);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void ffgemm_i8d_kernel(int M, int N, int K, const T* __restrict__ A,
+                                                          int64_t lda, const T* __restrict__ B,
+                                                          int64_t ldb, T* __restrict__ C, int64_t ldc,
+                                                          ModP mp, int alpha)
+{
+    __shared__ __attribute__((aligned(16))) int8_t As[2][64 * DROW];  // [limb][row][k]
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][64 * DROW];  // [limb][column][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int ip = (int)mp.p;
+
+    // A: row tid / 4, k = 4 (tid % 4) + 16 u + c; B: column tid % 64,
+    // k = 4 (tid / 64) + 16 u + c (u < 8, c < 4).  Rows past M and columns
+    // past N read a clamped (valid) address and feed only outputs that are
+    // never stored; k past K reads a clamped address and is zeroed.
+    const int arow = tid >> 2, ak = 4 * (tid & 3), bcol = tid & 63, bk = 4 * (tid >> 6);
+    const T* pa = A + (int64_t)min(m0 + arow, M - 1) * lda;
+    const T* pb = B + min(n0 + bcol, N - 1);
+    int ra[8][4], rb[8][4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ra[u][c] = res_int(pa + min(k0 + ak + 16 * u + c, K - 1));
+                rb[u][c] = res_int(pb + (int64_t)min(k0 + bk + 16 * u + c, K - 1) * ldb);
+            }
+    };
+    auto store = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            int ha[4], la[4], hb[4], lb[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                limbs((k0 + ak + 16 * u + c < K) ? ra[u][c] : 0, ip, ha[c], la[c]);
+                limbs((k0 + bk + 16 * u + c < K) ? rb[u][c] : 0, ip, hb[c], lb[c]);
+            }
+            const int oa = arow * DROW + ak + 16 * u, ob = bcol * DROW + bk + 16 * u;
+            *reinterpret_cast<unsigned*>(&As[0][oa]) = byte4(ha[0], ha[1], ha[2], ha[3]);
+            *reinterpret_cast<unsigned*>(&As[1][oa]) = byte4(la[0], la[1], la[2], la[3]);
+            *reinterpret_cast<unsigned*>(&Bs[0][ob]) = byte4(hb[0], hb[1], hb[2], hb[3]);
+            *reinterpret_cast<unsigned*>(&Bs[1][ob]) = byte4(lb[0], lb[1], lb[2], lb[3]);
+        }
+    };
+
+    constexpr int TM = 2, TN = 2;
+    v4i acc[3][TM][TN];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+
+    const int fr = lane & 15, fk = (lane >> 4) * 16;
+    const int nk = (K + DKB - 1) / DKB;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load((kt + 1) * DKB);
+#pragma unroll
+        for (int kk = 0; kk < DKB; kk += 64) {
+            v4i a[2][TM], b[2][TN];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    a[q][i] = *reinterpret_cast<const v4i*>(&As[q][(wm + i * 16 + fr) * DROW + kk + fk]);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    b[q][j] = *reinterpret_cast<const v4i*>(&Bs[q][(wn + j * 16 + fr) * DROW + kk + fk]);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][i], b[0][j], acc[0][i][j], 0, 0, 0);
+                    acc[1][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0][i], b[1][j], acc[1][i][j], 0, 0, 0);
+                    acc[1][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1][i], b[0][j], acc[1][i][j], 0, 0, 0);
+                    acc[2][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1][i], b[1][j], acc[2][i][j], 0, 0, 0);
+                }
+        }
+        if (kt + 1 < nk) {
+            __syncthreads();
+            store((kt + 1) * DKB);
+            __syncthreads();
+        }
+    }
+
+    // Epilogue as in the packed kernel: canonical residues first, all C
+    // loads in flight together, predicated stores.
+    const double P = mp.p, PI = mp.pinv;
+    const int gm0 = m0 + wm + 4 * (lane >> 4), gn0 = n0 + wn + (lane & 15);
+    int sv[TM][TN][4], cv[TM][TN][4];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double s = 65536.0 * (double)acc[0][i][j][e] + 256.0 * (double)acc[1][i][j][e] +
+                                 (double)acc[2][i][j][e];
+                sv[i][j][e] = (int)mod_red(s, P, PI);
+                const int gm = min(gm0 + i * 16 + e, M - 1), gn = min(gn0 + j * 16, N - 1);
+                cv[i][j][e] = res_int(C + (int64_t)gm * ldc + gn);
+            }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = gm0 + i * 16 + e, gn = gn0 + j * 16;
+                if (gm < M && gn < N) {
+                    int r = (alpha < 0) ? cv[i][j][e] - sv[i][j][e] : cv[i][j][e] + sv[i][j][e];
+                    r = (r < 0) ? r + ip : r;
+                    r = (r >= ip) ? r - ip : r;
+                    C[(int64_t)gm * ldc + gn] = (T)r;
+                }
+            }
+}
+
 }  // namespace
 
 int ffgemm_i8_kmax(int limb) { return limb ? 65472 : 131072; }  // INT32 stays exact
@@ -302,11 +444,32 @@ void launch_mma_i8(hipStream_t s, int M, int N, int Kp, const int8_t* ws, T* C, 
     CUP_HIP(hipGetLastError());
 }
 
+template <typename T>
+void launch_mma_i8_direct(hipStream_t s, int M, int N, int K, const T* A, int64_t lda, const T* B,
+                          int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, hipEvent_t ev0,
+                          hipEvent_t ev1)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return;
+    const int kmax = ffgemm_i8_kmax(1);
+    const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+    for (int k0 = 0; k0 < K; k0 += kmax) {
+        const int kc = std::min(kmax, K - k0);
+        // timing events (optional) open with the first chunk and close with the last
+        hipEvent_t a = (k0 == 0) ? ev0 : nullptr;
+        hipEvent_t b = (k0 + kmax >= K) ? ev1 : nullptr;
+        hipExtLaunchKernelGGL((ffgemm_i8d_kernel<T>), grid, dim3(256), 0, s, a, b, 0, M, N, kc, A + k0,
+                              lda, B + (int64_t)k0 * ldb, ldb, C, ldc, mp, alpha);
+        CUP_HIP(hipGetLastError());
+    }
+}
+
 #define CUP_INST(T)                                                                             \
     template int launch_pack_i8<T>(hipStream_t, int, int, int, const T*, int64_t, const T*,     \
                                    int64_t, ModP, int, int8_t*);                                \
     template void launch_mma_i8<T>(hipStream_t, int, int, int, const int8_t*, T*, int64_t, ModP, \
-                                   int, int, hipEvent_t, hipEvent_t);
+                                   int, int, hipEvent_t, hipEvent_t);                           \
+    template void launch_mma_i8_direct<T>(hipStream_t, int, int, int, const T*, int64_t, const T*, \
+                                          int64_t, T*, int64_t, ModP, int, hipEvent_t, hipEvent_t);
 CUP_INST(int64_t)
 CUP_INST(int8_t)
 #undef CUP_INST

@@ -386,6 +386,85 @@ def test_ffgemm_limb_window_extremes(cup_lib, monkeypatch, p):
         cup_lib.cup_set_form("auto")
 
 
+def _i8_direct_products(monkeypatch):
+    """Keep every product below the packed kernel's work threshold, so that
+    every product with K > 64 takes the direct INT8-limb kernel."""
+    monkeypatch.setenv("CUP_I8_MIN_WORK", "1e30")
+
+
+@pytest.mark.parametrize("form,p,dtype", [("i8limb", 65521, "int64"), ("i8limb", 257, "int64"),
+                                          ("i8limb", 2, "int64"), ("i8limb", 32771, "int64"),
+                                          ("i8", 127, "int8"), ("i8", 3, "int64")])
+@pytest.mark.parametrize("shape", [(1, 1, 65), (63, 65, 129), (200, 300, 513), (128, 2100, 128),
+                                   (70, 40, 1000), (8, 9, 70000)])
+def test_ffgemm_direct_i8(cup_lib, monkeypatch, form, p, dtype, shape):
+    """The direct INT8-limb product: ragged tiles, K tails, and K beyond one
+    launch's exact accumulation (70000 > 65472 terms: two launches)."""
+    _i8_direct_products(monkeypatch)
+    M, N, K = shape
+    rng = np.random.default_rng(M * 3 + N + K + p)
+    A = rng.integers(0, p, size=(M, K), dtype=np.int64)
+    B = rng.integers(0, p, size=(K, N), dtype=np.int64)
+    C = rng.integers(0, p, size=(M, N), dtype=np.int64)
+    tdt = torch.int8 if dtype == "int8" else torch.int64
+    cup_lib.cup_set_form(form)
+    try:
+        for alpha in (-1, 1):
+            dC = dev(C, tdt)
+            cup_lib.cup_ffgemm(dC, dev(A, tdt), dev(B, tdt), p, alpha)
+            assert np.array_equal(host(dC), exact_gemm(C, A, B, p, alpha)), (form, p, alpha)
+    finally:
+        cup_lib.cup_set_form("auto")
+
+
+@pytest.mark.parametrize("p", [65521, 40009])
+def test_ffgemm_direct_limb_extremes(cup_lib, monkeypatch, p):
+    """Residues at both ends of the signed limb window and at p - 1, summed
+    over a full launch's worth of terms, through the direct kernel."""
+    _i8_direct_products(monkeypatch)
+    vals = np.array([0, 1, 127, 128, 255, 256, 32639, 32640, p - 129, p - 128, p - 1], dtype=np.int64) % p
+    M, N, K = 96, 80, 65472
+    rng = np.random.default_rng(p + 1)
+    A = vals[rng.integers(0, len(vals), size=(M, K))]
+    B = vals[rng.integers(0, len(vals), size=(K, N))]
+    A[:8, :] = p - 1
+    B[:, :8] = p - 1
+    A[8:16, :] = 32640 % p
+    B[:, 8:16] = 32640 % p
+    C = np.full((M, N), p - 1, dtype=np.int64)
+    cup_lib.cup_set_form("i8limb")
+    try:
+        dC = dev(C)
+        cup_lib.cup_ffgemm(dC, dev(A), dev(B), p, -1)
+        assert np.array_equal(host(dC), exact_gemm(C, A, B, p, -1))
+    finally:
+        cup_lib.cup_set_form("auto")
+
+
+@pytest.mark.parametrize("form,p,i8", [("i8limb", 65521, False), ("i8", 127, True)])
+def test_cup_direct_products_vs_oracle(cup_lib, monkeypatch, form, p, i8):
+    """CUP, RREF and inverse with every product below the packed kernel's threshold."""
+    _i8_direct_products(monkeypatch)
+    cup_lib.cup_set_form(form)
+    try:
+        for m, n, rank in [(700, 520, None), (600, 600, 350), (1100, 260, None)]:
+            A = structured(m, n, p, m + n + 1, rank=rank)
+            assert_same_cup(run_cup(cup_lib, A, p, i8=i8), oracle.cup(A, p), f"{form} {m}x{n}")
+        if not i8:
+            A = structured(500, 420, p, 19, rank=300)
+            d = dev(A)
+            r, P, Q = cup_lib.cup_rref_inplace(d, p)
+            O, rr, rP, rQ = oracle.rref_packed(A, p)
+            assert r == rr and np.array_equal(host(d), O)
+            B = inputs.uniform((384, 384), p, seed=78)
+            X = oracle.inverse(B, p)
+            d = dev(B)
+            ok, r = cup_lib.cup_inverse_inplace(d, p)
+            assert ok and np.array_equal(host(d), X)
+    finally:
+        cup_lib.cup_set_form("auto")
+
+
 @pytest.mark.parametrize("form,p,i8", [("i8limb", 65521, False), ("i8", 127, True), ("i8", 127, False),
                                        ("fp64", 65521, False)])
 def test_cup_forms_vs_oracle(cup_lib, monkeypatch, form, p, i8):
