@@ -161,11 +161,12 @@ void launch_diag_prep2(hipStream_t s, T* A, int64_t lda, int n, int uplo, int un
                        int expect = 0);
 
 // X = B U^{-1} in place for an upper U of order n (n <= 512, a multiple of
-// 64) with its 64 x 64 diagonal-block inverses in W; B is rows x n.
-// Returns false (nothing launched) outside those limits.
+// 64) with its 64 x 64 diagonal-block inverses in W; B is rows x n.  With
+// int8_mfma (the INT8 forms) and p <= 2^16, int64 storage runs on the INT8
+// matrix cores.  Returns false (nothing launched) outside those limits.
 template <typename T>
 bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double* W, T* B,
-                     int64_t ldb, int rows, ModP mp);
+                     int64_t ldb, int rows, ModP mp, bool int8_mfma);
 
 template <typename T>
 void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, int64_t ldb,

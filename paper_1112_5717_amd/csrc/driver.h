@@ -356,7 +356,8 @@ void tri_rec(Ctx& c, int op, int side, int uplo, int n, const T* Tm, int64_t ldt
 {
     // right solves with an upper triangle of order <= 512: one fused launch
     if (op == SOLVE && side == RIGHT && uplo == UPPER && n > kTriNB &&
-        launch_tri_slab<T>(c.s, n, Tm, ldt, W, B, ldb, other, c.mp))
+        launch_tri_slab<T>(c.s, n, Tm, ldt, W, B, ldb, other, c.mp,
+                           c.form == FORM_I8 || c.form == FORM_I8LIMB))
         return;
     if (n <= kTriNB) {
         launch_tri_apply<T>(c.s, side, n, W, B, ldb, other, c.mp);

@@ -479,6 +479,174 @@ __global__ __launch_bounds__(256) void tri_slab_mfma_kernel(int n, const T* __re
     }
 }
 
+// The same solve for p <= 2^16 on the INT8 matrix cores.  A residue x is
+// split into two signed bytes x = 256 h + l (x taken in [-(p - 32640), 32639]
+// first), and a 64-term product X U becomes four v_mfma_i32_16x16x64_i8
+// (h h, the two cross terms sharing one accumulator, l l) instead of sixteen
+// FP64 MFMAs, so the chain of dependent products that bounds the solve is
+// about sixteen times shorter.  The INT32 sums of all the tiles of a block
+// stay exact (at most 8 tiles of 64 terms, each below 2^15 in magnitude) and
+// are recombined and reduced once per block.  One workgroup per 16 rows of
+// B; wave w owns columns 16w..16w+15 of every 64-column block.  The solved
+// blocks live in LDS as limb bytes in A-operand order ([row][k]); the U and
+// W tiles stream from global memory as B operands (16 consecutive k of one
+// column per lane) through three register buffers with identical loads in
+// every step, so no use waits for a later fetch.  int64 storage only.
+__device__ __forceinline__ void slab_limbs(int x, int p, int& h, int& l)
+{
+    const int xc = (x <= 32639) ? x : x - p;
+    h = (xc + 128) >> 8;
+    l = xc - 256 * h;
+}
+
+__device__ __forceinline__ int slab_byte4(const int* b)
+{
+    return (int)((unsigned)(b[0] & 0xff) | ((unsigned)(b[1] & 0xff) << 8) |
+                 ((unsigned)(b[2] & 0xff) << 16) | ((unsigned)(b[3] & 0xff) << 24));
+}
+
+constexpr int SXR = 80;  // LDS row stride of the limb blocks, bytes (conflict-free 16-byte reads)
+
+template <int NMAXC>
+__global__ __launch_bounds__(256) void tri_slab_i8_kernel(int n, const int64_t* __restrict__ U,
+                                                          int64_t ldu, const double* __restrict__ W,
+                                                          int64_t* __restrict__ B, int64_t ldb, int rows,
+                                                          ModP mp)
+{
+    typedef int v4i_t __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) int8_t Xq[2][NMAXC / NB][16 * SXR];
+    __shared__ __attribute__((aligned(16))) int8_t Eq[2][16 * SXR];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int hi = lane >> 4, lo = lane & 15;
+    const int ip = (int)mp.p;
+    const double P = mp.p, PI = mp.pinv;
+    const int v0 = blockIdx.x * 16;
+    const int nbk = n / NB;
+    // Result layout (v_mfma_i32_16x16x64_i8): rows 4 hi + e (e < 4), column
+    // 16 w + lo of a block; rows past the end are clamped and not stored.
+    int64_t roff[4];
+    bool rok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = v0 + 4 * hi + e;
+        rok[e] = r < rows;
+        roff[e] = (int64_t)min(r, rows - 1) * ldb;
+    }
+    // Tile stream: for each block l, U_0l .. U_(l-1)l, then W_l.  This lane's
+    // B-operand entries are rows 16 hi + t (t < 16) of the tile, column
+    // 16 w + lo; the B entries of the tile's block come along.  Registers hold
+    // raw 64-bit words (a U residue, or the bits of a W double).
+    struct Tile {
+        long long r[16];
+        long long bv[4];
+    };
+    int fl = 0, fj = 0;  // next tile to fetch
+    auto fetch_next = [&](Tile& tl) {
+        const int l = min(fl, nbk - 1);
+        const int j = (fl < nbk) ? fj : l;
+        const bool isu = j < l;
+        const long long* usrc = reinterpret_cast<const long long*>(U) + (int64_t)(NB * j + 16 * hi) * ldu +
+                                NB * l + 16 * w + lo;
+        const long long* wsrc = reinterpret_cast<const long long*>(W) + (size_t)l * NB * NB +
+                                16 * hi * NB + 16 * w + lo;
+        const long long* src = isu ? usrc : wsrc;
+        const int64_t st = isu ? ldu : (int64_t)NB;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) tl.r[t] = src[t * st];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tl.bv[e] = B[roff[e] + NB * l + 16 * w + lo];
+        if (fl < nbk && ++fj > fl) {
+            ++fl;
+            fj = 0;
+        }
+    };
+    // The two limb operands of a tile (W entries may be negative: made canonical).
+    auto operand = [&](const Tile& c, bool isw, v4i_t& oh, v4i_t& ol) {
+        int hb[16], lb[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            int x = isw ? (int)__longlong_as_double(c.r[t]) : (int)c.r[t];
+            x = (x < 0) ? x + ip : x;
+            slab_limbs(x, ip, hb[t], lb[t]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            oh[q] = slab_byte4(hb + 4 * q);
+            ol[q] = slab_byte4(lb + 4 * q);
+        }
+    };
+    auto recombine = [&](const v4i_t (&a)[3], int e) {
+        return mod_red(65536.0 * (double)a[0][e] + 256.0 * (double)a[1][e] + (double)a[2][e], P, PI);
+    };
+    // this lane's bytes of the limb blocks: rows 4 hi + e, column 16 w + lo
+    auto put = [&](int8_t* hbase, int8_t* lbase, int e, int x) {
+        int h, l;
+        slab_limbs(x, ip, h, l);
+        hbase[(4 * hi + e) * SXR + 16 * w + lo] = (int8_t)h;
+        lbase[(4 * hi + e) * SXR + 16 * w + lo] = (int8_t)l;
+    };
+
+    const int ntiles = nbk * (nbk + 1) / 2;
+    Tile buf0, buf1, buf2;
+    fetch_next(buf0);
+    fetch_next(buf1);
+    int l = 0, j = 0;  // tile being used: U_jl (j < l) or W_l (j == l)
+    v4i_t acc[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) acc[s] = v4i_t{0, 0, 0, 0};
+    // Every step fetches (also the padding steps that complete the last group
+    // of three, which do nothing else), so all paths issue the same loads.
+    auto step = [&](const Tile& cur, Tile& pf, bool live) {
+        fetch_next(pf);
+        if (!live) {
+        } else if (j < l) {
+            v4i_t uh, ul;
+            operand(cur, false, uh, ul);
+            const v4i_t xh = *reinterpret_cast<const v4i_t*>(&Xq[0][j][lo * SXR + 16 * hi]);
+            const v4i_t xl = *reinterpret_cast<const v4i_t*>(&Xq[1][j][lo * SXR + 16 * hi]);
+            acc[0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xh, uh, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xh, ul, acc[1], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xl, uh, acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xl, ul, acc[2], 0, 0, 0);
+            ++j;
+        } else {
+            // E = B_l - sum_j X_j U_jl, exchanged through LDS as limb bytes
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double tt = (double)(int)cur.bv[e] - recombine(acc, e);
+                put(Eq[0], Eq[1], e, (int)((tt < 0.0) ? tt + P : tt));
+            }
+            __syncthreads();
+            const v4i_t eh = *reinterpret_cast<const v4i_t*>(&Eq[0][lo * SXR + 16 * hi]);
+            const v4i_t el = *reinterpret_cast<const v4i_t*>(&Eq[1][lo * SXR + 16 * hi]);
+            v4i_t wh, wl;
+            operand(cur, true, wh, wl);
+            v4i_t xa[3];
+            xa[0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(eh, wh, v4i_t{0, 0, 0, 0}, 0, 0, 0);
+            xa[1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(eh, wl, v4i_t{0, 0, 0, 0}, 0, 0, 0);
+            xa[1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(el, wh, xa[1], 0, 0, 0);
+            xa[2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(el, wl, v4i_t{0, 0, 0, 0}, 0, 0, 0);
+            const int col = NB * l + 16 * w + lo;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double x = recombine(xa, e);
+                if (rok[e]) B[roff[e] + col] = (int64_t)(int)x;
+                put(Xq[0][l], Xq[1][l], e, (int)x);
+            }
+#pragma unroll
+            for (int s = 0; s < 3; ++s) acc[s] = v4i_t{0, 0, 0, 0};
+            __syncthreads();
+            ++l;
+            j = 0;
+        }
+    };
+    for (int t = 0; t < ntiles; t += 3) {
+        step(buf0, buf2, true);
+        step(buf1, buf0, t + 1 < ntiles);
+        step(buf2, buf1, t + 2 < ntiles);
+    }
+}
+
 // Two-leaf node whose first leaf (rows 0..63, the pivots in columns 0..63)
 // was decided as a full block with no column exchange, and whose second leaf
 // is the 64 rows below.  The leaf's solve of its other columns, Algorithm 6's
@@ -715,10 +883,18 @@ void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, in
 
 template <typename T>
 bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double* W, T* B,
-                     int64_t ldb, int rows, ModP mp)
+                     int64_t ldb, int rows, ModP mp, bool int8_mfma)
 {
     if (n <= 0 || n > SLAB_LIMIT || n % NB != 0 || rows <= 0) return false;
     const bool big = big_prime(mp);
+    if constexpr (sizeof(T) == sizeof(int64_t)) {
+        if (int8_mfma && mp.p <= 65536.0) {
+            hipLaunchKernelGGL((tri_slab_i8_kernel<SLAB_LIMIT>), dim3((rows + 15) / 16), dim3(256), 0, s, n,
+                               U, ldu, W, B, ldb, rows, mp);
+            CUP_HIP(hipGetLastError());
+            return true;
+        }
+    }
     if (!big) {
         dim3 grid((rows + 15) / 16);
         if (n <= 256)
@@ -786,7 +962,7 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
     template void launch_pair_update<T>(hipStream_t, T*, int64_t, int, const double*, const int*, \
                                         ModP);                                                    \
     template bool launch_tri_slab<T>(hipStream_t, int, const T*, int64_t, const double*, T*,    \
-                                     int64_t, int, ModP);                                       \
+                                     int64_t, int, ModP, bool);                                       \
     template void launch_negate<T>(hipStream_t, T*, int64_t, int, int, ModP);
 CUP_INST(int64_t)
 CUP_INST(int8_t)

@@ -115,6 +115,8 @@ CUP_CASES = [
     # solve (orders 64..1024), with a prime past the 64-term bound
     (1100, 1100, 65521, None, False), (2100, 2100, 33554393, None, False),
     (1500, 1300, 8388593, None, False), (1088, 1200, 2, None, False),
+    # the INT8-limb right solve at other primes and ragged row counts
+    (1300, 1100, 32771, None, False), (777, 1500, 257, None, False),
 ]
 
 
