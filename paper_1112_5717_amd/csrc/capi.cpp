@@ -200,6 +200,7 @@ int factor_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* ran
             Ql.reserve((size_t)std::min(m, n));
             ucache_begin(c, A, lda, (int)std::min(m, n));
             r = cup_rec<T>(c, A, lda, (int)m, (int)n, Pl, Ql);
+            flush_defer(c);
             c.base = nullptr;
         }
         if (tail >= 1 && r > 0) {

@@ -160,13 +160,25 @@ void launch_diag_prep2(hipStream_t s, T* A, int64_t lda, int n, int uplo, int un
                        T* A2, int uplo2, int unit2, double* W2, ModP mp, const int* guard = nullptr,
                        int expect = 0);
 
+// A left apply B <- W B (W 64 x 64, B 64 x other): a 64-row leaf's solve of
+// its columns right of its pivots, which a slab launch may carry along.
+struct LeftApply {
+    const double* W = nullptr;
+    void* B = nullptr;
+    int64_t ldb = 0;
+    int other = 0;
+};
+
 // X = B U^{-1} in place for an upper U of order n (n <= 512, a multiple of
 // 64) with its 64 x 64 diagonal-block inverses in W; B is rows x n.  With
 // int8_mfma (the INT8 forms) and p <= 2^16, int64 storage runs on the INT8
-// matrix cores.  Returns false (nothing launched) outside those limits.
+// matrix cores, and then `carry` (if given) is done by the same launch, and
+// *carried set; its B must not overlap U, W or this B.  Returns false
+// (nothing launched) outside those limits.
 template <typename T>
 bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double* W, T* B,
-                     int64_t ldb, int rows, ModP mp, bool int8_mfma);
+                     int64_t ldb, int rows, ModP mp, bool int8_mfma, const LeftApply* carry = nullptr,
+                     bool* carried = nullptr);
 
 template <typename T>
 void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, int64_t ldb,

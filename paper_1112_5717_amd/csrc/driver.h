@@ -117,6 +117,12 @@ struct Ctx {
     // the node's G and Schur update.
     void* pair_below = nullptr;
     bool pair_done = false;
+    // A full leaf's solve of its columns right of its pivots, held back so
+    // that the parent's slab launch can carry it (it touches neither the
+    // parent's U block nor the rows below); launched by itself before
+    // anything that does touch it.
+    LeftApply defer;
+    bool defer_on = false;
     int log = 0;
     double i8_min_work = 1.0e9;  // M N K below which products stay on FP64
     // The matrix being factored (its top-left and leading dimension) and
@@ -238,8 +244,21 @@ inline unsigned next_seq(Ctx& c)
     return s;
 }
 
+// Launch the held-back leaf solve, if any (only int64 storage holds one back).
+inline void flush_defer(Ctx& c)
+{
+    if (!c.defer_on) return;
+    c.defer_on = false;
+    launch_tri_apply<int64_t>(c.s, LEFT, kLeafRows, c.defer.W, static_cast<int64_t*>(c.defer.B),
+                              c.defer.ldb, c.defer.other, c.mp);
+}
+
+// The triangular workspace; a held-back leaf solve reads its inverse from it,
+// so that solve is launched first (stream order) before the buffer is
+// handed out again or reallocated.
 inline double* tri_workspace(Ctx& c, int n)
 {
+    flush_defer(c);
     const size_t need = (size_t)((n + kTriNB - 1) / kTriNB) * kTriNB * kTriNB;
     Workspace& w = *c.ws;
     if (need > w.tri_cap) {
@@ -355,10 +374,15 @@ void tri_rec(Ctx& c, int op, int side, int uplo, int n, const T* Tm, int64_t ldt
              int64_t ldb, int other, const double* W)
 {
     // right solves with an upper triangle of order <= 512: one fused launch
-    if (op == SOLVE && side == RIGHT && uplo == UPPER && n > kTriNB &&
-        launch_tri_slab<T>(c.s, n, Tm, ldt, W, B, ldb, other, c.mp,
-                           c.form == FORM_I8 || c.form == FORM_I8LIMB))
-        return;
+    if (op == SOLVE && side == RIGHT && uplo == UPPER && n > kTriNB) {
+        bool carried = false;
+        if (launch_tri_slab<T>(c.s, n, Tm, ldt, W, B, ldb, other, c.mp,
+                               c.form == FORM_I8 || c.form == FORM_I8LIMB,
+                               c.defer_on ? &c.defer : nullptr, &carried)) {
+            if (carried) c.defer_on = false;
+            return;
+        }
+    }
     if (n <= kTriNB) {
         launch_tri_apply<T>(c.s, side, n, W, B, ldb, other, c.mp);
         return;
@@ -598,15 +622,27 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         // node's G (in the window) and, with its own solve, the Schur update
         // of those rows (one launch), when the window exchanges no column.
         const bool pair = fused && below != nullptr && winv != nullptr;
+        flush_defer(c);
         launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small, c.mail_d, seq, winv, uinv,
                          pair ? below : nullptr);
         if (prof) c.prof->end(c.s);
         if (pair) {
             launch_pair_update<T>(c.s, A, lda, N, winv, c.d_small, c.mp);
         } else if (fused) {
-            if (winv)
+            // held back (and dropped unless the window finds 64 pivots) when
+            // the parent's slab solve runs on the INT8 matrix cores and can
+            // carry it; otherwise launched now, doing nothing unless it does
+            if (winv && sizeof(T) == sizeof(int64_t) && c.mp.p <= 65536.0 &&
+                (c.form == FORM_I8 || c.form == FORM_I8LIMB)) {
+                c.defer.W = winv;
+                c.defer.B = A + wc;
+                c.defer.ldb = lda;
+                c.defer.other = N - wc;
+                c.defer_on = true;
+            } else if (winv) {
                 launch_tri_apply<T>(c.s, LEFT, kLeafRows, winv, A + wc, lda, N - wc, c.mp, c.d_small,
                                     kLeafRows);
+            }
         } else if (ahead) {
             leaf_followup(c, A, lda, b, N, 0, 0, wc, kLeafRows, c.d_small);
         }
@@ -614,6 +650,7 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         await_window(c, seq, h);
         const int d = h[0], stop = h[1];
         if (stop == STOP_FAIL) throw CupError{-3000};  // CUP_ERR_INTERNAL
+        if (d != kLeafRows) c.defer_on = false;  // the held-back solve would do nothing
         for (int a = 0; a < d; ++a) {
             int col = h[2 + a];
             if (a == 0 && pending >= 0) col = pending;
@@ -707,17 +744,24 @@ int cup_rec(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& P,
         for (int bb = 0; W1 && bb < r1 / kTriNB; ++bb)
             if ((size_t)(g0 / kTriNB + bb) >= c.uc_ok.size() || !c.uc_ok[(size_t)(g0 / kTriNB + bb)])
                 W1 = nullptr;
+        // (a leaf solve held back by the top half's last leaf touches its own
+        // rows right of column r1 only: the solve for G may carry it, the
+        // Schur update needs it done)
         if (W1)
             tri_rec(c, SOLVE, RIGHT, UPPER, r1, A, lda, A2, lda, m - k, (const double*)W1);
         else
             trsm(c, RIGHT, UPPER, 1, r1, A, lda, A2, lda, m - k);
+        flush_defer(c);
         if (r1 == n) return r1;
         gemm(c, m - k, n - r1, r1, A2, lda, A + r1, lda, A2 + r1, lda, -1); // H = A22 - G V1
     }
     const int r2 = cup_rec(c, A2 + r1, lda, m - k, n - r1, P, Q);
     if (r2 > 0) {
         if (r1 > 0) apply_transpositions(c, A + r1, lda, r1, P.data() + p0 + r1, r2);  // V1 P2^T
-        if (k > r1) launch_rowmove_shift<T>(c.s, A, lda, n, r1, k, r2);
+        if (k > r1) {
+            flush_defer(c);  // the moved rows include the bottom half's last leaf
+            launch_rowmove_shift<T>(c.s, A, lda, n, r1, k, r2);
+        }
     }
     for (size_t x = p0 + r1; x < P.size(); ++x) P[x] += r1;
     for (size_t x = q0 + r1; x < Q.size(); ++x) Q[x] += k;

@@ -186,18 +186,16 @@ __global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64
 // columns (left) of B; each thread computes 4 of their 16 x 64 outputs.
 constexpr int AV = 16;  // vectors per workgroup
 
+// The work of workgroup blk (also run by the combined launch with the slab solve).
 template <typename T, bool BIG>
-__global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const double* __restrict__ W,
-                                                        T* __restrict__ B, int64_t ldb, int other,
-                                                        ModP mp, const int* __restrict__ guard,
-                                                        int expect)
+__device__ __forceinline__ void tri_apply_block(int blk, int side, int nb, const double* __restrict__ W,
+                                                T* __restrict__ B, int64_t ldb, int other, ModP mp)
 {
-    if (guard && *guard != expect) return;  // launched ahead of a pivot count that differs
     __shared__ double Ws[NB][NB + 1];
     __shared__ double Bs[AV][NB + 1];
     const int tid = threadIdx.x;
     const double P = mp.p, PI = mp.pinv;
-    const int v0 = blockIdx.x * AV;
+    const int v0 = blk * AV;
     const int nv = min(AV, other - v0);
     // all loads of a thread issued together (addresses clamped, selects after)
     {
@@ -262,6 +260,16 @@ __global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const 
             }
         }
     }
+}
+
+template <typename T, bool BIG>
+__global__ __launch_bounds__(256) void tri_apply_kernel(int side, int nb, const double* __restrict__ W,
+                                                        T* __restrict__ B, int64_t ldb, int other,
+                                                        ModP mp, const int* __restrict__ guard,
+                                                        int expect)
+{
+    if (guard && *guard != expect) return;  // launched ahead of a pivot count that differs
+    tri_apply_block<T, BIG>(blockIdx.x, side, nb, W, B, ldb, other, mp);
 }
 
 // Whole right solve X = B U^{-1} for an upper U of order n <= 512 (n a
@@ -508,10 +516,9 @@ __device__ __forceinline__ int slab_byte4(const int* b)
 constexpr int SXR = 80;  // LDS row stride of the limb blocks, bytes (conflict-free 16-byte reads)
 
 template <int NMAXC>
-__global__ __launch_bounds__(256) void tri_slab_i8_kernel(int n, const int64_t* __restrict__ U,
-                                                          int64_t ldu, const double* __restrict__ W,
-                                                          int64_t* __restrict__ B, int64_t ldb, int rows,
-                                                          ModP mp)
+__device__ __forceinline__ void tri_slab_i8_block(int blk, int n, const int64_t* __restrict__ U,
+                                                  int64_t ldu, const double* __restrict__ W,
+                                                  int64_t* __restrict__ B, int64_t ldb, int rows, ModP mp)
 {
     typedef int v4i_t __attribute__((ext_vector_type(4)));
     __shared__ __attribute__((aligned(16))) int8_t Xq[2][NMAXC / NB][16 * SXR];
@@ -520,7 +527,7 @@ __global__ __launch_bounds__(256) void tri_slab_i8_kernel(int n, const int64_t* 
     const int hi = lane >> 4, lo = lane & 15;
     const int ip = (int)mp.p;
     const double P = mp.p, PI = mp.pinv;
-    const int v0 = blockIdx.x * 16;
+    const int v0 = blk * 16;
     const int nbk = n / NB;
     // Result layout (v_mfma_i32_16x16x64_i8): rows 4 hi + e (e < 4), column
     // 16 w + lo of a block; rows past the end are clamped and not stored.
@@ -645,6 +652,32 @@ __global__ __launch_bounds__(256) void tri_slab_i8_kernel(int n, const int64_t* 
         step(buf1, buf0, t + 1 < ntiles);
         step(buf2, buf1, t + 2 < ntiles);
     }
+}
+
+template <int NMAXC>
+__global__ __launch_bounds__(256) void tri_slab_i8_kernel(int n, const int64_t* __restrict__ U,
+                                                          int64_t ldu, const double* __restrict__ W,
+                                                          int64_t* __restrict__ B, int64_t ldb, int rows,
+                                                          ModP mp)
+{
+    tri_slab_i8_block<NMAXC>(blockIdx.x, n, U, ldu, W, B, ldb, rows, mp);
+}
+
+// The slab solve and an independent left apply B2 <- W2 B2 (a 64-row leaf's
+// solve of its columns right of its pivots, which the solve's rows and
+// columns do not touch) in one launch: the first workgroups solve, the
+// others apply.  Saves the launch gap between them and lets them overlap.
+template <int NMAXC>
+__global__ __launch_bounds__(256) void slab_apply_kernel(int n, const int64_t* __restrict__ U, int64_t ldu,
+                                                         const double* __restrict__ W,
+                                                         int64_t* __restrict__ B, int64_t ldb, int rows,
+                                                         ModP mp, int nslab, const double* __restrict__ W2,
+                                                         int64_t* __restrict__ B2, int64_t ldb2, int other2)
+{
+    if ((int)blockIdx.x < nslab)
+        tri_slab_i8_block<NMAXC>(blockIdx.x, n, U, ldu, W, B, ldb, rows, mp);
+    else
+        tri_apply_block<int64_t, false>(blockIdx.x - nslab, 0, NB, W2, B2, ldb2, other2, mp);
 }
 
 // Two-leaf node whose first leaf (rows 0..63, the pivots in columns 0..63)
@@ -883,14 +916,25 @@ void launch_tri_apply(hipStream_t s, int side, int nb, const double* W, T* B, in
 
 template <typename T>
 bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double* W, T* B,
-                     int64_t ldb, int rows, ModP mp, bool int8_mfma)
+                     int64_t ldb, int rows, ModP mp, bool int8_mfma, const LeftApply* carry,
+                     bool* carried)
 {
+    if (carried) *carried = false;
     if (n <= 0 || n > SLAB_LIMIT || n % NB != 0 || rows <= 0) return false;
     const bool big = big_prime(mp);
     if constexpr (sizeof(T) == sizeof(int64_t)) {
         if (int8_mfma && mp.p <= 65536.0) {
-            hipLaunchKernelGGL((tri_slab_i8_kernel<SLAB_LIMIT>), dim3((rows + 15) / 16), dim3(256), 0, s, n,
-                               U, ldu, W, B, ldb, rows, mp);
+            const int nslab = (rows + 15) / 16;
+            if (carry && carry->other > 0 && carried) {
+                const int napply = (carry->other + AV - 1) / AV;
+                hipLaunchKernelGGL((slab_apply_kernel<SLAB_LIMIT>), dim3(nslab + napply), dim3(256), 0, s, n,
+                                   U, ldu, W, B, ldb, rows, mp, nslab, carry->W,
+                                   static_cast<int64_t*>(carry->B), carry->ldb, carry->other);
+                *carried = true;
+            } else {
+                hipLaunchKernelGGL((tri_slab_i8_kernel<SLAB_LIMIT>), dim3(nslab), dim3(256), 0, s, n, U,
+                                   ldu, W, B, ldb, rows, mp);
+            }
             CUP_HIP(hipGetLastError());
             return true;
         }
@@ -962,7 +1006,7 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
     template void launch_pair_update<T>(hipStream_t, T*, int64_t, int, const double*, const int*, \
                                         ModP);                                                    \
     template bool launch_tri_slab<T>(hipStream_t, int, const T*, int64_t, const double*, T*,    \
-                                     int64_t, int, ModP, bool);                                       \
+                                     int64_t, int, ModP, bool, const LeftApply*, bool*);                                       \
     template void launch_negate<T>(hipStream_t, T*, int64_t, int, int, ModP);
 CUP_INST(int64_t)
 CUP_INST(int8_t)
