@@ -654,6 +654,62 @@ __device__ __forceinline__ void tri_slab_i8_block(int blk, int n, const int64_t*
     }
 }
 
+// The left apply B <- W B (W 64 x 64, B 64 x other, in place) for p <= 2^16
+// on the INT8 matrix cores: workgroup blk owns 16 columns of B, wave w forms
+// rows 16w..16w+15 of them with four v_mfma_i32_16x16x64_i8 on the limbs.
+// Operands come straight from global memory (a W row and a B column of 16
+// entries per lane), so no LDS is needed; a barrier keeps every wave's reads
+// of the old B ahead of the stores.
+__device__ __forceinline__ void tri_apply_i8_block(int blk, const double* __restrict__ W,
+                                                   int64_t* __restrict__ B, int64_t ldb, int other,
+                                                   ModP mp)
+{
+    typedef int v4i_t __attribute__((ext_vector_type(4)));
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int hi = lane >> 4, lo = lane & 15;
+    const int ip = (int)mp.p;
+    const double P = mp.p, PI = mp.pinv;
+    const int col = blk * 16 + lo;
+    const int ccol = min(col, other - 1);
+    double wv[16];
+    int bv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        wv[t] = W[(16 * w + lo) * NB + 16 * hi + t];
+        bv[t] = (int)B[(int64_t)(16 * hi + t) * ldb + ccol];
+    }
+    int ah[16], al[16], bh[16], bl[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        int x = (int)wv[t];
+        x = (x < 0) ? x + ip : x;
+        slab_limbs(x, ip, ah[t], al[t]);
+        slab_limbs(bv[t], ip, bh[t], bl[t]);
+    }
+    v4i_t oah, oal, obh, obl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        oah[q] = slab_byte4(ah + 4 * q);
+        oal[q] = slab_byte4(al + 4 * q);
+        obh[q] = slab_byte4(bh + 4 * q);
+        obl[q] = slab_byte4(bl + 4 * q);
+    }
+    const v4i_t z = {0, 0, 0, 0};
+    const v4i_t s0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(oah, obh, z, 0, 0, 0);
+    v4i_t s1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(oah, obl, z, 0, 0, 0);
+    s1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(oal, obh, s1, 0, 0, 0);
+    const v4i_t s2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(oal, obl, z, 0, 0, 0);
+    double x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        x[e] = mod_red(65536.0 * (double)s0[e] + 256.0 * (double)s1[e] + (double)s2[e], P, PI);
+    __syncthreads();  // every wave has read the old B columns
+    if (col < other) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) B[(int64_t)(16 * w + 4 * hi + e) * ldb + col] = (int64_t)(int)x[e];
+    }
+}
+
 template <int NMAXC>
 __global__ __launch_bounds__(256) void tri_slab_i8_kernel(int n, const int64_t* __restrict__ U,
                                                           int64_t ldu, const double* __restrict__ W,
@@ -677,7 +733,7 @@ __global__ __launch_bounds__(256) void slab_apply_kernel(int n, const int64_t* _
     if ((int)blockIdx.x < nslab)
         tri_slab_i8_block<NMAXC>(blockIdx.x, n, U, ldu, W, B, ldb, rows, mp);
     else
-        tri_apply_block<int64_t, false>(blockIdx.x - nslab, 0, NB, W2, B2, ldb2, other2, mp);
+        tri_apply_i8_block(blockIdx.x - nslab, W2, B2, ldb2, other2, mp);
 }
 
 // Two-leaf node whose first leaf (rows 0..63, the pivots in columns 0..63)
@@ -926,7 +982,7 @@ bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double
         if (int8_mfma && mp.p <= 65536.0) {
             const int nslab = (rows + 15) / 16;
             if (carry && carry->other > 0 && carried) {
-                const int napply = (carry->other + AV - 1) / AV;
+                const int napply = (carry->other + 15) / 16;
                 hipLaunchKernelGGL((slab_apply_kernel<SLAB_LIMIT>), dim3(nslab + napply), dim3(256), 0, s, n,
                                    U, ldu, W, B, ldb, rows, mp, nslab, carry->W,
                                    static_cast<int64_t*>(carry->B), carry->ldb, carry->other);
