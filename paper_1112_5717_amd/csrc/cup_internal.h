@@ -110,9 +110,11 @@ constexpr int kSwapWord = 2 + kLeafRows;
 // block with no exchange, U12 = L^{-1} T and H = B - G U12 for every column
 // right of the block, in one launch; nothing unless guard[0] == 64 and
 // guard[kSwapWord] == 0.
+// With int8_mfma (the INT8 forms), p <= 2^16 and int64 storage, on the INT8
+// matrix cores.
 template <typename T>
 void launch_pair_update(hipStream_t s, T* A, int64_t lda, int N, const double* WL, const int* guard,
-                        ModP mp);
+                        ModP mp, bool int8_mfma = false);
 
 // For each row r in [i0,b): leftmost nonzero column >= t0 (or N), into out[r-i0]
 // and, when `mail` is given, into mail[kMailScan + r - i0] as a word tagged

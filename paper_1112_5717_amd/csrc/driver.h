@@ -627,7 +627,8 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
                          pair ? below : nullptr);
         if (prof) c.prof->end(c.s);
         if (pair) {
-            launch_pair_update<T>(c.s, A, lda, N, winv, c.d_small, c.mp);
+            launch_pair_update<T>(c.s, A, lda, N, winv, c.d_small, c.mp,
+                                  c.form == FORM_I8 || c.form == FORM_I8LIMB);
         } else if (fused) {
             // held back (and dropped unless the window finds 64 pivots) when
             // the parent's slab solve runs on the INT8 matrix cores and can

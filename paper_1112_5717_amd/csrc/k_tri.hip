@@ -820,6 +820,106 @@ __global__ __launch_bounds__(256) void pair_update_kernel(T* __restrict__ A, int
     }
 }
 
+// The same two-leaf update for p <= 2^16 on the INT8 matrix cores (int64
+// storage): each 64-term product of a 16 x 16 tile is four
+// v_mfma_i32_16x16x64_i8 on the limbs.  Wave w forms rows 16w..16w+15 of
+// U12 and of H for the workgroup's 32 columns; L^{-1} and G rows and the T
+// columns are read from global memory straight into operands, and U12 goes
+// through LDS as limb bytes in B-operand order ([column][k]).
+template <typename T>
+__global__ __launch_bounds__(256) void pair_update_i8_kernel(T* __restrict__ A, int64_t lda, int N,
+                                                             const double* __restrict__ WL,
+                                                             const int* __restrict__ guard, ModP mp)
+{
+    typedef int v4i_t __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) int8_t Uq[2][PC * SXR];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hi = lane >> 4, lo = lane & 15;
+    const int ip = (int)mp.p;
+    const double P = mp.p, PI = mp.pinv;
+    const int c0 = NB + PC * blockIdx.x;
+    T* Bm = A + (int64_t)NB * lda;
+    // every load first (columns past N clamped; not stored), the guard
+    // checked before anything is written
+    const int g0 = guard[0], g1 = guard[kSwapWord];
+    double wl[16];
+    int gv[16], tv[2][16], bv[2][4];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        wl[t] = WL[(16 * w + lo) * NB + 16 * hi + t];
+        gv[t] = (int)Bm[(int64_t)(16 * w + lo) * lda + 16 * hi + t];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+            tv[ct][t] = (int)A[(int64_t)(16 * hi + t) * lda + min(c0 + 16 * ct + lo, N - 1)];
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            bv[ct][e] = (int)Bm[(int64_t)(16 * w + 4 * hi + e) * lda + min(c0 + 16 * ct + lo, N - 1)];
+    if (g0 != kLeafRows || g1 != 0) return;
+    auto split = [&](const int* x, v4i_t& oh, v4i_t& ol) {
+        int h[16], l[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) slab_limbs(x[t], ip, h[t], l[t]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            oh[q] = slab_byte4(h + 4 * q);
+            ol[q] = slab_byte4(l + 4 * q);
+        }
+    };
+    v4i_t lh, ll, gh, gl;
+    {
+        int x[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int v = (int)wl[t];
+            x[t] = (v < 0) ? v + ip : v;
+        }
+        split(x, lh, ll);
+        split(gv, gh, gl);
+    }
+    const v4i_t z = {0, 0, 0, 0};
+    // U12 = L^{-1} T
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        v4i_t th, tl;
+        split(tv[ct], th, tl);
+        const v4i_t s0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(lh, th, z, 0, 0, 0);
+        v4i_t s1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(lh, tl, z, 0, 0, 0);
+        s1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(ll, th, s1, 0, 0, 0);
+        const v4i_t s2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(ll, tl, z, 0, 0, 0);
+        const int c = c0 + 16 * ct + lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int u = (int)mod_red(65536.0 * (double)s0[e] + 256.0 * (double)s1[e] + (double)s2[e], P, PI);
+            const int row = 16 * w + 4 * hi + e;
+            int h, l;
+            slab_limbs(u, ip, h, l);
+            Uq[0][(16 * ct + lo) * SXR + row] = (int8_t)h;
+            Uq[1][(16 * ct + lo) * SXR + row] = (int8_t)l;
+            if (c < N) A[(int64_t)row * lda + c] = (T)u;
+        }
+    }
+    __syncthreads();
+    // H = B - G U12
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        const v4i_t uh = *reinterpret_cast<const v4i_t*>(&Uq[0][(16 * ct + lo) * SXR + 16 * hi]);
+        const v4i_t ul = *reinterpret_cast<const v4i_t*>(&Uq[1][(16 * ct + lo) * SXR + 16 * hi]);
+        const v4i_t s0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(gh, uh, z, 0, 0, 0);
+        v4i_t s1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(gh, ul, z, 0, 0, 0);
+        s1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(gl, uh, s1, 0, 0, 0);
+        const v4i_t s2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(gl, ul, z, 0, 0, 0);
+        const int c = c0 + 16 * ct + lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double g = mod_red(65536.0 * (double)s0[e] + 256.0 * (double)s1[e] + (double)s2[e], P, PI);
+            const double h = (double)bv[ct][e] - g;
+            if (c < N) Bm[(int64_t)(16 * w + 4 * hi + e) * lda + c] = (T)(int)((h < 0.0) ? h + P : h);
+        }
+    }
+}
+
 // [N\T] <- T N on an nb x nb block (nb <= 64): T unit upper (strict upper
 // part stored), N lower with its diagonal.  Thread j holds column j of N;
 // used for p > kExact64 (every product reduced as it is added).
@@ -1019,9 +1119,17 @@ bool launch_tri_slab(hipStream_t s, int n, const T* U, int64_t ldu, const double
 
 template <typename T>
 void launch_pair_update(hipStream_t s, T* A, int64_t lda, int N, const double* WL, const int* guard,
-                        ModP mp)
+                        ModP mp, bool int8_mfma)
 {
     if (N <= NB) return;
+    if constexpr (sizeof(T) == sizeof(int64_t)) {
+        if (int8_mfma && mp.p <= 65536.0) {
+            hipLaunchKernelGGL(pair_update_i8_kernel<T>, dim3((N - NB + PC - 1) / PC), dim3(256), 0, s, A, lda,
+                               N, WL, guard, mp);
+            CUP_HIP(hipGetLastError());
+            return;
+        }
+    }
     hipLaunchKernelGGL(pair_update_kernel<T>, dim3((N - NB + PC - 1) / PC), dim3(256), 0, s, A, lda, N,
                        WL, guard, mp);
     CUP_HIP(hipGetLastError());
@@ -1060,7 +1168,7 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
                                       ModP, const int*, int);                                   \
     template void launch_trulm_leaf<T>(hipStream_t, int, T*, int64_t, ModP, int64_t);           \
     template void launch_pair_update<T>(hipStream_t, T*, int64_t, int, const double*, const int*, \
-                                        ModP);                                                    \
+                                        ModP, bool);                                              \
     template bool launch_tri_slab<T>(hipStream_t, int, const T*, int64_t, const double*, T*,    \
                                      int64_t, int, ModP, bool, const LeftApply*, bool*);                                       \
     template void launch_negate<T>(hipStream_t, T*, int64_t, int, int, ModP);
