@@ -307,6 +307,19 @@ __global__ __launch_bounds__(256, 2) void ffgemm_i8d_kernel(int M, int N, int K,
 
     const int fr = lane & 15, fk = (lane >> 4) * 16;
     const int nk = (K + DKB - 1) / DKB;
+    // the C entries this lane updates are read with the first operands (one
+    // memory latency for a single-step K)
+    const int gm0 = m0 + wm + 4 * (lane >> 4), gn0 = n0 + wn + (lane & 15);
+    int cv[TM][TN][4];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = min(gm0 + i * 16 + e, M - 1), gn = min(gn0 + j * 16, N - 1);
+                cv[i][j][e] = res_int(C + (int64_t)gm * ldc + gn);
+            }
     load(0);
     store(0);
     __syncthreads();
@@ -341,11 +354,9 @@ __global__ __launch_bounds__(256, 2) void ffgemm_i8d_kernel(int M, int N, int K,
         }
     }
 
-    // Epilogue as in the packed kernel: canonical residues first, all C
-    // loads in flight together, predicated stores.
+    // Epilogue: canonical residues, predicated stores.
     const double P = mp.p, PI = mp.pinv;
-    const int gm0 = m0 + wm + 4 * (lane >> 4), gn0 = n0 + wn + (lane & 15);
-    int sv[TM][TN][4], cv[TM][TN][4];
+    int sv[TM][TN][4];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -355,8 +366,6 @@ __global__ __launch_bounds__(256, 2) void ffgemm_i8d_kernel(int M, int N, int K,
                 const double s = 65536.0 * (double)acc[0][i][j][e] + 256.0 * (double)acc[1][i][j][e] +
                                  (double)acc[2][i][j][e];
                 sv[i][j][e] = (int)mod_red(s, P, PI);
-                const int gm = min(gm0 + i * 16 + e, M - 1), gn = min(gn0 + j * 16, N - 1);
-                cv[i][j][e] = res_int(C + (int64_t)gm * ldc + gn);
             }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
