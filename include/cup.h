@@ -177,10 +177,17 @@ const char *cup_strerror(int status);
  * Kernel timing for measurement.  cup_profile(1) resets and starts timing
  * every ffgemm launch and every leaf-window launch with a pair of HIP events
  * on the launch stream (no extra synchronisation); cup_profile(0) stops.
+ * A value above 1 times only the classes whose bits it sets, bit k + 1 for
+ * class k below (2: the FP64-carrier and direct products, 8: the INT8
+ * product kernel): those product launches record their own events, so
+ * timing them alone adds no work to the stream, while the window and
+ * packing classes (4 and 16) add an event record before and after each
+ * launch.  Returns -1 for a value outside 0 .. 31.
  * cup_profile_read fills stats[16] with four figures for each of four
  * kernel classes: {launches, kernel ms, algorithmic field operations
- * (2MNK per product), algorithmic bytes} for (0) the FP64-carrier ffgemm
- * (bytes (MK + KN + 2MN) x element size), (1) the leaf window kernel
+ * (2MNK per product), algorithmic bytes} for (0) the products below the
+ * INT8 kernel's threshold (FP64 carrier, or the direct INT8-limb kernel in
+ * the INT8 forms; bytes (MK + KN + 2MN) x element size), (1) the leaf window kernel
  * (operations 0, bytes one read and one write of its tile), (2) the INT8
  * ffgemm product kernel (bytes: packed operands read once plus C read and
  * written), (3) the INT8 operand packing (operations 0, bytes read and

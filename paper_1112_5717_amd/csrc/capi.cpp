@@ -428,10 +428,13 @@ const char* cup_strerror(int status)
 
 int cup_profile(int enable)
 {
+    // 1: every class; above 1: bit k + 1 selects class k
+    if (enable < 0 || enable > (2 << kProfKinds) - 1) return -1;
     Global& g = G();
     std::lock_guard<std::mutex> lk(g.mu);
     if (enable) g.prof.reset();
     g.prof.on = enable != 0;
+    g.prof.mask = (enable == 1) ? ((1u << kProfKinds) - 1) : ((unsigned)enable >> 1);
     return CUP_OK;
 }
 

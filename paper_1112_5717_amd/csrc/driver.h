@@ -35,6 +35,8 @@ struct ProfRec {
 
 struct Profiler {
     bool on = false;
+    unsigned mask = 0;  // kernel classes timed (bit k: class k)
+    bool want(int kind) const { return on && ((mask >> kind) & 1u); }
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<ProfRec> recs;
@@ -320,7 +322,9 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
     // the FP64 carrier below (the results are identical either way).
     const bool i8 = (c.form == FORM_I8 || c.form == FORM_I8LIMB) && M >= 128 && N >= 128 &&
                     K >= 64 && (double)M * N * K >= c.i8_min_work;
-    const bool prof = c.prof && c.prof->on;
+    const bool prof_pack = c.prof && c.prof->want(3);
+    const bool prof_i8 = c.prof && c.prof->want(2);
+    const bool prof_small = c.prof && c.prof->want(0);
     if (i8) {
         const int limb = (c.form == FORM_I8LIMB) ? 1 : 0;
         const int nl = limb ? 2 : 1;
@@ -328,14 +332,14 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
         const int kmax = ffgemm_i8_kmax(limb);
         for (int k0 = 0; k0 < K; k0 += kmax) {
             const int kc = std::min(kmax, K - k0);
-            if (prof)
+            if (prof_pack)
                 c.prof->begin(c.s, 3, 0.0,
                               ((double)M * kc + (double)kc * N) * (sizeof(T) + nl));
             const int Kp = launch_pack_i8<T>(c.s, M, N, kc, A + k0, lda, B + (int64_t)k0 * ldb, ldb,
                                              c.mp, limb, ws);
+            if (prof_pack) c.prof->end(c.s);
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (prof) {
-                c.prof->end(c.s);
+            if (prof_i8) {
                 ProfRec& r = c.prof->open(2, 2.0 * M * N * kc,
                                           ((double)M * kc + (double)kc * N) * nl + 2.0 * M * N * sizeof(T));
                 e0 = r.a;
@@ -345,7 +349,7 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
         }
     } else {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (prof) {
+        if (prof_small) {
             ProfRec& r = c.prof->open(0, 2.0 * M * N * K,
                                       ((double)M * K + (double)K * N + 2.0 * M * N) * sizeof(T));
             e0 = r.a;
@@ -599,7 +603,7 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
     c.pair_below = nullptr;
     while (i < b && t < N) {
         const int wc = std::min(kWin, N - t);
-        const bool prof = c.prof && c.prof->on;
+        const bool prof = c.prof && c.prof->want(1);
         if (prof) c.prof->begin(c.s, 1, 0.0, 2.0 * (b - i) * wc * sizeof(T));
         const unsigned seq = next_seq(c);
         // The usual outcome of a leaf's first window, 64 pivots, has its

@@ -258,8 +258,13 @@ def cup_ffgemm(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, p: int, alpha:
         raise CupError(rc, name)
 
 
-def cup_profile(enable: bool) -> None:
-    load().cup_profile(1 if enable else 0)
+def cup_profile(enable) -> None:
+    """True/False: time every kernel class or stop; an int above 1 selects
+    classes by bit (k + 1 for class k, as in include/cup.h)."""
+    mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+    rc = load().cup_profile(mode)
+    if rc < 0:
+        raise CupError(rc, "cup_profile")
 
 
 def cup_profile_read() -> dict:

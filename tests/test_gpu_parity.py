@@ -498,3 +498,25 @@ def test_rref_inverse_i8limb(cup_lib, monkeypatch):
         assert ok and np.array_equal(host(d), X)
     finally:
         cup_lib.cup_set_form("auto")
+
+
+def test_profile_classes(cup_lib, monkeypatch):
+    """cup_profile with a class mask times only those classes (here the INT8
+    product, whose launches record their own events); other values are refused."""
+    _i8_small_products(monkeypatch)
+    p = 65521
+    A = inputs.uniform((700, 700), p, seed=5)
+    cup_lib.cup_set_form("i8limb")
+    try:
+        cup_lib.cup_profile(8)
+        run_cup(cup_lib, A, p)
+        st = cup_lib.cup_profile_read()
+        cup_lib.cup_profile(False)
+        assert st["ffgemm_i8"]["launches"] > 0 and st["ffgemm_i8"]["ms"] > 0
+        assert st["window"]["launches"] == 0 and st["pack_i8"]["launches"] == 0
+        assert st["ffgemm"]["launches"] == 0
+        with pytest.raises(cup_lib.CupError):
+            cup_lib.cup_profile(32)
+    finally:
+        cup_lib.cup_profile(False)
+        cup_lib.cup_set_form("auto")
