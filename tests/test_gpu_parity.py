@@ -520,3 +520,47 @@ def test_profile_classes(cup_lib, monkeypatch):
     finally:
         cup_lib.cup_profile(False)
         cup_lib.cup_set_form("auto")
+
+
+def _row_blocks(blocks, n, p, seed):
+    """Rows in blocks of (rows, rank): each block a random product X Y of that
+    rank over GF(p) (rank 0: zero rows), so the leaves' ranks are known."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for rows, rank in blocks:
+        if rank == 0:
+            out.append(np.zeros((rows, n), dtype=np.int64))
+            continue
+        X = rng.integers(0, p, size=(rows, rank), dtype=np.int64)
+        Y = rng.integers(0, p, size=(rank, n), dtype=np.int64)
+        out.append(inputs.product_mod(X, Y, p))
+    return np.concatenate(out, axis=0)
+
+
+HELD_BACK_CASES = [
+    # a full leaf after a deficient one: the parent's U is not a whole number
+    # of 64-blocks (the held-back solve goes out before the general solve)
+    ("deficient-then-full", [(64, 50), (64, 64), (128, 128)], 400),
+    # a deficient top half: the bottom half's rows move up (row move after a
+    # full leaf that held its solve back)
+    ("row-move", [(64, 64), (64, 20), (64, 64), (64, 64)], 300),
+    # full leaves only, ending the matrix: the last held-back solve goes out
+    # when the call returns
+    ("full-to-the-end", [(64, 64), (64, 64), (64, 64)], 500),
+    # zero rows between full leaves
+    ("zero-rows", [(64, 64), (64, 0), (64, 64), (64, 64)], 320),
+]
+
+
+@pytest.mark.parametrize("case", HELD_BACK_CASES, ids=[c[0] for c in HELD_BACK_CASES])
+@pytest.mark.parametrize("p", [65521, 257])
+def test_cup_held_back_solve_paths(cup_lib, case, p):
+    """CUP in the INT8-limb form where full leaves hold their solve back, on
+    rank patterns that send it out by each of its paths."""
+    name, blocks, n = case
+    A = _row_blocks(blocks, n, p, seed=len(name) + p)
+    cup_lib.cup_set_form("i8limb")
+    try:
+        assert_same_cup(run_cup(cup_lib, A, p), oracle.cup(A, p), f"{name} p={p}")
+    finally:
+        cup_lib.cup_set_form("auto")
