@@ -51,6 +51,16 @@ def _load():
         lib.oracle_rref_pack.restype = ctypes.c_int
         lib.oracle_inv_mod.argtypes = [i64, i64]
         lib.oracle_inv_mod.restype = i64
+        lib.oracle_mm.argtypes = [i64, i64, i64, i64, p64, p64, p64, i64]
+        lib.oracle_mm.restype = ctypes.c_int
+        lib.oracle_ple.argtypes = [i64, i64, i64, p64, p64, p64, p64]
+        lib.oracle_ple.restype = ctypes.c_int
+        lib.oracle_det.argtypes = [i64, i64, p64]
+        lib.oracle_det.restype = i64
+        lib.oracle_solve.argtypes = [i64, i64, i64, p64, p64, p64]
+        lib.oracle_solve.restype = ctypes.c_int
+        lib.oracle_nullspace.argtypes = [i64, i64, i64, p64, i64, p64, p64]
+        lib.oracle_nullspace.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -133,6 +143,94 @@ def rref_packed(A, p: int):
     if rc != 0:
         raise MemoryError("oracle_rref_pack failed")
     return O, r, P, Q
+
+
+def mm(C, A, B, p: int, alpha: int = 1) -> np.ndarray:
+    """C + alpha A B mod p (Algorithm 1, from the definition of the product)."""
+    A, B = _mat(A), _mat(B)
+    out = _mat(C).copy()
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2 and out.shape == (M, N) and alpha in (1, -1)
+    if M and N:
+        A1 = A if A.size else np.zeros(1, dtype=np.int64)
+        B1 = B if B.size else np.zeros(1, dtype=np.int64)
+        _load().oracle_mm(M, N, K, int(p), _ptr(A1), _ptr(B1), _ptr(out), int(alpha))
+    return out
+
+
+def ple(A, p: int):
+    """PLE decomposition (Section 5, Algorithm 10, unrolled column by column).
+
+    Returns ``(packed, rank, P, Q)``: packed [L\\E], the rank, the row
+    transposition list P (length m) and Q (length n) whose first ``rank``
+    entries are the column rank profile.
+    """
+    A = _mat(A).copy()
+    m, n = A.shape
+    P = np.zeros(max(m, 1), dtype=np.int64)
+    Q = np.zeros(max(n, 1), dtype=np.int64)
+    r = ctypes.c_int64(0)
+    rc = _load().oracle_ple(m, n, int(p), _ptr(A), ctypes.byref(r), _ptr(P), _ptr(Q))
+    if rc != 0:
+        raise MemoryError("oracle_ple failed")
+    return A, int(r.value), P[:m].copy(), Q[:n].copy()
+
+
+def det(A, p: int) -> int:
+    """Determinant by classical Gaussian elimination (Section 4.4)."""
+    A = _mat(A)
+    n = A.shape[0]
+    assert A.shape == (n, n)
+    if n == 0:
+        return 1 % int(p)
+    d = int(_load().oracle_det(n, int(p), _ptr(A)))
+    if d < 0:
+        raise MemoryError("oracle_det failed")
+    return d
+
+
+def solve(A, B, p: int):
+    """X with A X = B for nonsingular A (Gauss-Jordan on [A | B]); None if singular."""
+    A, B = _mat(A), _mat(B)
+    n = A.shape[0]
+    nrhs = B.shape[1]
+    assert A.shape == (n, n) and B.shape[0] == n
+    X = np.zeros((n, nrhs), dtype=np.int64)
+    if n == 0 or nrhs == 0:
+        return X
+    rc = _load().oracle_solve(n, nrhs, int(p), _ptr(A), _ptr(B), _ptr(X))
+    if rc < 0:
+        raise MemoryError("oracle_solve failed")
+    return None if rc == 1 else X
+
+
+def nullspace(A, p: int):
+    """Right nullspace basis N (n x (n - r)) in the column order of the CUP
+    transposition list (Section 3.4); returns ``(N, rank, P)``."""
+    A = _mat(A)
+    m, n = A.shape
+    _, r, P, _ = cup(A, p)
+    N = np.zeros((n, n - r), dtype=np.int64)
+    if n - r > 0:
+        A1 = A if A.size else np.zeros(1, dtype=np.int64)
+        Pc = np.ascontiguousarray(P if n > 0 else np.zeros(1, dtype=np.int64))
+        rc = _load().oracle_nullspace(m, n, int(p), _ptr(A1), r, _ptr(Pc), _ptr(N))
+        if rc != 0:
+            raise RuntimeError("oracle_nullspace failed (%d)" % rc)
+    return N, r, P
+
+
+def unpack_ple(packed: np.ndarray, r: int):
+    """Split packed [L\\E] into L (m x m unit lower) and E (m x n, zero below row r)."""
+    m, n = packed.shape
+    L = np.eye(m, dtype=np.int64)
+    E = np.zeros((m, n), dtype=np.int64)
+    for i in range(min(r, m)):
+        E[i, i:] = packed[i, i:]
+    for j in range(min(r, n)):
+        L[j + 1:, j] = packed[j + 1:, j]
+    return L, E
 
 
 def unpack_cup(packed: np.ndarray, r: int):

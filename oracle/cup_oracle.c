@@ -6,7 +6,10 @@
  * "Rank-profile revealing Gaussian elimination and the CUP matrix
  * decomposition", Section 3.3, Algorithm 6), together with independent
  * oracles for the reduced column echelon form (Section 2.2, Proposition 1 and
- * Section 3.5, Proposition 5) and the inverse (Section 4.3).
+ * Section 3.5, Proposition 5), the inverse (Section 4.3), the matrix product
+ * (Section 3.2, Algorithm 1), the PLE decomposition (Section 5,
+ * Algorithm 10), and the invariants of Section 4.4 (determinant, system
+ * solution, nullspace basis).
  *
  * Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark may load this file.  The GPU library shares no code with it and
@@ -295,5 +298,258 @@ int oracle_rref_pack(int64_t m, int64_t n, int64_t p, const int64_t *CU,
             O[i * n + j] = v;
         }
     free(Uinv); free(L1inv); free(QR);
+    return 0;
+}
+
+/*
+ * Matrix product over GF(p), the black box of Section 3.2 (Algorithm 1):
+ * C <- C + alpha A B mod p for alpha = +1 or -1, written out from the
+ * definition of a matrix product: one reduction after every term.
+ * A is M x K, B is K x N, C is M x N, all row-major with leading dimensions
+ * K, N and N.  Returns 0.
+ */
+int oracle_mm(int64_t M, int64_t N, int64_t K, int64_t p, const int64_t *A,
+              const int64_t *B, int64_t *C, int64_t alpha)
+{
+    #pragma omp parallel for schedule(static) if (M * N * K > 1000000)
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            int64_t acc = 0;
+            for (int64_t k = 0; k < K; ++k)
+                acc = md(acc + A[i * K + k] * B[k * N + j], p);
+            C[i * N + j] = md(C[i * N + j] + alpha * acc, p);
+        }
+    return 0;
+}
+
+/*
+ * PLE decomposition (Section 5, Algorithm 10) unrolled to one column at a
+ * time: columns are taken left to right; for column j, with t pivots found
+ * so far, the pivot is the first nonzero of the column's residual at rows
+ * t..m-1 in the CURRENT row order (the base case of Algorithm 10 picks the
+ * row index of the first nonzero entry).  Rows t and i are exchanged across
+ * the residual and the columns of L already formed; the pivot row stays in E
+ * (pivot kept), the entries below it are divided by the pivot to form
+ * column t of the unit lower L, and the residual below is eliminated.
+ *
+ * In : A  m x n row-major (leading dimension n), residues in [0,p).
+ * Out: A  overwritten with the packed [L\E] (Section 5's storage, the
+ *         transpose of the [C\U] layout): E (r x n row echelon, pivots
+ *         kept) in the upper part including the diagonal of its first r
+ *         rows, the strict lower part of L's first r columns below it, zero
+ *         in every entry (i >= r, j >= r).
+ *      *rank = r; P[0..m) row transposition list (P[t] = i_t >= t for t < r,
+ *      P[t] = t for t >= r: applying T(t,P[t]) to the rows of A for
+ *      t = 0,1,... gives P^T A = L E); Q[0..n) with Q[t] = j_t, the column
+ *      rank profile, for t < r and Q[t] = t otherwise.
+ * Returns 0, or -1 on allocation failure.
+ */
+int oracle_ple(int64_t m, int64_t n, int64_t p, int64_t *A,
+               int64_t *rank, int64_t *P, int64_t *Q)
+{
+    int64_t rmax = m < n ? m : n;
+    int64_t *W = NULL, *L = NULL, *E = NULL;
+    int64_t t = 0;
+
+    for (int64_t i = 0; i < m; ++i) P[i] = i;
+    for (int64_t c = 0; c < n; ++c) Q[c] = c;
+    if (m == 0 || n == 0) { *rank = 0; return 0; }
+
+    W = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m * n));   /* residual rows    */
+    L = (int64_t *)calloc((size_t)(m * rmax), sizeof(int64_t));  /* L columns < r    */
+    E = (int64_t *)calloc((size_t)(rmax * n), sizeof(int64_t));  /* E rows < r       */
+    if (!W || !L || !E) { free(W); free(L); free(E); return -1; }
+    memcpy(W, A, sizeof(int64_t) * (size_t)(m * n));
+
+    for (int64_t j = 0; j < n && t < m; ++j) {
+        int64_t i = -1;
+        /* topmost nonzero of the residual of column j, rows t..m-1 */
+        for (int64_t l = t; l < m; ++l)
+            if (W[l * n + j] != 0) { i = l; break; }
+        if (i < 0) continue;                     /* column j is dependent */
+
+        P[t] = i;
+        Q[t] = j;
+        /* row transposition t <-> i: residual rows and the L columns < t */
+        if (i != t) {
+            for (int64_t c = 0; c < n; ++c) {
+                int64_t tmp = W[t * n + c]; W[t * n + c] = W[i * n + c]; W[i * n + c] = tmp;
+            }
+            for (int64_t s = 0; s < t; ++s) {
+                int64_t tmp = L[t * rmax + s]; L[t * rmax + s] = L[i * rmax + s]; L[i * rmax + s] = tmp;
+            }
+        }
+        /* E row t: the residual pivot row, pivot kept */
+        for (int64_t c = j; c < n; ++c) E[t * n + c] = W[t * n + c];
+        int64_t inv = oracle_inv_mod(W[t * n + j], p);
+        L[t * rmax + t] = 1;
+        for (int64_t l = t + 1; l < m; ++l) L[l * rmax + t] = md(W[l * n + j] * inv, p);
+        /* eliminate column j from the rows below: W[l] <- W[l] - L[l][t] E[t] */
+        #pragma omp parallel for schedule(static) if ((m - t) * (n - j) > 32768)
+        for (int64_t l = t + 1; l < m; ++l) {
+            int64_t f = L[l * rmax + t];
+            W[l * n + j] = 0;
+            if (f == 0) continue;
+            for (int64_t c = j + 1; c < n; ++c)
+                W[l * n + c] = md(W[l * n + c] - f * E[t * n + c], p);
+        }
+        ++t;
+    }
+    *rank = t;
+
+    /* pack [L\E] */
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t v = 0;
+            if (i < t && j >= i) v = E[i * n + j];
+            else if (j < t && j < i) v = L[i * rmax + j];
+            A[i * n + j] = v;
+        }
+    free(W); free(L); free(E);
+    return 0;
+}
+
+/*
+ * Determinant of an n x n matrix (Section 4.4 lists it among the invariants
+ * the CUP decomposition yields), by classical Gaussian elimination: the
+ * first nonzero entry of each column at or below the diagonal is the pivot,
+ * every row exchange flips the sign, and the determinant is the signed
+ * product of the pivots (0 when a column has no pivot).  Returns det in
+ * [0,p), or -1 on allocation failure.
+ */
+int64_t oracle_det(int64_t n, int64_t p, const int64_t *A)
+{
+    int64_t *G = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n * n > 0 ? n * n : 1));
+    int64_t det = 1;
+    if (!G) return -1;
+    memcpy(G, A, sizeof(int64_t) * (size_t)(n * n));
+    for (int64_t c = 0; c < n; ++c) {
+        int64_t piv = -1;
+        for (int64_t l = c; l < n; ++l)
+            if (G[l * n + c] != 0) { piv = l; break; }
+        if (piv < 0) { free(G); return 0; }
+        if (piv != c) {
+            for (int64_t k = 0; k < n; ++k) {
+                int64_t tmp = G[c * n + k]; G[c * n + k] = G[piv * n + k]; G[piv * n + k] = tmp;
+            }
+            det = md(-det, p);
+        }
+        det = md(det * G[c * n + c], p);
+        int64_t inv = oracle_inv_mod(G[c * n + c], p);
+        #pragma omp parallel for schedule(static) if (n * n > 32768)
+        for (int64_t l = c + 1; l < n; ++l) {
+            int64_t f = md(G[l * n + c] * inv, p);
+            if (f == 0) continue;
+            for (int64_t k = c; k < n; ++k)
+                G[l * n + k] = md(G[l * n + k] - f * G[c * n + k], p);
+        }
+    }
+    free(G);
+    return det;
+}
+
+/*
+ * Solution of the linear system A X = B for a nonsingular n x n matrix A and
+ * an n x nrhs right-hand side B (Section 4.4: the CUP decomposition suffices
+ * for it), by classical Gauss-Jordan elimination on [A | B].
+ * Out: X (n x nrhs).  Returns 0, 1 if A is singular, -1 on allocation failure.
+ */
+int oracle_solve(int64_t n, int64_t nrhs, int64_t p, const int64_t *A,
+                 const int64_t *B, int64_t *X)
+{
+    int64_t w = n + nrhs;
+    int64_t *G = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n * w > 0 ? n * w : 1));
+    if (!G) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < w; ++j)
+            G[i * w + j] = j < n ? A[i * n + j] : B[i * nrhs + (j - n)];
+    for (int64_t c = 0; c < n; ++c) {
+        int64_t piv = -1;
+        for (int64_t l = c; l < n; ++l)
+            if (G[l * w + c] != 0) { piv = l; break; }
+        if (piv < 0) { free(G); return 1; }
+        if (piv != c)
+            for (int64_t k = 0; k < w; ++k) {
+                int64_t tmp = G[c * w + k]; G[c * w + k] = G[piv * w + k]; G[piv * w + k] = tmp;
+            }
+        int64_t inv = oracle_inv_mod(G[c * w + c], p);
+        for (int64_t k = 0; k < w; ++k) G[c * w + k] = md(G[c * w + k] * inv, p);
+        #pragma omp parallel for schedule(static) if (n * w > 32768)
+        for (int64_t l = 0; l < n; ++l) {
+            if (l == c) continue;
+            int64_t f = G[l * w + c];
+            if (f == 0) continue;
+            for (int64_t k = 0; k < w; ++k)
+                G[l * w + k] = md(G[l * w + k] - f * G[c * w + k], p);
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < nrhs; ++j)
+            X[i * nrhs + j] = G[i * w + n + j];
+    free(G);
+    return 0;
+}
+
+/*
+ * Basis of the right nullspace of an m x n matrix A of rank r, in the form
+ * the transformation to column echelon form gives (Section 3.4: with
+ * A P^T X = [C 0], the last n - r columns of P^T X span the nullspace).
+ *
+ * The column order comes from the transposition list P of the CUP
+ * decomposition (P[t] for t < r): order[] starts as 0..n-1 and T(t,P[t]) is
+ * applied to it for t = 0,1,..., so that column c of A P^T is column
+ * order[c] of A, and the first r of them are linearly independent.  The
+ * basis is then fixed by the definition: vector s (s = 0..n-r-1) has a one
+ * at the free column order[r+s], zeros at the other free columns, and the
+ * unique values at the columns order[0..r) that make A x = 0.  They are
+ * found here by a classical Gauss-Jordan reduction of A P^T (m x n), whose
+ * pivots fall on its first r columns: with the reduced rows [I_r R; 0 0],
+ * x'[0..r) = -R[:, s] and x[order[c]] = x'[c].
+ * Out: N (n x (n - r), row-major, leading dimension n - r).
+ * Returns 0, or -1 on allocation failure, -2 if the first r columns of
+ * A P^T are not independent (P is not a CUP transposition list of A).
+ */
+int oracle_nullspace(int64_t m, int64_t n, int64_t p, const int64_t *A,
+                     int64_t r, const int64_t *P, int64_t *N)
+{
+    int64_t f = n - r;
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *G = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m * n > 0 ? m * n : 1));
+    if (!order || !G) { free(order); free(G); return -1; }
+    for (int64_t c = 0; c < n; ++c) order[c] = c;
+    for (int64_t t = 0; t < r; ++t) {
+        int64_t tmp = order[t]; order[t] = order[P[t]]; order[P[t]] = tmp;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t c = 0; c < n; ++c)
+            G[i * n + c] = A[i * n + order[c]];
+    /* Gauss-Jordan on the rows of A P^T; pivots must be columns 0..r-1 */
+    for (int64_t c = 0; c < r; ++c) {
+        int64_t piv = -1;
+        for (int64_t l = c; l < m; ++l)
+            if (G[l * n + c] != 0) { piv = l; break; }
+        if (piv < 0) { free(order); free(G); return -2; }
+        if (piv != c)
+            for (int64_t k = 0; k < n; ++k) {
+                int64_t tmp = G[c * n + k]; G[c * n + k] = G[piv * n + k]; G[piv * n + k] = tmp;
+            }
+        int64_t inv = oracle_inv_mod(G[c * n + c], p);
+        for (int64_t k = 0; k < n; ++k) G[c * n + k] = md(G[c * n + k] * inv, p);
+        #pragma omp parallel for schedule(static) if (m * n > 32768)
+        for (int64_t l = 0; l < m; ++l) {
+            if (l == c) continue;
+            int64_t g = G[l * n + c];
+            if (g == 0) continue;
+            for (int64_t k = 0; k < n; ++k)
+                G[l * n + k] = md(G[l * n + k] - g * G[c * n + k], p);
+        }
+    }
+    for (int64_t s = 0; s < f; ++s) {
+        for (int64_t c = 0; c < n; ++c) N[order[c] * f + s] = 0;
+        N[order[r + s] * f + s] = 1;
+        for (int64_t c = 0; c < r; ++c)
+            N[order[c] * f + s] = md(-G[c * n + r + s], p);
+    }
+    free(order); free(G);
     return 0;
 }
