@@ -9,7 +9,10 @@
  *     (Section 3.3, Algorithm 6; Proposition 3),
  *   - transformation to reduced column echelon form (Section 3.4,
  *     Algorithm 7 and Section 3.5, Algorithm 8; Proposition 5),
- *   - the in-place inverse (Section 4.3).
+ *   - the in-place inverse (Section 4.3),
+ *   - the PLE decomposition (Section 5, Algorithm 10),
+ *   - the determinant, system solution and nullspace basis (Sections 3.4
+ *     and 4.4), TRLUM (Algorithm 5) and InPlaceMM (Algorithm 9).
  *
  * Conventions shared by every entry point
  *   - Matrices are row-major with leading dimension lda >= max(1, n):
@@ -40,7 +43,9 @@
  *      1  CUP_SINGULAR  (inverse only; *rank is set, A is unspecified)
  *     -i  the i-th argument is invalid
  *  -1000 - e   a HIP runtime error e
- *  -2000  a device or host allocation failed
+ *  -2000  a device or host allocation failed (a test can force this path by
+ *         setting CUP_FAULT=alloc in the environment: every allocation of the
+ *         library then fails without allocating)
  */
 #ifndef LIBCUP_CUP_H
 #define LIBCUP_CUP_H
@@ -157,6 +162,91 @@ int cup_factor_batched(int64_t batch, const int64_t *m, const int64_t *n, int64_
                        int64_t *const *Q, int32_t *info);
 
 /*
+ * PLE decomposition (Section 5, Algorithm 10), the row-echelon twin of CUP:
+ * P^T A = L E, revealing the column rank profile.  Computed as the
+ * transpose of the CUP of A^T, the relation Section 5 states between the
+ * two decompositions (the CUP pivot rule on A^T is PLE's rule on A: the
+ * topmost nonzero of each column's residual, columns left to right).
+ *   A : device m x n (lda), overwritten with the packed [L\E]: E (r x n row
+ *       echelon, pivots kept) in the upper part including the diagonal of
+ *       its first r rows, the strict lower part of L's first r columns
+ *       (L unit lower) below it, zero in every entry (i >= r, j >= r).
+ *   P : device int64, length m: the row transposition list, P[t] = i_t >= t
+ *       for t < r and P[t] = t otherwise; applying T(t, P[t]) to the rows
+ *       of A for t = 0, 1, ... gives P^T A = L E.
+ *   Q : device int64, length n: Q[t] = j_t, the column rank profile, for
+ *       t < r, Q[t] = t otherwise.  Either may be NULL.
+ * A square matrix is transposed in place; a rectangular one goes through a
+ * library workspace of m n elements (reported by cup_workspace_bytes).
+ * Errors as cup_factor (-1 m, -2 n, -3 A, -4 lda, -5 p, -6 rank).
+ */
+int cup_ple(int64_t m, int64_t n, int64_t *A, int64_t lda, int64_t p, int64_t *rank, int64_t *P,
+            int64_t *Q);
+int cup_ple_i8(int64_t m, int64_t n, int8_t *A, int64_t lda, int64_t p, int64_t *rank, int64_t *P,
+               int64_t *Q);
+
+/*
+ * Determinant (Section 4.4, an invariant the CUP decomposition yields): with
+ * A P^T = C U, det A = det(P) * prod_t C[t][t] for a nonsingular n x n A (C
+ * is then lower triangular and U unit upper), det(P) = (-1)^(number of t
+ * with P[t] != t), and det A = 0 when the rank is below n.
+ *   A    : device n x n (lda), overwritten with the packed [C\U]
+ *   det  : host, receives det A in [0, p) (1 for n = 0)
+ *   rank : host, receives the rank
+ * Errors: -1 n, -2 A (or an entry out of range under CUP_CHECK=1), -3 lda,
+ * -4 p, -5 det, -6 rank.
+ */
+int cup_det(int64_t n, int64_t *A, int64_t lda, int64_t p, int64_t *det, int64_t *rank);
+
+/*
+ * Solution of A X = B for a nonsingular n x n A (Section 4.4): CUP of A,
+ * then X = P^T U^{-1} C^{-1} B by the Left-Lower-NonUnit and
+ * Left-Upper-Unit triangular solves (Algorithm 2's variants) and the row
+ * transpositions t <-> P[t] for t = n-1 down to 0.
+ *   A : device n x n (lda), overwritten with the packed [C\U]
+ *   B : device n x nrhs (ldb >= max(1, nrhs)), overwritten with X
+ * Returns CUP_SINGULAR (1) with *rank < n when A is singular (B is then
+ * untouched).  Errors: -1 n, -2 nrhs, -3 A, -4 lda, -5 B, -6 ldb, -7 p,
+ * -8 rank.
+ */
+int cup_solve(int64_t n, int64_t nrhs, int64_t *A, int64_t lda, int64_t *B, int64_t ldb, int64_t p,
+              int64_t *rank);
+
+/*
+ * Basis of the right nullspace of an m x n A of rank r (Section 3.4: with
+ * A P^T X = [C 0] and X = [U1^{-1}, -U1^{-1} U2; 0, I_{n-r}], the last n - r
+ * columns of P^T X span the kernel):  N = P^T [-U1^{-1} U2; I_{n-r}], so
+ * A N = 0, and row P-position r + s of N is the unit vector e_s.
+ *   A   : device m x n (lda), overwritten with [C\U] whose block right of
+ *         the first r columns holds -U1^{-1} U2 (Algorithm 7's first steps)
+ *   P   : device int64 transposition list of length n (or NULL)
+ *   N   : device, n rows with leading dimension ldn >= max(1, n): receives
+ *         the n x (n - r) basis in its first n - r columns
+ * Errors: -1 m, -2 n, -3 A, -4 lda, -5 p, -6 rank, -8 N, -9 ldn.
+ */
+int cup_nullspace(int64_t m, int64_t n, int64_t *A, int64_t lda, int64_t p, int64_t *rank, int64_t *P,
+                  int64_t *N, int64_t ldn);
+
+/*
+ * TRLUM (Section 3.2, Algorithm 5) in the variant that InPlaceMM applies to
+ * a packed CUP: A = [L\U] (n x n, L lower triangular with its diagonal
+ * stored, U unit upper with its strict upper part stored) <- L U, in place.
+ * Errors: -1 n, -2 A, -3 lda, -4 p.
+ */
+int cup_trlum(int64_t n, int64_t *A, int64_t lda, int64_t p);
+
+/*
+ * InPlaceMM (Section 4.3, Algorithm 9): B <- A B for an m x m A and an
+ * m x n B with no temporary of B's size: CUP of A (A = C U P), B <- P B,
+ * B <- U B, B <- C B (triangular products), then A <- C U (TRLUM) and
+ * A <- A P, which restores A.
+ *   A : device m x m (lda), unchanged on return
+ *   B : device m x n (ldb >= max(1, n)), overwritten with A B
+ * Errors: -1 m, -2 n, -3 A, -4 lda, -5 B, -6 ldb, -7 p.
+ */
+int cup_inplace_mm(int64_t m, int64_t n, int64_t *A, int64_t lda, int64_t *B, int64_t ldb, int64_t p);
+
+/*
  * Modular matrix product, the black box of Section 3.2 (Algorithm 1) that
  * every routine above reduces to:  C <- C + alpha A B mod p, alpha = +1 or
  * -1 (CUP's Schur complement uses -1, Algorithm 6), in the form selected by
@@ -196,7 +286,26 @@ const char *cup_strerror(int status);
 int cup_profile(int enable);
 int cup_profile_read(double *stats);
 
-/* Bytes of device workspace currently cached by the library. */
+/*
+ * Bytes of device workspace currently cached by the library (it grows to the
+ * largest call since the last cup_finalize).  After calls on matrices of at
+ * most m x n, with k = min(m, n), it is at most
+ *     16 KiB                                  result words
+ *   + 32 KiB * (max(64, ceil(k/64)) + floor(k/64))
+ *                                             dense inverses of the 64 x 64
+ *                                             diagonal blocks of the triangle
+ *                                             being solved, and the cache of
+ *                                             those of U (Section 3.2 leaves)
+ *   + 4 * max(k, 1024)                        row rank profile (reduced forms)
+ *   + 2 * (m + n + 256) * (k + 64)            INT8 forms only: packed limb
+ *                                             operands of one product
+ *   + 4 * max(batch, 4096)                    batched order (batch <= 32768)
+ * The two block caches are the library's departure from Definition 1
+ * (Section 3.1: O(1) extra field elements outside matrix multiplication):
+ * O(k) blocks of 64 x 64, i.e. 64 k field elements against the m n of A.
+ * The packed operands are matrix-multiplication memory, which Definition 1
+ * allows.
+ */
 size_t cup_workspace_bytes(void);
 
 /* Release cached workspace. */

@@ -50,6 +50,16 @@ bool env_flag(const char* name)
     return v && v[0] && std::strcmp(v, "0") != 0;
 }
 
+}  // namespace
+
+bool fault_alloc()
+{
+    const char* v = std::getenv("CUP_FAULT");
+    return v && std::strcmp(v, "alloc") == 0;
+}
+
+namespace {
+
 bool is_prime_i64(int64_t p)
 {
     if (p < 2) return false;
@@ -63,14 +73,14 @@ bool is_prime_i64(int64_t p)
 void ensure_small(Global& g)
 {
     if (!g.d_small) {
-        if (hipMalloc((void**)&g.d_small, sizeof(int) * kSmallInts) != hipSuccess) {
+        if (dev_malloc((void**)&g.d_small, sizeof(int) * kSmallInts) != hipSuccess) {
             g.d_small = nullptr;
             throw CupError{CUP_ERR_ALLOC};
         }
         g.bytes += sizeof(int) * kSmallInts;
     }
     if (!g.h_small) {
-        if (hipHostMalloc((void**)&g.h_small, sizeof(int) * kSmallInts, hipHostMallocDefault) !=
+        if (host_malloc((void**)&g.h_small, sizeof(int) * kSmallInts, hipHostMallocDefault) !=
             hipSuccess) {
             g.h_small = nullptr;
             throw CupError{CUP_ERR_ALLOC};
@@ -79,7 +89,7 @@ void ensure_small(Global& g)
     if (!g.h_mail) {
         const size_t bytes = sizeof(unsigned long long) * kMailWords;
         unsigned long long* h = nullptr;
-        if (hipHostMalloc((void**)&h, bytes,
+        if (host_malloc((void**)&h, bytes,
                           hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable) !=
             hipSuccess)
             throw CupError{CUP_ERR_ALLOC};
@@ -102,7 +112,7 @@ int* ensure_list(Global& g, size_t ints)
             g.list_cap = 0;
         }
         size_t cap = std::max<size_t>(ints, 1024);
-        if (hipMalloc((void**)&g.d_list, sizeof(int) * cap) != hipSuccess) throw CupError{CUP_ERR_ALLOC};
+        if (dev_malloc((void**)&g.d_list, sizeof(int) * cap) != hipSuccess) throw CupError{CUP_ERR_ALLOC};
         g.list_cap = cap;
         g.bytes += sizeof(int) * cap;
     }
@@ -179,6 +189,37 @@ Ctx make_ctx(Global& g, int64_t p, int form)
     return c;
 }
 
+// CUP of the m x n view at A (Algorithm 6); returns the rank, with the
+// transposition list and the row rank profile on the host.
+template <typename T>
+int run_cup(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& Pl, std::vector<int64_t>& Ql)
+{
+    if (m <= 0 || n <= 0) return 0;
+    Pl.reserve((size_t)std::min(m, n));
+    Ql.reserve((size_t)std::min(m, n));
+    ucache_begin(c, A, lda, std::min(m, n));
+    const int r = cup_rec<T>(c, A, lda, m, n, Pl, Ql);
+    flush_defer(c);
+    c.base = nullptr;
+    return r;
+}
+
+// Run `body` (which returns a status) under the library lock, turning the
+// internal failures into status codes.
+template <typename F>
+int guarded(Global& g, F&& body)
+{
+    try {
+        return body();
+    } catch (const CupError& e) {
+        g.prof.drop();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g.prof.drop();
+        return CUP_ERR_ALLOC;
+    }
+}
+
 template <typename T>
 int factor_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* rank, int64_t* P,
                 int64_t* Q, int tail)
@@ -194,15 +235,7 @@ int factor_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* ran
         int chk = check_range(c, A, lda, (int)m, (int)n, p);
         if (chk) return chk;
         std::vector<int64_t> Pl, Ql;
-        int r = 0;
-        if (m > 0 && n > 0) {
-            Pl.reserve((size_t)std::min(m, n));
-            Ql.reserve((size_t)std::min(m, n));
-            ucache_begin(c, A, lda, (int)std::min(m, n));
-            r = cup_rec<T>(c, A, lda, (int)m, (int)n, Pl, Ql);
-            flush_defer(c);
-            c.base = nullptr;
-        }
+        const int r = run_cup<T>(c, A, lda, (int)m, (int)n, Pl, Ql);
         if (tail >= 1 && r > 0) {
             int* dq = ensure_list(g, (size_t)r);
             std::vector<int> q32(Ql.begin(), Ql.end());
@@ -212,12 +245,7 @@ int factor_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* ran
             rref_tail<T>(c, A, lda, (int)m, (int)n, r, dq);
             if (tail == 2 && r == (int)n) {
                 // A^{-1} = P^T X: rows t <-> p_t for t = n-1 down to 0
-                CUP_HIP(hipStreamSynchronize(c.s));
-                std::vector<int> p32(Pl.begin(), Pl.end());
-                CUP_HIP(hipMemcpyAsync(dq, p32.data(), sizeof(int) * (size_t)r,
-                                       hipMemcpyHostToDevice, c.s));
-                CUP_HIP(hipStreamSynchronize(c.s));
-                launch_rowswap_desc<T>(c.s, A, lda, r, (int)n, dq);
+                apply_row_transpositions<T>(c, A, lda, (int)n, Pl.data(), r, true);
             }
         }
         CUP_HIP(hipStreamSynchronize(c.s));
@@ -228,8 +256,10 @@ int factor_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* ran
         if (tail == 2 && r < n) return CUP_SINGULAR;
         return CUP_OK;
     } catch (const CupError& e) {
+        g.prof.drop();
         return e.code;
     } catch (const std::bad_alloc&) {
+        g.prof.drop();
         return CUP_ERR_ALLOC;
     }
 }
@@ -258,8 +288,251 @@ int ffgemm_impl(int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const 
         if (g.prof.on) g.prof.collect();
         return CUP_OK;
     } catch (const CupError& e) {
+        g.prof.drop();
         return e.code;
     }
+}
+
+// The transposition workspace of a rectangular PLE (n x m elements).
+void* transpose_workspace(Global& g, Ctx& c, size_t bytes)
+{
+    Workspace& w = g.ws;
+    if (bytes > w.tp_cap) {
+        if (w.tp) {
+            CUP_HIP(hipStreamSynchronize(c.s));
+            CUP_HIP(hipFree(w.tp));
+            w.bytes -= w.tp_cap;
+            w.tp = nullptr;
+            w.tp_cap = 0;
+        }
+        if (dev_malloc(&w.tp, bytes) != hipSuccess) {
+            w.tp = nullptr;
+            throw CupError{CUP_ERR_ALLOC};
+        }
+        w.tp_cap = bytes;
+        w.bytes += bytes;
+    }
+    return w.tp;
+}
+
+// PLE (Section 5, Algorithm 10) as the transpose of the CUP of A^T: the
+// matrix is transposed (in place when square, else through the workspace),
+// factored by Algorithm 6 and transposed back; the CUP's column
+// transpositions are PLE's row transpositions and its row rank profile is
+// A's column rank profile.
+template <typename T>
+int ple_impl(int64_t m, int64_t n, T* A, int64_t lda, int64_t p, int64_t* rank, int64_t* P, int64_t* Q)
+{
+    int v = validate(m, n, A, lda, p, rank);
+    if (v) return v;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    int form = resolve_form(g.form, p, sizeof(T) == 1);
+    if (form < 0) return form;
+    return guarded(g, [&]() -> int {
+        Ctx c = make_ctx(g, p, form);
+        int chk = check_range(c, A, lda, (int)m, (int)n, p);
+        if (chk) return chk;
+        std::vector<int64_t> Pl, Ql;
+        int r = 0;
+        if (m > 0 && n > 0) {
+            if (m == n) {
+                launch_transpose_square<T>(c.s, A, lda, (int)n);
+                r = run_cup<T>(c, A, lda, (int)n, (int)m, Pl, Ql);
+                launch_transpose_square<T>(c.s, A, lda, (int)n);
+            } else {
+                T* Tb = static_cast<T*>(transpose_workspace(g, c, sizeof(T) * (size_t)m * (size_t)n));
+                launch_transpose<T>(c.s, A, lda, Tb, m, (int)m, (int)n);
+                r = run_cup<T>(c, Tb, m, (int)n, (int)m, Pl, Ql);
+                launch_transpose<T>(c.s, Tb, m, A, lda, (int)n, (int)m);
+            }
+        }
+        CUP_HIP(hipStreamSynchronize(c.s));
+        if (g.prof.on) g.prof.collect();
+        write_perm(c, P, Pl, m);
+        write_perm(c, Q, Ql, n);
+        *rank = r;
+        return CUP_OK;
+    });
+}
+
+// Determinant (Section 4.4): det A = det(P) prod C[t][t] for a nonsingular
+// A, with A P^T = C U (C lower triangular, U unit upper) and det(P) = -1 to
+// the number of nontrivial transpositions; 0 when the rank is below n.
+int det_impl(int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* det, int64_t* rank)
+{
+    int64_t dummy = 0;
+    int v = validate(n, n, A, lda, p, &dummy);
+    if (v) return v == -1 || v == -2 ? -1 : v + 1;  // -3 A -> -2, -4 lda -> -3, -5 p -> -4
+    if (!det) return -5;
+    if (!rank) return -6;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    int form = resolve_form(g.form, p, false);
+    if (form < 0) return -4;
+    return guarded(g, [&]() -> int {
+        Ctx c = make_ctx(g, p, form);
+        int chk = check_range(c, A, lda, (int)n, (int)n, p);
+        if (chk) return -2;
+        std::vector<int64_t> Pl, Ql;
+        const int r = run_cup<int64_t>(c, A, lda, (int)n, (int)n, Pl, Ql);
+        int64_t d = (n == 0) ? 1 % p : 0;
+        if (n > 0 && r == (int)n) {
+            int odd = 0;
+            for (int t = 0; t < r; ++t) odd ^= (Pl[(size_t)t] != t) ? 1 : 0;
+            launch_diag_prod<int64_t>(c.s, A, lda, (int)n, p, odd, reinterpret_cast<int64_t*>(c.d_small));
+            const int* h = fetch_small(c, 2);
+            std::memcpy(&d, h, sizeof(int64_t));
+        }
+        CUP_HIP(hipStreamSynchronize(c.s));
+        if (g.prof.on) g.prof.collect();
+        *det = d;
+        *rank = r;
+        return CUP_OK;
+    });
+}
+
+// A X = B (Section 4.4): with A P^T = C U, X = P^T U^{-1} C^{-1} B by two
+// triangular solves (Algorithm 2's Left-Lower-NonUnit and Left-Upper-Unit
+// variants) and the row transpositions t <-> p_t for t = n-1 down to 0.
+int solve_impl(int64_t n, int64_t nrhs, int64_t* A, int64_t lda, int64_t* B, int64_t ldb, int64_t p,
+               int64_t* rank)
+{
+    if (n < 0 || n > INT32_MAX / 2) return -1;
+    if (nrhs < 0 || nrhs > INT32_MAX / 2) return -2;
+    if (!A && n > 0) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (!B && n > 0 && nrhs > 0) return -5;
+    if (ldb < std::max<int64_t>(1, nrhs)) return -6;
+    if (!is_prime_i64(p) || p >= ((int64_t)1 << 26)) return -7;
+    if (!rank) return -8;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    int form = resolve_form(g.form, p, false);
+    if (form < 0) return -7;
+    return guarded(g, [&]() -> int {
+        Ctx c = make_ctx(g, p, form);
+        if (check_range(c, A, lda, (int)n, (int)n, p)) return -3;
+        if (check_range(c, B, ldb, (int)n, (int)nrhs, p)) return -5;
+        std::vector<int64_t> Pl, Ql;
+        const int r = run_cup<int64_t>(c, A, lda, (int)n, (int)n, Pl, Ql);
+        *rank = r;
+        if (r < (int)n) {
+            CUP_HIP(hipStreamSynchronize(c.s));
+            if (g.prof.on) g.prof.collect();
+            return CUP_SINGULAR;
+        }
+        if (n > 0 && nrhs > 0) {
+            trsm<int64_t>(c, LEFT, LOWER, 0, (int)n, A, lda, B, ldb, (int)nrhs);  // C^{-1} B
+            trsm<int64_t>(c, LEFT, UPPER, 1, (int)n, A, lda, B, ldb, (int)nrhs);  // U^{-1} (.)
+            apply_row_transpositions<int64_t>(c, B, ldb, (int)nrhs, Pl.data(), r, true);
+        }
+        CUP_HIP(hipStreamSynchronize(c.s));
+        if (g.prof.on) g.prof.collect();
+        return CUP_OK;
+    });
+}
+
+// Right nullspace basis (Section 3.4): A P^T X = [C 0] with
+// X = [U1^{-1}, -U1^{-1} U2; 0, I], so the last n - r columns of P^T X,
+// N = P^T [-U1^{-1} U2; I_{n-r}], span ker A.  The block -U1^{-1} U2 is
+// ColEchTrans's first two steps (Algorithm 7) on the packed [C\U].
+int nullspace_impl(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* rank, int64_t* P,
+                   int64_t* N, int64_t ldn)
+{
+    int v = validate(m, n, A, lda, p, rank);
+    if (v) return v;
+    if (!N && n > 0) return -8;
+    if (ldn < std::max<int64_t>(1, n)) return -9;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    int form = resolve_form(g.form, p, false);
+    if (form < 0) return form;
+    return guarded(g, [&]() -> int {
+        Ctx c = make_ctx(g, p, form);
+        if (check_range(c, A, lda, (int)m, (int)n, p)) return -3;
+        std::vector<int64_t> Pl, Ql;
+        const int r = run_cup<int64_t>(c, A, lda, (int)m, (int)n, Pl, Ql);
+        const int f = (int)n - r;
+        if (f > 0) {
+            if (r > 0) {
+                trsm<int64_t>(c, LEFT, UPPER, 1, r, A, lda, A + r, lda, f);  // U1^{-1} U2
+                launch_negate<int64_t>(c.s, A + r, lda, r, f, c.mp);
+            }
+            // pos[x]: where column x of A stands in the CUP column order
+            std::vector<int> order((size_t)n), pos((size_t)n);
+            for (int x = 0; x < (int)n; ++x) order[(size_t)x] = x;
+            for (int t = 0; t < r; ++t) std::swap(order[(size_t)t], order[(size_t)Pl[(size_t)t]]);
+            for (int x = 0; x < (int)n; ++x) pos[(size_t)order[(size_t)x]] = x;
+            int* dpos = ensure_list(g, (size_t)n);
+            CUP_HIP(hipMemcpyAsync(dpos, pos.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice, c.s));
+            launch_nullspace_assemble<int64_t>(c.s, A + r, lda, r, f, dpos, N, ldn, (int)n);
+            CUP_HIP(hipStreamSynchronize(c.s));  // `pos` is read by the copy
+        }
+        CUP_HIP(hipStreamSynchronize(c.s));
+        if (g.prof.on) g.prof.collect();
+        write_perm(c, P, Pl, n);
+        *rank = r;
+        return CUP_OK;
+    });
+}
+
+int trlum_impl(int64_t n, int64_t* A, int64_t lda, int64_t p)
+{
+    if (n < 0 || n > INT32_MAX / 2) return -1;
+    if (!A && n > 0) return -2;
+    if (lda < std::max<int64_t>(1, n)) return -3;
+    if (!is_prime_i64(p) || p >= ((int64_t)1 << 26)) return -4;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    int form = resolve_form(g.form, p, false);
+    if (form < 0) return -4;
+    return guarded(g, [&]() -> int {
+        Ctx c = make_ctx(g, p, form);
+        if (check_range(c, A, lda, (int)n, (int)n, p)) return -2;
+        trlum<int64_t>(c, (int)n, A, lda);
+        CUP_HIP(hipStreamSynchronize(c.s));
+        if (g.prof.on) g.prof.collect();
+        return CUP_OK;
+    });
+}
+
+// InPlaceMM (Section 4.3, Algorithm 9): B <- A B for an m x m A, with no
+// temporary of B's size.  CUP of A (A = C U P), B <- P B (row
+// transpositions t <-> p_t for t ascending), B <- U B, B <- C B (TRMM), then
+// A <- C U (TRLUM) and A <- A P (column transpositions, t descending),
+// which gives back A.
+int inplace_mm_impl(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t* B, int64_t ldb, int64_t p)
+{
+    if (m < 0 || m > INT32_MAX / 2) return -1;
+    if (n < 0 || n > INT32_MAX / 2) return -2;
+    if (!A && m > 0) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (!B && m > 0 && n > 0) return -5;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (!is_prime_i64(p) || p >= ((int64_t)1 << 26)) return -7;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    int form = resolve_form(g.form, p, false);
+    if (form < 0) return -7;
+    return guarded(g, [&]() -> int {
+        Ctx c = make_ctx(g, p, form);
+        if (check_range(c, A, lda, (int)m, (int)m, p)) return -3;
+        if (check_range(c, B, ldb, (int)m, (int)n, p)) return -5;
+        if (m == 0) return CUP_OK;
+        std::vector<int64_t> Pl, Ql;
+        const int r = run_cup<int64_t>(c, A, lda, (int)m, (int)m, Pl, Ql);
+        if (n > 0) {
+            apply_row_transpositions<int64_t>(c, B, ldb, (int)n, Pl.data(), r, false);  // P B
+            trmm<int64_t>(c, LEFT, UPPER, 1, (int)m, A, lda, B, ldb, (int)n);            // U B
+            trmm<int64_t>(c, LEFT, LOWER, 0, (int)m, A, lda, B, ldb, (int)n);            // C B
+        }
+        trlum<int64_t>(c, (int)m, A, lda);                                              // C U
+        apply_transpositions<int64_t>(c, A, lda, (int)m, Pl.data(), r, true);           // (C U) P
+        CUP_HIP(hipStreamSynchronize(c.s));
+        if (g.prof.on) g.prof.collect();
+        return CUP_OK;
+    });
 }
 
 }  // namespace
@@ -378,7 +651,7 @@ int cup_factor_batched(int64_t batch, const int64_t* m, const int64_t* n, int64_
                     g.order_cap = 0;
                 }
                 size_t cap = std::max<size_t>((size_t)batch, 4096);
-                if (hipMalloc((void**)&g.d_order, sizeof(int) * cap) != hipSuccess)
+                if (dev_malloc((void**)&g.d_order, sizeof(int) * cap) != hipSuccess)
                     throw CupError{CUP_ERR_ALLOC};
                 g.order_cap = cap;
                 g.bytes += sizeof(int) * cap;
@@ -390,6 +663,45 @@ int cup_factor_batched(int64_t batch, const int64_t* m, const int64_t* n, int64_
     } catch (const CupError& e) {
         return e.code;
     }
+}
+
+int cup_ple(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* rank, int64_t* P,
+            int64_t* Q)
+{
+    return ple_impl<int64_t>(m, n, A, lda, p, rank, P, Q);
+}
+
+int cup_ple_i8(int64_t m, int64_t n, int8_t* A, int64_t lda, int64_t p, int64_t* rank, int64_t* P,
+               int64_t* Q)
+{
+    return ple_impl<int8_t>(m, n, A, lda, p, rank, P, Q);
+}
+
+int cup_det(int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* det, int64_t* rank)
+{
+    return det_impl(n, A, lda, p, det, rank);
+}
+
+int cup_solve(int64_t n, int64_t nrhs, int64_t* A, int64_t lda, int64_t* B, int64_t ldb, int64_t p,
+              int64_t* rank)
+{
+    return solve_impl(n, nrhs, A, lda, B, ldb, p, rank);
+}
+
+int cup_nullspace(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t p, int64_t* rank, int64_t* P,
+                  int64_t* N, int64_t ldn)
+{
+    return nullspace_impl(m, n, A, lda, p, rank, P, N, ldn);
+}
+
+int cup_trlum(int64_t n, int64_t* A, int64_t lda, int64_t p)
+{
+    return trlum_impl(n, A, lda, p);
+}
+
+int cup_inplace_mm(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t* B, int64_t ldb, int64_t p)
+{
+    return inplace_mm_impl(m, n, A, lda, B, ldb, p);
 }
 
 int cup_ffgemm(int64_t M, int64_t N, int64_t K, const int64_t* A, int64_t lda, const int64_t* B,
@@ -470,6 +782,7 @@ int cup_finalize(void)
     if (g.ws.tri) (void)hipFree(g.ws.tri);
     if (g.ws.uc) (void)hipFree(g.ws.uc);
     if (g.ws.pk) (void)hipFree(g.ws.pk);
+    if (g.ws.tp) (void)hipFree(g.ws.tp);
     g.ws = Workspace{};
     g.d_small = nullptr;
     g.h_small = nullptr;

@@ -27,6 +27,28 @@ struct CupError {
     int code;
 };
 
+// Every device and pinned-host allocation of the library goes through these
+// two calls.  With CUP_FAULT=alloc in the environment they report failure
+// without allocating, so that the CUP_ERR_ALLOC path of every entry point can
+// be exercised by a test; the variable is read on each allocation.
+bool fault_alloc();
+inline hipError_t dev_malloc(void** ptr, size_t bytes)
+{
+    if (fault_alloc()) {
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(ptr, bytes);
+}
+inline hipError_t host_malloc(void** ptr, size_t bytes, unsigned flags)
+{
+    if (fault_alloc()) {
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipHostMalloc(ptr, bytes, flags);
+}
+
 #define CUP_HIP(call)                                                   \
     do {                                                                \
         hipError_t e_ = (call);                                         \
@@ -48,12 +70,15 @@ struct MoveList {
     int src[kLeafRows];
 };
 
-// Column transpositions passed by value (one launch per chunk).
-constexpr int kTranspChunk = 120;
-struct TranspList {
+// A composed permutation of at most kGatherMax positions (columns) or
+// kGatherRows positions (rows), passed by value: position dst[k] receives
+// what position src[k] held before the launch.
+constexpr int kGatherMax = 256;
+constexpr int kGatherRows = 128;
+struct GatherList {
     int n;
-    int a[kTranspChunk];
-    int b[kTranspChunk];
+    int dst[kGatherMax];
+    int src[kGatherMax];
 };
 
 // ---------------------------------------------------------------- launchers
@@ -140,10 +165,21 @@ template <typename T>
 void launch_rowmove_shift(hipStream_t s, T* A, int64_t lda, int ncols, int dst0, int src0,
                           int count);
 
-// Column transpositions a[k] <-> b[k], applied for k = 0..n-1 in order, to
-// rows [0,rows).
+// Composed column permutation g on rows [0,rows) (g.n <= kGatherMax).
 template <typename T>
-void launch_coltransp(hipStream_t s, T* A, int64_t lda, int rows, const TranspList& tl);
+void launch_colgather(hipStream_t s, T* A, int64_t lda, int rows, const GatherList& g);
+
+// Composed row permutation g on columns [0,cols) (g.n <= kGatherRows).
+template <typename T>
+void launch_rowgather(hipStream_t s, T* A, int64_t lda, int cols, const GatherList& g);
+
+// In-place transpose of the n x n view at A.
+template <typename T>
+void launch_transpose_square(hipStream_t s, T* A, int64_t lda, int n);
+
+// D (cols x rows, leading dimension ldd) <- S^T for S rows x cols.
+template <typename T>
+void launch_transpose(hipStream_t s, const T* S, int64_t lds, T* D, int64_t ldd, int rows, int cols);
 
 // Diagonal blocks of a triangle of order n (uplo 0=Upper 1=Lower, unit 0/1):
 // mode 0 writes W[b] = T_bb^{-1}, mode 1 writes W[b] = T_bb (each a dense
@@ -198,9 +234,21 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
 template <typename T>
 void launch_rowswap_lower(hipStream_t s, T* A, int64_t lda, int r, const int* q);
 
-// For t = r-1 down to 0: swap rows t and pv[t] over `cols` columns.
+// *out = (-1)^negate * prod_{i<n} A[i][i] mod p (one workgroup).
 template <typename T>
-void launch_rowswap_desc(hipStream_t s, T* A, int64_t lda, int r, int cols, const int* pv);
+void launch_diag_prod(hipStream_t s, const T* A, int64_t lda, int n, int64_t p, int negate, int64_t* out);
+
+// Nullspace basis from ColEchTrans's block M (r x f at M, f = n - r, the
+// negated U1^{-1} U2): row x of N (n x f) is row pos[x] of M when
+// pos[x] < r, else the unit vector e_{pos[x] - r}.
+template <typename T>
+void launch_nullspace_assemble(hipStream_t s, const T* M, int64_t ldm, int r, int f, const int* pos,
+                               T* N, int64_t ldn, int n);
+
+// [L\U] (L lower with its diagonal, U unit upper) <- L U on an nb x nb block
+// (nb <= 64): the leaf of TRLUM (Algorithm 5, in the variant of Algorithm 9).
+template <typename T>
+void launch_trlum_leaf(hipStream_t s, int nb, T* A, int64_t lda, ModP mp);
 
 // Count entries outside [0,p) of a rows x cols view (atomic add into *bad).
 template <typename T>

@@ -1,8 +1,18 @@
 // Host side of libcup: the in-place recursive drivers of Sections 3.2-3.5.
 //
 // Every routine works on row-major views (pointer, leading dimension) of
-// the caller's matrix; the only memory besides the matrix is the ffgemm
-// workspace and O(m + n) bookkeeping (Section 3.1, Definition 1: in place).
+// the caller's matrix and allocates nothing of the matrix's size.  Memory
+// besides the matrix (all of it reported by cup_workspace_bytes):
+//   - O(m + n) bookkeeping (transposition lists, small result buffers);
+//   - the ffgemm workspace of the INT8 forms (packed operands), which
+//     Definition 1 (Section 3.1) allows inside matrix multiplication;
+//   - two buffers outside matrix multiplication, a deliberate departure from
+//     Definition 1's O(1) extra field elements: the dense inverses of the
+//     64 x 64 diagonal blocks of the triangle being solved (ceil(n/64) blocks
+//     of 32 KiB, at least 64 blocks, so n/2 KiB for large n) and the cache
+//     of the inverses of U's 64 x 64 diagonal blocks (floor(min(m,n)/64)
+//     blocks of 32 KiB, 4 MiB at r = 8192).  Both are O(n) blocks, i.e.
+//     O(n * 64) field elements against the mn of the matrix.
 // The recursions split on multiples of the leaf sizes; outputs do not depend
 // on the split point because the pivot rule fixes P, and P fixes C and U
 // (Section 2.2, Proposition 1).
@@ -70,17 +80,27 @@ struct Profiler {
         recs.push_back(ProfRec{kind, f, by, next(), next()});
         return recs.back();
     }
-    // after the stream has synchronised
+    // After the stream has synchronised.  The pending records are taken out
+    // first, so that a failure leaves nothing behind for the next call; a
+    // pair whose events were not both recorded (a launch that failed) is
+    // skipped.
     void collect()
     {
-        for (auto& r : recs) {
+        std::vector<ProfRec> done;
+        done.swap(recs);
+        used = 0;
+        for (auto& r : done) {
             float t = 0.f;
-            CUP_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) continue;
             launches[r.kind] += 1;
             ms[r.kind] += t;
             flops[r.kind] += r.flops;
             bytes[r.kind] += r.bytes;
         }
+    }
+    // Forget the records of a call that failed before collect().
+    void drop()
+    {
         recs.clear();
         used = 0;
     }
@@ -95,6 +115,8 @@ struct Workspace {
     size_t uc_cap = 0;     // blocks
     int8_t* pk = nullptr;  // packed ffgemm operands of the INT8 forms
     size_t pk_cap = 0;     // bytes
+    void* tp = nullptr;    // the transpose of a rectangular matrix (PLE)
+    size_t tp_cap = 0;     // bytes
     size_t bytes = 0;
 };
 
@@ -167,7 +189,7 @@ inline void ucache_begin(Ctx& c, const void* base, int64_t lda, int rmax)
             w.uc = nullptr;
             w.uc_cap = 0;
         }
-        if (hipMalloc((void**)&w.uc, blocks * kTriNB * kTriNB * sizeof(double)) != hipSuccess) {
+        if (dev_malloc((void**)&w.uc, blocks * kTriNB * kTriNB * sizeof(double)) != hipSuccess) {
             w.uc = nullptr;
             throw CupError{-2000};
         }
@@ -272,7 +294,7 @@ inline double* tri_workspace(Ctx& c, int n)
             w.tri_cap = 0;
         }
         size_t cap = std::max(need, (size_t)64 * kTriNB * kTriNB);
-        if (hipMalloc((void**)&w.tri, cap * sizeof(double)) != hipSuccess) {
+        if (dev_malloc((void**)&w.tri, cap * sizeof(double)) != hipSuccess) {
             w.tri = nullptr;
             throw CupError{-2000};
         }
@@ -293,7 +315,7 @@ inline int8_t* pack_workspace(Ctx& c, size_t need)
             w.pk = nullptr;
             w.pk_cap = 0;
         }
-        if (hipMalloc((void**)&w.pk, need) != hipSuccess) {
+        if (dev_malloc((void**)&w.pk, need) != hipSuccess) {
             w.pk = nullptr;
             throw CupError{-2000};
         }
@@ -515,23 +537,107 @@ void trulm(Ctx& c, int n, T* A, int64_t lda)
     trulm(c, n - k, A22, lda);                               // X22 = T22 N22
 }
 
-// ------------------------------------------------------- column transpositions
+// ----------------------------------------------------------------- TRLUM
+// Section 3.2, Algorithm 5, in the variant InPlaceMM (Algorithm 9) applies to
+// the packed [C\U] of a CUP: on [L\U] with L lower (diagonal stored) and U
+// unit upper (strict upper part stored), A <- L U.
 template <typename T>
-void apply_transpositions(Ctx& c, T* A, int64_t lda, int rows, const int64_t* piv, int count)
+void trlum(Ctx& c, int n, T* A, int64_t lda)
 {
-    if (rows <= 0) return;
-    TranspList tl;
-    tl.n = 0;
-    for (int t = 0; t < count; ++t) {
-        if (piv[t] == t) continue;
-        tl.a[tl.n] = t;
-        tl.b[tl.n] = (int)piv[t];
-        if (++tl.n == kTranspChunk) {
-            launch_coltransp<T>(c.s, A, lda, rows, tl);
-            tl.n = 0;
-        }
+    if (n <= 0) return;
+    if (n <= kTriNB) {
+        launch_trlum_leaf<T>(c.s, n, A, lda, c.mp);
+        return;
     }
-    if (tl.n) launch_coltransp<T>(c.s, A, lda, rows, tl);
+    const int k = split_at(n, kTriNB);
+    T* A11 = A;
+    T* A12 = A + k;
+    T* A21 = A + (int64_t)k * lda;
+    T* A22 = A + (int64_t)k * lda + k;
+    trlum(c, n - k, A22, lda);                               // X4 = L3 U3
+    gemm(c, n - k, n - k, k, A21, lda, A12, lda, A22, lda, +1); // X4 += L2 U2
+    trmm(c, LEFT, LOWER, 0, k, A11, lda, A12, lda, n - k);   // X2 = L1 U2
+    trmm(c, RIGHT, UPPER, 1, k, A11, lda, A21, lda, n - k);  // X3 = L2 U1
+    trlum(c, k, A11, lda);                                   // X1 = L1 U1
+}
+
+// ------------------------------------------------------ permutations
+// A sequence of transpositions T(t, piv[t]) (t = 0..count-1, or count-1
+// down to 0 when `descending`), applied in that order to the rows or columns
+// of a matrix, composed into gathers: each gather moves at most `lim`
+// positions, position dst receiving what src held before it, and the
+// gathers are launched in order.  Trivial transpositions cost nothing.
+struct Gathers {
+    std::vector<GatherList> lists;
+};
+
+inline void compose_transpositions(const int64_t* piv, int count, bool descending, int lim, Gathers& out)
+{
+    out.lists.clear();
+    // moved[k] = (position x, the position whose entry (at the start of the
+    // current gather) is now at x); slot[x] = k, or -1 for an untouched x
+    std::vector<std::pair<int, int>> moved;
+    std::vector<int> slot;
+    auto at = [&](int x) -> int {
+        if ((size_t)x >= slot.size()) slot.resize((size_t)x + 1 + slot.size() / 2, -1);
+        return slot[(size_t)x];
+    };
+    auto flush = [&]() {
+        GatherList g;
+        g.n = 0;
+        for (auto& pr : moved) {
+            slot[(size_t)pr.first] = -1;
+            if (pr.first != pr.second) {
+                g.dst[g.n] = pr.first;
+                g.src[g.n] = pr.second;
+                ++g.n;
+            }
+        }
+        if (g.n) out.lists.push_back(g);
+        moved.clear();
+    };
+    for (int u = 0; u < count; ++u) {
+        const int t = descending ? count - 1 - u : u;
+        const int j = (int)piv[t];
+        if (j == t) continue;
+        const int fresh = (at(t) < 0 ? 1 : 0) + (at(j) < 0 ? 1 : 0);
+        if ((int)moved.size() + fresh > lim) flush();
+        int kt = at(t), kj = at(j);
+        if (kt < 0) {
+            kt = (int)moved.size();
+            moved.push_back({t, t});
+            slot[(size_t)t] = kt;
+        }
+        if (kj < 0) {
+            kj = (int)moved.size();
+            moved.push_back({j, j});
+            slot[(size_t)j] = kj;
+        }
+        std::swap(moved[(size_t)kt].second, moved[(size_t)kj].second);
+    }
+    flush();
+}
+
+// A P^T on rows [0, rows): columns t <-> piv[t] for t = 0..count-1 in order.
+template <typename T>
+void apply_transpositions(Ctx& c, T* A, int64_t lda, int rows, const int64_t* piv, int count,
+                          bool descending = false)
+{
+    if (rows <= 0 || count <= 0) return;
+    Gathers gs;
+    compose_transpositions(piv, count, descending, kGatherMax, gs);
+    for (const GatherList& g : gs.lists) launch_colgather<T>(c.s, A, lda, rows, g);
+}
+
+// The same on rows: rows t <-> piv[t] over columns [0, cols).
+template <typename T>
+void apply_row_transpositions(Ctx& c, T* A, int64_t lda, int cols, const int64_t* piv, int count,
+                              bool descending)
+{
+    if (cols <= 0 || count <= 0) return;
+    Gathers gs;
+    compose_transpositions(piv, count, descending, kGatherRows, gs);
+    for (const GatherList& g : gs.lists) launch_rowgather<T>(c.s, A, lda, cols, g);
 }
 
 // ------------------------------------------------------------- CUP leaf

@@ -921,9 +921,12 @@ __global__ __launch_bounds__(256) void pair_update_i8_kernel(T* __restrict__ A, 
 }
 
 // [N\T] <- T N on an nb x nb block (nb <= 64): T unit upper (strict upper
-// part stored), N lower with its diagonal.  Thread j holds column j of N;
-// used for p > kExact64 (every product reduced as it is added).
-template <typename T, bool BIG>
+// part stored), N lower with its diagonal (TRULM's leaf); with LU, the
+// other product of the same storage, [L\U] <- L U with L lower with its
+// diagonal and U unit upper (TRLUM's leaf).  Thread j holds column j of the
+// right factor; used for p > kExact64 (every product reduced as it is
+// added).
+template <typename T, bool BIG, bool LU>
 __global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ A, int64_t lda, ModP mp)
 {
     __shared__ double Tu[NB][NB + 1];
@@ -932,20 +935,28 @@ __global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ 
     for (int idx = j; idx < NB * NB; idx += NB) {
         int i = idx >> 6, s = idx & 63;
         double v = 0.0;
-        if (i < nb && s < nb) v = (s > i) ? ld_res(A + (int64_t)i * lda + s) : (s == i ? 1.0 : 0.0);
+        if (i < nb && s < nb) {
+            if (LU) v = (s <= i) ? ld_res(A + (int64_t)i * lda + s) : 0.0;
+            else v = (s > i) ? ld_res(A + (int64_t)i * lda + s) : (s == i ? 1.0 : 0.0);
+        }
         Tu[i][s] = v;
     }
     double ncol[NB];
 #pragma unroll
-    for (int s = 0; s < NB; ++s)
-        ncol[s] = (j < nb && s < nb && s >= j) ? ld_res(A + (int64_t)s * lda + j) : 0.0;
+    for (int s = 0; s < NB; ++s) {
+        if (LU)
+            ncol[s] = (j < nb && s < nb && s < j) ? ld_res(A + (int64_t)s * lda + j) : (s == j ? 1.0 : 0.0);
+        else
+            ncol[s] = (j < nb && s < nb && s >= j) ? ld_res(A + (int64_t)s * lda + j) : 0.0;
+    }
     __syncthreads();
     double x[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) x[q] = 0.0;
     for (int i = 0; i < NB; ++i) {
         double acc = 0.0;
-        for (int s = i; s < NB; ++s) {
+        const int s0 = LU ? 0 : i, s1 = LU ? i + 1 : NB;
+        for (int s = s0; s < s1; ++s) {
             double nv = 0.0;
 #pragma unroll
             for (int q = 0; q < NB; ++q) nv = (q == s) ? ncol[q] : nv;
@@ -963,13 +974,14 @@ __global__ __launch_bounds__(NB) void trulm_leaf_kernel(int nb, T* __restrict__ 
     }
 }
 
-// The same product on the FP64 matrix cores for p <= kExact64: T (unit
-// upper, identity-padded) and N (lower with its diagonal, zero-padded) are
-// staged in LDS as dense 64 x 64 triangles, and wave w forms rows
-// 16w..16w+15 of T N with 64 v_mfma_f64_16x16x4f64 (a sum of at most 64
-// canonical products is exact).  Every read of the block precedes the
-// barrier before the block is overwritten.
-template <typename T>
+// The same products on the FP64 matrix cores for p <= kExact64: the left
+// factor (T unit upper, identity-padded; with LU, L lower with its
+// diagonal) and the right one (N lower with its diagonal; with LU, U unit
+// upper) are staged in LDS as dense 64 x 64 triangles, and wave w forms
+// rows 16w..16w+15 of the product with 64 v_mfma_f64_16x16x4f64 (a sum of
+// at most 64 canonical products is exact).  Every read of the block
+// precedes the barrier before the block is overwritten.
+template <typename T, bool LU>
 __global__ __launch_bounds__(256) void trulm_mfma_kernel(int nb, T* __restrict__ A, int64_t lda, ModP mp)
 {
     __shared__ double Tu[NB][NB + 1];
@@ -986,8 +998,10 @@ __global__ __launch_bounds__(256) void trulm_mfma_kernel(int nb, T* __restrict__
     for (int it = 0; it < NB * NB / 256; ++it) {
         const int idx = tid + 256 * it, i = idx >> 6, s = idx & 63;
         const bool in = i < nb && s < nb;
-        Tu[i][s] = (i == s) ? 1.0 : ((in && s > i) ? ev[it] : 0.0);
-        Nl[i][s] = (in && s <= i) ? ev[it] : 0.0;
+        const double up = (i == s) ? 1.0 : ((in && s > i) ? ev[it] : 0.0);
+        const double lo_ = (in && s <= i) ? ev[it] : 0.0;
+        Tu[i][s] = LU ? lo_ : up;
+        Nl[i][s] = LU ? up : lo_;
     }
     __syncthreads();
     v4d acc[4];
@@ -1141,9 +1155,20 @@ void launch_trulm_leaf(hipStream_t s, int nb, T* A, int64_t lda, ModP mp, int64_
     (void)kred;
     if (nb <= 0) return;
     if (big_prime(mp))
-        hipLaunchKernelGGL((trulm_leaf_kernel<T, true>), dim3(1), dim3(NB), 0, s, nb, A, lda, mp);
+        hipLaunchKernelGGL((trulm_leaf_kernel<T, true, false>), dim3(1), dim3(NB), 0, s, nb, A, lda, mp);
     else
-        hipLaunchKernelGGL(trulm_mfma_kernel<T>, dim3(1), dim3(256), 0, s, nb, A, lda, mp);
+        hipLaunchKernelGGL((trulm_mfma_kernel<T, false>), dim3(1), dim3(256), 0, s, nb, A, lda, mp);
+    CUP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_trlum_leaf(hipStream_t s, int nb, T* A, int64_t lda, ModP mp)
+{
+    if (nb <= 0) return;
+    if (big_prime(mp))
+        hipLaunchKernelGGL((trulm_leaf_kernel<T, true, true>), dim3(1), dim3(NB), 0, s, nb, A, lda, mp);
+    else
+        hipLaunchKernelGGL((trulm_mfma_kernel<T, true>), dim3(1), dim3(256), 0, s, nb, A, lda, mp);
     CUP_HIP(hipGetLastError());
 }
 
@@ -1167,6 +1192,7 @@ void launch_negate(hipStream_t s, T* B, int64_t ldb, int rows, int cols, ModP mp
     template void launch_tri_apply<T>(hipStream_t, int, int, const double*, T*, int64_t, int,   \
                                       ModP, const int*, int);                                   \
     template void launch_trulm_leaf<T>(hipStream_t, int, T*, int64_t, ModP, int64_t);           \
+    template void launch_trlum_leaf<T>(hipStream_t, int, T*, int64_t, ModP);                    \
     template void launch_pair_update<T>(hipStream_t, T*, int64_t, int, const double*, const int*, \
                                         ModP, bool);                                              \
     template bool launch_tri_slab<T>(hipStream_t, int, const T*, int64_t, const double*, T*,    \

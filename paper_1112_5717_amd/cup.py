@@ -39,6 +39,13 @@ SIGNATURES = {
                                   ctypes.c_int]),
     "cup_ffgemm_i8": (ctypes.c_int, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _I64,
                                      ctypes.c_int]),
+    "cup_ple": (ctypes.c_int, [_I64, _I64, _VP, _I64, _I64, _PI64, _VP, _VP]),
+    "cup_ple_i8": (ctypes.c_int, [_I64, _I64, _VP, _I64, _I64, _PI64, _VP, _VP]),
+    "cup_det": (ctypes.c_int, [_I64, _VP, _I64, _I64, _PI64, _PI64]),
+    "cup_solve": (ctypes.c_int, [_I64, _I64, _VP, _I64, _VP, _I64, _I64, _PI64]),
+    "cup_nullspace": (ctypes.c_int, [_I64, _I64, _VP, _I64, _I64, _PI64, _VP, _VP, _I64]),
+    "cup_trlum": (ctypes.c_int, [_I64, _VP, _I64, _I64]),
+    "cup_inplace_mm": (ctypes.c_int, [_I64, _I64, _VP, _I64, _VP, _I64, _I64]),
     "cup_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cup_profile": (ctypes.c_int, [ctypes.c_int]),
     "cup_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double)]),
@@ -241,6 +248,92 @@ class FlatBatch:
                                        _vec(self.pP), _vec(self.pQ), _vec(self.info))
         if rc < 0:
             raise CupError(rc, "cup_factor_batched")
+
+
+def _ple(name, A, p, dtype):
+    m, n, lda, ptr = _matrix(A, dtype)
+    P = torch.empty(m, dtype=torch.int64, device=A.device)
+    Q = torch.empty(n, dtype=torch.int64, device=A.device)
+    r = ctypes.c_int64(0)
+    _sync_stream()
+    rc = getattr(load(), name)(m, n, ptr, lda, int(p), ctypes.byref(r), _vec(P), _vec(Q))
+    if rc < 0:
+        raise CupError(rc, name)
+    return int(r.value), P, Q
+
+
+def cup_ple(A: torch.Tensor, p: int):
+    """In-place PLE of an int64 device matrix (A <- [L\\E]); returns (rank, P, Q)."""
+    return _ple("cup_ple", A, p, torch.int64)
+
+
+def cup_ple_i8(A: torch.Tensor, p: int):
+    return _ple("cup_ple_i8", A, p, torch.int8)
+
+
+def cup_det(A: torch.Tensor, p: int):
+    """Determinant of a square int64 device matrix (A <- [C\\U]); returns (det, rank)."""
+    m, n, lda, ptr = _matrix(A, torch.int64)
+    if m != n:
+        raise ValueError("square matrix expected")
+    d, r = ctypes.c_int64(0), ctypes.c_int64(0)
+    _sync_stream()
+    rc = load().cup_det(n, ptr, lda, int(p), ctypes.byref(d), ctypes.byref(r))
+    if rc < 0:
+        raise CupError(rc, "cup_det")
+    return int(d.value), int(r.value)
+
+
+def cup_solve(A: torch.Tensor, B: torch.Tensor, p: int):
+    """B <- A^{-1} B (A <- [C\\U]); returns (nonsingular, rank)."""
+    n, n2, lda, pa = _matrix(A, torch.int64)
+    nb, nrhs, ldb, pb = _matrix(B, torch.int64)
+    if n != n2 or nb != n:
+        raise ValueError("A must be n x n and B n x nrhs")
+    r = ctypes.c_int64(0)
+    _sync_stream()
+    rc = load().cup_solve(n, nrhs, pa, lda, pb, max(ldb, 1), int(p), ctypes.byref(r))
+    if rc < 0:
+        raise CupError(rc, "cup_solve")
+    return rc == CUP_OK, int(r.value)
+
+
+def cup_nullspace(A: torch.Tensor, p: int):
+    """Right nullspace basis N (n x (n - rank)) of an int64 device matrix
+    (A is overwritten); returns (N, rank, P)."""
+    m, n, lda, ptr = _matrix(A, torch.int64)
+    N = torch.empty((max(n, 1), max(n, 1)), dtype=torch.int64, device=A.device)
+    P = torch.empty(n, dtype=torch.int64, device=A.device)
+    r = ctypes.c_int64(0)
+    _sync_stream()
+    rc = load().cup_nullspace(m, n, ptr, lda, int(p), ctypes.byref(r), _vec(P), _vec(N), max(n, 1))
+    if rc < 0:
+        raise CupError(rc, "cup_nullspace")
+    rank = int(r.value)
+    return N[:n, : n - rank], rank, P
+
+
+def cup_trlum(A: torch.Tensor, p: int) -> None:
+    """A = [L\\U] <- L U in place (L lower with diagonal, U unit upper)."""
+    m, n, lda, ptr = _matrix(A, torch.int64)
+    if m != n:
+        raise ValueError("square matrix expected")
+    _sync_stream()
+    rc = load().cup_trlum(n, ptr, lda, int(p))
+    if rc < 0:
+        raise CupError(rc, "cup_trlum")
+
+
+def cup_inplace_mm(A: torch.Tensor, B: torch.Tensor, p: int) -> None:
+    """B <- A B in place (A m x m is restored on return)."""
+    m, m2, lda, pa = _matrix(A, torch.int64)
+    mb, n, ldb, pb = _matrix(B, torch.int64)
+    if m != m2 or mb != m:
+        raise ValueError("A must be m x m and B m x n")
+    _sync_stream()
+    rc = load().cup_inplace_mm(m, n, pa, lda, pb, max(ldb, 1), int(p))
+    if rc < 0:
+        raise CupError(rc, "cup_inplace_mm")
 
 
 def cup_ffgemm(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, p: int, alpha: int = -1):

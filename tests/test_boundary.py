@@ -60,3 +60,32 @@ def test_argument_validation():
     assert lib.cup_set_form(9) == -1
     for code in (0, 1, -1, -5, -1001, -2000, -3000):
         assert cup.strerror(code)
+
+
+def test_argument_validation_derived():
+    from paper_1112_5717_amd import cup
+    lib = cup.load()
+    r = ctypes.c_int64(0)
+    d = ctypes.c_int64(0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.cup_ple(-1, 4, fake, 4, 7, ctypes.byref(r), None, None) == -1
+    assert lib.cup_ple(4, 4, fake, 3, 7, ctypes.byref(r), None, None) == -4
+    assert lib.cup_ple_i8(4, 4, fake, 4, 131, ctypes.byref(r), None, None) == -5
+    assert lib.cup_det(-1, fake, 4, 7, ctypes.byref(d), ctypes.byref(r)) == -1
+    assert lib.cup_det(4, None, 4, 7, ctypes.byref(d), ctypes.byref(r)) == -2
+    assert lib.cup_det(4, fake, 3, 7, ctypes.byref(d), ctypes.byref(r)) == -3
+    assert lib.cup_det(4, fake, 4, 8, ctypes.byref(d), ctypes.byref(r)) == -4
+    assert lib.cup_det(4, fake, 4, 7, None, ctypes.byref(r)) == -5
+    assert lib.cup_det(4, fake, 4, 7, ctypes.byref(d), None) == -6
+    assert lib.cup_solve(-1, 1, fake, 4, fake, 1, 7, ctypes.byref(r)) == -1
+    assert lib.cup_solve(4, -1, fake, 4, fake, 1, 7, ctypes.byref(r)) == -2
+    assert lib.cup_solve(4, 2, fake, 4, None, 2, 7, ctypes.byref(r)) == -5
+    assert lib.cup_solve(4, 2, fake, 4, fake, 1, 7, ctypes.byref(r)) == -6
+    assert lib.cup_solve(4, 2, fake, 4, fake, 2, 9, ctypes.byref(r)) == -7
+    assert lib.cup_solve(4, 2, fake, 4, fake, 2, 7, None) == -8
+    assert lib.cup_nullspace(4, 5, fake, 5, 7, ctypes.byref(r), None, None, 5) == -8
+    assert lib.cup_nullspace(4, 5, fake, 5, 7, ctypes.byref(r), None, fake, 4) == -9
+    assert lib.cup_trlum(-1, fake, 4, 7) == -1
+    assert lib.cup_trlum(4, fake, 4, 6) == -4
+    assert lib.cup_inplace_mm(4, 3, fake, 3, fake, 3, 7) == -4
+    assert lib.cup_inplace_mm(4, 3, fake, 4, fake, 2, 7) == -6
