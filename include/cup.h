@@ -64,6 +64,10 @@ extern "C" {
 /* An internal consistency check of a kernel failed (a pivot row that a
  * waiting wave never received); the matrix is then unspecified. */
 #define CUP_ERR_INTERNAL (-3000)
+/* A size beyond the fixed scratch of an allocation-free entry point. */
+#define CUP_ERR_NOALLOC_LIMIT (-4000)
+/* Largest batch of cup_factor_batched_noalloc. */
+#define CUP_NOALLOC_BATCH_MAX 32768
 
 /* Forms of the modular matrix product (ffgemm) used inside every call.
  *   FP64   : FP64 MFMA as an exact integer carrier, any p < 2^26.
@@ -245,6 +249,24 @@ int cup_trlum(int64_t n, int64_t *A, int64_t lda, int64_t p);
  * Errors: -1 m, -2 n, -3 A, -4 lda, -5 B, -6 ldb, -7 p.
  */
 int cup_inplace_mm(int64_t m, int64_t n, int64_t *A, int64_t lda, int64_t *B, int64_t ldb, int64_t p);
+
+/*
+ * cup_factor_batched for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same arguments, launches and results as cup_factor_batched, but the
+ * library's scratch (the processing order of the batch, 4 bytes per matrix)
+ * lives in a static device array of CUP_NOALLOC_BATCH_MAX entries (128 KiB,
+ * held on each GPU the library runs on until the process ends), so the call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * The caller passes every input and output.  A batch above
+ * CUP_NOALLOC_BATCH_MAX returns CUP_ERR_NOALLOC_LIMIT before any work.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams, or from different threads without ordering)
+ * race on it.  Asynchronous on the stream, like cup_factor_batched.
+ */
+int cup_factor_batched_noalloc(int64_t batch, const int64_t *m, const int64_t *n, int64_t *const *A,
+                               const int64_t *lda, const int64_t *p, int64_t *rank,
+                               int64_t *const *P, int64_t *const *Q, int32_t *info);
 
 /*
  * Modular matrix product, the black box of Section 3.2 (Algorithm 1) that

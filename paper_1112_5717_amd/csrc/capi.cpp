@@ -38,6 +38,34 @@ struct Global {
 
 constexpr int64_t kOrderMax = 32768;  // largest batch that is sorted by cost
 
+// Scratch of the allocation-free batched entry point: the processing order
+// of up to CUP_NOALLOC_BATCH_MAX matrices, one copy per GPU in the device
+// image of this file (128 KiB), held until the process ends.  Host code never
+// passes the array's name to a kernel (in host code it is a host-side
+// stand-in); it passes the device address that hipGetSymbolAddress returns
+// for the current device, resolved once per device.
+static_assert(CUP_NOALLOC_BATCH_MAX <= kOrderMax, "the batched order covers the no-alloc limit");
+static __device__ __align__(256) int scratch[CUP_NOALLOC_BATCH_MAX];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (under the library
+// lock).
+void* noalloc_scratch()
+{
+    int dev = 0;
+    CUP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw CupError{CUP_ERR_HIP - (int)hipErrorInvalidDevice};
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        CUP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw CupError{CUP_ERR_INTERNAL};
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 Global& G()
 {
     static Global g;
@@ -704,6 +732,33 @@ int cup_inplace_mm(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t* B, in
     return inplace_mm_impl(m, n, A, lda, B, ldb, p);
 }
 
+int cup_factor_batched_noalloc(int64_t batch, const int64_t* m, const int64_t* n, int64_t* const* A,
+                               const int64_t* lda, const int64_t* p, int64_t* rank, int64_t* const* P,
+                               int64_t* const* Q, int32_t* info)
+{
+    if (batch < 0) return -1;
+    if (batch > CUP_NOALLOC_BATCH_MAX) return CUP_ERR_NOALLOC_LIMIT;
+    if (batch == 0) return CUP_OK;
+    if (!m) return -2;
+    if (!n) return -3;
+    if (!A) return -4;
+    if (!lda) return -5;
+    if (!p) return -6;
+    if (!rank) return -7;
+    if (!info) return -10;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    try {
+        // the same launches as cup_factor_batched, with the processing order
+        // in this device's static scratch array instead of library memory
+        int* order = static_cast<int*>(noalloc_scratch());
+        launch_batched_cup(g.stream, (int)batch, m, n, A, lda, p, rank, P, Q, info, order);
+        return CUP_OK;
+    } catch (const CupError& e) {
+        return e.code;
+    }
+}
+
 int cup_ffgemm(int64_t M, int64_t N, int64_t K, const int64_t* A, int64_t lda, const int64_t* B,
                int64_t ldb, int64_t* C, int64_t ldc, int64_t p, int alpha)
 {
@@ -722,6 +777,8 @@ const char* cup_strerror(int status)
     if (status == CUP_SINGULAR) return "matrix is singular";
     if (status == CUP_ERR_ALLOC) return "allocation failure";
     if (status == CUP_ERR_INTERNAL) return "internal kernel check failed";
+    if (status == CUP_ERR_NOALLOC_LIMIT)
+        return "batch larger than the allocation-free entry point's static scratch (CUP_NOALLOC_BATCH_MAX)";
     if (status <= CUP_ERR_HIP && status > CUP_ERR_ALLOC) return "HIP runtime error";
     switch (status) {
     case -1: return "argument 1 is invalid";

@@ -35,6 +35,7 @@ SIGNATURES = {
     "cup_inverse_inplace": (ctypes.c_int, [_I64, _VP, _I64, _I64, _PI64]),
     "cup_inverse_inplace_i8": (ctypes.c_int, [_I64, _VP, _I64, _I64, _PI64]),
     "cup_factor_batched": (ctypes.c_int, [_I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "cup_factor_batched_noalloc": (ctypes.c_int, [_I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "cup_ffgemm": (ctypes.c_int, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _I64,
                                   ctypes.c_int]),
     "cup_ffgemm_i8": (ctypes.c_int, [_I64, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _I64,
@@ -180,8 +181,10 @@ def cup_inverse_inplace_i8(A: torch.Tensor, p: int):
     return _inverse("cup_inverse_inplace_i8", A, p, torch.int8)
 
 
-def cup_factor_batched(mats: list[torch.Tensor], primes, want_pq: bool = True):
-    """Batched CUP of int64 device matrices, one prime each.
+def cup_factor_batched(mats: list[torch.Tensor], primes, want_pq: bool = True,
+                       name: str = "cup_factor_batched"):
+    """Batched CUP of int64 device matrices, one prime each (``name`` selects
+    the entry point: cup_factor_batched or cup_factor_batched_noalloc).
 
     Returns (rank, info, Ps, Qs): rank and info are device tensors.
     """
@@ -200,11 +203,16 @@ def cup_factor_batched(mats: list[torch.Tensor], primes, want_pq: bool = True):
     rank = torch.zeros(B, dtype=torch.int64, device=dev)
     info = torch.zeros(B, dtype=torch.int32, device=dev)
     _sync_stream()
-    rc = load().cup_factor_batched(B, _vec(m), _vec(n), _vec(ptrs), _vec(lda), _vec(pp), _vec(rank),
-                                   _vec(pP), _vec(pQ), _vec(info))
+    rc = getattr(load(), name)(B, _vec(m), _vec(n), _vec(ptrs), _vec(lda), _vec(pp), _vec(rank),
+                               _vec(pP), _vec(pQ), _vec(info))
     if rc < 0:
-        raise CupError(rc, "cup_factor_batched")
+        raise CupError(rc, name)
     return rank, info, Ps, Qs
+
+
+def cup_factor_batched_noalloc(mats: list[torch.Tensor], primes, want_pq: bool = True):
+    """cup_factor_batched through the allocation-free entry point."""
+    return cup_factor_batched(mats, primes, want_pq, name="cup_factor_batched_noalloc")
 
 
 class FlatBatch:
@@ -240,14 +248,14 @@ class FlatBatch:
             raise TypeError("flat must be a contiguous int64 device buffer holding the batch")
         return flat.data_ptr() + self.dbyte_offs
 
-    def factor(self, ptrs: torch.Tensor) -> None:
-        """cup_factor_batched over the matrices at ``ptrs`` (asynchronous)."""
+    def factor(self, ptrs: torch.Tensor, name: str = "cup_factor_batched") -> None:
+        """cup_factor_batched (or ``name``) over the matrices at ``ptrs`` (asynchronous)."""
         _sync_stream()
-        rc = load().cup_factor_batched(self.count, _vec(self.dm), _vec(self.dn), _vec(ptrs),
-                                       _vec(self.dn), _vec(self.dp), _vec(self.rank),
-                                       _vec(self.pP), _vec(self.pQ), _vec(self.info))
+        rc = getattr(load(), name)(self.count, _vec(self.dm), _vec(self.dn), _vec(ptrs),
+                                   _vec(self.dn), _vec(self.dp), _vec(self.rank),
+                                   _vec(self.pP), _vec(self.pQ), _vec(self.info))
         if rc < 0:
-            raise CupError(rc, "cup_factor_batched")
+            raise CupError(rc, name)
 
 
 def _ple(name, A, p, dtype):
