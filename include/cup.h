@@ -89,6 +89,20 @@ int cup_set_form(int form);
 int cup_get_form(void);
 
 /*
+ * Strassen-Winograd products (Section 4.4, Table 1's exponent log2 7, after
+ * Winograd's seven-product scheme) for later calls: every modular product
+ * whose M, N and K are all at least min_dim is split into quadrants and
+ * formed with seven half-size products instead of eight, recursively up to
+ * `levels` times (0, the default, keeps the classical products).  Sums of
+ * quadrants and the seven partial products are canonical residue matrices
+ * in a library workspace of about (4/3)(MK + KN + MN) elements for one level
+ * (reported by cup_workspace_bytes), so results are identical to the
+ * classical product's.  Returns -1 for levels outside 0..8, -2 for
+ * min_dim < 128.
+ */
+int cup_set_winograd(int levels, int64_t min_dim);
+
+/*
  * CUP decomposition (Section 3.3, Algorithm 6).
  *   m, n  : dimensions (>= 0)
  *   A     : device, m x n, int64 residues; overwritten in place with the

@@ -19,6 +19,8 @@ struct Global {
     std::mutex mu;
     hipStream_t stream = nullptr;
     int form = FORM_AUTO;
+    int wino_levels = 0;     // Strassen-Winograd recursion levels (0: off)
+    int wino_min = 2048;     // smallest dimension split by it
     int* d_small = nullptr;
     int* h_small = nullptr;
     // Result words of the window kernel in mapped, coherent host memory (kept
@@ -213,6 +215,8 @@ Ctx make_ctx(Global& g, int64_t p, int form)
     if (const char* v = std::getenv("CUP_I8_MIN_WORK")) c.i8_min_work = std::atof(v);
     c.prof = &g.prof;
     c.ws = &g.ws;
+    c.wino_levels = g.wino_levels;
+    c.wino_min = g.wino_min;
     ctx_set_prime(c, p);
     return c;
 }
@@ -587,6 +591,17 @@ int cup_set_form(int form)
     return CUP_OK;
 }
 
+int cup_set_winograd(int levels, int64_t min_dim)
+{
+    if (levels < 0 || levels > 8) return -1;
+    if (min_dim < 2 * kTriNB || min_dim > INT32_MAX / 2) return -2;
+    Global& g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    g.wino_levels = levels;
+    g.wino_min = (int)min_dim;
+    return CUP_OK;
+}
+
 int cup_get_form(void)
 {
     Global& g = G();
@@ -840,6 +855,7 @@ int cup_finalize(void)
     if (g.ws.uc) (void)hipFree(g.ws.uc);
     if (g.ws.pk) (void)hipFree(g.ws.pk);
     if (g.ws.tp) (void)hipFree(g.ws.tp);
+    if (g.ws.wg) (void)hipFree(g.ws.wg);
     g.ws = Workspace{};
     g.d_small = nullptr;
     g.h_small = nullptr;

@@ -112,6 +112,20 @@ void launch_mma_i8_direct(hipStream_t s, int M, int N, int K, const T* A, int64_
                           int64_t ldb, T* C, int64_t ldc, ModP mp, int alpha, hipEvent_t ev0 = nullptr,
                           hipEvent_t ev1 = nullptr);
 
+// One level of the Strassen-Winograd product (see k_wino.hip), on residue
+// matrices: the four sums of the quadrants of X (2 hr x 2 hc; side 0 forms
+// S1..S4 from A, side 1 T1..T4 from B) into o1..o4 (hr x hc, dense); zeroing
+// of `count` elements; and C's quadrants (2 hm x 2 hn) += alpha times the
+// combinations of P1 = W, P6 = X, P5 = Y, P7 = Z (hm x hn, dense).
+template <typename T>
+void launch_wino_pre(hipStream_t s, const T* X, int64_t ldx, int hr, int hc, int side, int64_t p, T* o1,
+                     T* o2, T* o3, T* o4);
+template <typename T>
+void launch_wino_zero(hipStream_t s, T* X, int64_t count);
+template <typename T>
+void launch_wino_post(hipStream_t s, T* C, int64_t ldc, int hm, int hn, const T* W, const T* X, const T* Y,
+                      const T* Z, int alpha, int64_t p);
+
 // Window elimination of a leaf (see k_panel.hip).  Writes d, stop and the
 // chosen columns to `out` (device ints: out[0]=d, out[1]=stop, out[2+a]=col)
 // and, when `mail` is given (mapped host memory), the same values to

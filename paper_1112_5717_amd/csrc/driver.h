@@ -117,6 +117,8 @@ struct Workspace {
     size_t pk_cap = 0;     // bytes
     void* tp = nullptr;    // the transpose of a rectangular matrix (PLE)
     size_t tp_cap = 0;     // bytes
+    void* wg = nullptr;    // Strassen-Winograd temporaries
+    size_t wg_cap = 0;     // bytes
     size_t bytes = 0;
 };
 
@@ -149,6 +151,10 @@ struct Ctx {
     bool defer_on = false;
     int log = 0;
     double i8_min_work = 1.0e9;  // M N K below which products skip the packed INT8 kernel
+    // Strassen-Winograd: recursion levels (0: classical products only) and
+    // the smallest M, N, K that is split
+    int wino_levels = 0;
+    int wino_min = 2048;
     // The matrix being factored (its top-left and leading dimension) and
     // which 64 x 64 diagonal blocks of its U have their inverse in ws->uc.
     const void* base = nullptr;
@@ -335,8 +341,8 @@ inline int split_at(int n, int unit)
 
 // ------------------------------------------------------------------ ffgemm
 template <typename T>
-void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
-          int64_t ldc, int alpha)
+void gemm_classic(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
+                  int64_t ldc, int alpha)
 {
     if (M <= 0 || N <= 0 || K <= 0) return;
     // The packed INT8 kernel pays two packing launches per product, so only
@@ -387,6 +393,112 @@ void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int6
             launch_ffgemm_f64<T>(c.s, M, N, K, A, lda, B, ldb, C, ldc, c.mp, alpha, c.kred_steps, e0,
                                  e1);
     }
+}
+
+// Strassen-Winograd (Table 1's exponent log2 7, Section 4.4): with the
+// leading Me x Ke, Ke x Ne parts (multiples of 128) split into quadrants,
+// C += alpha A B takes seven half-size products (each again split while
+// `level` allows and the halves reach c.wino_min) instead of eight; P2, P3
+// and P4 accumulate straight into their quadrant of C, P1, P5, P6 and P7
+// into temporaries that one pass folds into C.  The rows, columns and depth
+// beyond the even parts are classical products.  Every temporary is a
+// canonical residue matrix, so results equal the classical product's.
+inline size_t wino_elems(const Ctx& c, int M, int N, int K, int level)
+{
+    const int g = 2 * kTriNB;
+    const int Me = M / g * g, Ne = N / g * g, Ke = K / g * g;
+    if (level <= 0 || Me < c.wino_min || Ne < c.wino_min || Ke < c.wino_min) return 0;
+    const size_t hm = (size_t)Me / 2, hn = (size_t)Ne / 2, hk = (size_t)Ke / 2;
+    return 4 * (hm * hk + hk * hn + hm * hn) + wino_elems(c, (int)hm, (int)hn, (int)hk, level - 1);
+}
+
+template <typename T>
+void gemm_wino(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
+               int64_t ldc, int alpha, int level, T* ws)
+{
+    const int g = 2 * kTriNB;
+    const int Me = M / g * g, Ne = N / g * g, Ke = K / g * g;
+    if (level <= 0 || Me < c.wino_min || Ne < c.wino_min || Ke < c.wino_min) {
+        gemm_classic(c, M, N, K, A, lda, B, ldb, C, ldc, alpha);
+        return;
+    }
+    const int hm = Me / 2, hn = Ne / 2, hk = Ke / 2;
+    const int64_t sa = (int64_t)hm * hk, sb = (int64_t)hk * hn, sc = (int64_t)hm * hn;
+    T* S1 = ws;
+    T* S2 = S1 + sa;
+    T* S3 = S2 + sa;
+    T* S4 = S3 + sa;
+    T* T1 = S4 + sa;
+    T* T2 = T1 + sb;
+    T* T3 = T2 + sb;
+    T* T4 = T3 + sb;
+    T* Pw = T4 + sb;  // P1
+    T* Px = Pw + sc;  // P6
+    T* Py = Px + sc;  // P5
+    T* Pz = Py + sc;  // P7
+    T* next = Pz + sc;
+    const T* A11 = A;
+    const T* A12 = A + hk;
+    const T* A21 = A + (int64_t)hm * lda;
+    const T* A22 = A21 + hk;
+    const T* B11 = B;
+    const T* B21 = B + (int64_t)hk * ldb;
+    const T* B22 = B21 + hn;
+    T* C11 = C;
+    T* C12 = C + hn;
+    T* C21 = C + (int64_t)hm * ldc;
+    launch_wino_pre<T>(c.s, A, lda, hm, hk, 0, c.p, S1, S2, S3, S4);
+    launch_wino_pre<T>(c.s, B, ldb, hk, hn, 1, c.p, T1, T2, T3, T4);
+    launch_wino_zero<T>(c.s, Pw, 4 * sc);
+    gemm_wino(c, hm, hn, hk, A12, lda, B21, ldb, C11, ldc, alpha, level - 1, next);   // P2
+    gemm_wino(c, hm, hn, hk, (const T*)S4, hk, B22, ldb, C12, ldc, alpha, level - 1, next);  // P3
+    gemm_wino(c, hm, hn, hk, A22, lda, (const T*)T4, hn, C21, ldc, -alpha, level - 1, next); // P4
+    gemm_wino(c, hm, hn, hk, A11, lda, B11, ldb, Pw, hn, +1, level - 1, next);         // P1
+    gemm_wino(c, hm, hn, hk, (const T*)S1, hk, (const T*)T1, hn, Py, hn, +1, level - 1, next);  // P5
+    gemm_wino(c, hm, hn, hk, (const T*)S2, hk, (const T*)T2, hn, Px, hn, +1, level - 1, next);  // P6
+    gemm_wino(c, hm, hn, hk, (const T*)S3, hk, (const T*)T3, hn, Pz, hn, +1, level - 1, next);  // P7
+    launch_wino_post<T>(c.s, C, ldc, hm, hn, Pw, Px, Py, Pz, alpha, c.p);
+    if (Ke < K) gemm_classic(c, Me, Ne, K - Ke, A + Ke, lda, B + (int64_t)Ke * ldb, ldb, C, ldc, alpha);
+    if (Ne < N) gemm_classic(c, Me, N - Ne, K, A, lda, B + Ne, ldb, C + Ne, ldc, alpha);
+    if (Me < M) gemm_classic(c, M - Me, N, K, A + (int64_t)Me * lda, lda, B, ldb, C + (int64_t)Me * ldc, ldc,
+                             alpha);
+}
+
+inline void* wino_workspace(Ctx& c, size_t bytes)
+{
+    Workspace& w = *c.ws;
+    if (bytes > w.wg_cap) {
+        if (w.wg) {
+            CUP_HIP(hipStreamSynchronize(c.s));
+            CUP_HIP(hipFree(w.wg));
+            w.bytes -= w.wg_cap;
+            w.wg = nullptr;
+            w.wg_cap = 0;
+        }
+        if (dev_malloc(&w.wg, bytes) != hipSuccess) {
+            w.wg = nullptr;
+            throw CupError{-2000};
+        }
+        w.wg_cap = bytes;
+        w.bytes += bytes;
+    }
+    return w.wg;
+}
+
+// C <- C + alpha A B mod p (Algorithm 1): Strassen-Winograd when it is
+// enabled and the product is large enough, else the classical kernels.
+template <typename T>
+void gemm(Ctx& c, int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
+          int64_t ldc, int alpha)
+{
+    if (M <= 0 || N <= 0 || K <= 0) return;
+    const size_t need = wino_elems(c, M, N, K, c.wino_levels);
+    if (need == 0) {
+        gemm_classic(c, M, N, K, A, lda, B, ldb, C, ldc, alpha);
+        return;
+    }
+    T* ws = static_cast<T*>(wino_workspace(c, need * sizeof(T)));
+    gemm_wino(c, M, N, K, A, lda, B, ldb, C, ldc, alpha, c.wino_levels, ws);
 }
 
 // ------------------------------------------------------------ TRSM / TRMM

@@ -27,6 +27,7 @@ SIGNATURES = {
     "cup_set_stream": (ctypes.c_int, [_VP]),
     "cup_set_form": (ctypes.c_int, [ctypes.c_int]),
     "cup_get_form": (ctypes.c_int, []),
+    "cup_set_winograd": (ctypes.c_int, [ctypes.c_int, _I64]),
     "cup_factor": (ctypes.c_int, [_I64, _I64, _VP, _I64, _I64, _PI64, _VP, _VP]),
     "cup_factor_i8": (ctypes.c_int, [_I64, _I64, _VP, _I64, _I64, _PI64, _VP, _VP]),
     "cup_rank_profile": (ctypes.c_int, [_I64, _I64, _VP, _I64, _I64, _PI64, _VP]),
@@ -111,6 +112,14 @@ def cup_set_form(form) -> None:
     rc = load().cup_set_form(code)
     if rc != 0:
         raise CupError(rc, "cup_set_form")
+
+
+def cup_set_winograd(levels: int, min_dim: int = 2048) -> None:
+    """Strassen-Winograd products up to `levels` recursion levels for products
+    whose dimensions all reach `min_dim` (0 levels: classical products)."""
+    rc = load().cup_set_winograd(int(levels), int(min_dim))
+    if rc != 0:
+        raise CupError(rc, "cup_set_winograd")
 
 
 def cup_get_form() -> int:

@@ -89,3 +89,7 @@ def test_argument_validation_derived():
     assert lib.cup_trlum(4, fake, 4, 6) == -4
     assert lib.cup_inplace_mm(4, 3, fake, 3, fake, 3, 7) == -4
     assert lib.cup_inplace_mm(4, 3, fake, 4, fake, 2, 7) == -6
+    assert lib.cup_set_winograd(-1, 2048) == -1
+    assert lib.cup_set_winograd(9, 2048) == -1
+    assert lib.cup_set_winograd(1, 64) == -2
+    assert lib.cup_set_winograd(0, 2048) == 0

@@ -228,3 +228,81 @@ def test_inplace_mm_vs_oracle(cup_lib, m, n, p, rank):
     cup_lib.cup_inplace_mm(dA, dB, p)
     assert np.array_equal(host(dB), ref), "B <- A B"
     assert np.array_equal(host(dA), A), "A must be restored"
+
+
+# --------------------------------------------------- Strassen-Winograd
+
+WINO_SHAPES = [(300, 300, 300), (257, 390, 520), (640, 384, 1000), (129, 129, 129), (1024, 512, 768)]
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("form,p,dtype", [("fp64", 65521, "int64"), ("fp64", 8388593, "int64"),
+                                          ("fp64", 33554393, "int64"), ("fp64", 2, "int64"),
+                                          ("i8limb", 65521, "int64"), ("i8", 127, "int8")])
+def test_ffgemm_winograd_vs_oracle(cup_lib, monkeypatch, levels, form, p, dtype):
+    """Seven-product products (one and two levels, with ragged peels) equal
+    the oracle's product bit for bit, in every form; products small enough
+    for the packed INT8 kernel are forced onto it too."""
+    monkeypatch.setenv("CUP_I8_MIN_WORK", "1e6")
+    tdt = torch.int64 if dtype == "int64" else torch.int8
+    cup_lib.cup_set_form(form)
+    cup_lib.cup_set_winograd(levels, 128)
+    try:
+        for M, N, K in WINO_SHAPES:
+            rng = np.random.default_rng(M + 3 * N + 7 * K + p % 1000)
+            A = rng.integers(0, p, size=(M, K), dtype=np.int64)
+            B = rng.integers(0, p, size=(K, N), dtype=np.int64)
+            C = rng.integers(0, p, size=(M, N), dtype=np.int64)
+            for alpha in (-1, 1):
+                dC = dev(C, tdt)
+                cup_lib.cup_ffgemm(dC, dev(A, tdt), dev(B, tdt), p, alpha)
+                ref = oracle.mm(C, A, B, p, alpha)
+                assert np.array_equal(host(dC), ref), (M, N, K, alpha)
+    finally:
+        cup_lib.cup_set_winograd(0, 2048)
+        cup_lib.cup_set_form("auto")
+
+
+def test_ffgemm_winograd_worst_magnitude(cup_lib):
+    """Operands at p - 1 and at the centring threshold through two levels."""
+    cup_lib.cup_set_form("fp64")
+    cup_lib.cup_set_winograd(2, 128)
+    try:
+        for p in (65521, 33554393):
+            h = p // 2
+            for va, vb in [(p - 1, p - 1), (h, h + 1)]:
+                A = np.full((520, 600), va, dtype=np.int64)
+                B = np.full((600, 530), vb, dtype=np.int64)
+                C = np.full((520, 530), p - 1, dtype=np.int64)
+                dC = dev(C)
+                cup_lib.cup_ffgemm(dC, dev(A), dev(B), p, -1)
+                assert np.array_equal(host(dC), oracle.mm(C, A, B, p, -1))
+    finally:
+        cup_lib.cup_set_winograd(0, 2048)
+        cup_lib.cup_set_form("auto")
+
+
+@pytest.mark.parametrize("form", ["fp64", "i8limb"])
+def test_cup_rref_inverse_winograd(cup_lib, form):
+    """CUP, the reduced echelon form and the inverse with every large enough
+    product (Schur updates, triangular solves and products) split."""
+    p = 65521
+    cup_lib.cup_set_form(form)
+    cup_lib.cup_set_winograd(2, 128)
+    try:
+        A = structured(1100, 1000, p, 21, rank=800)
+        d = dev(A)
+        r, P, Q = cup_lib.cup_factor(d, p)
+        ref = oracle.cup(A, p)
+        assert r == ref[1] and np.array_equal(host(d), ref[0])
+        assert np.array_equal(host(P), ref[2]) and np.array_equal(host(Q), ref[3])
+        d = dev(A)
+        cup_lib.cup_rref_inplace(d, p)
+        assert np.array_equal(host(d), oracle.rref_packed(A, p)[0])
+        B = nonsingular(700, p, seed=5)
+        d = dev(B)
+        ok, r = cup_lib.cup_inverse_inplace(d, p)
+        assert ok and np.array_equal(host(d), oracle.inverse(B, p))
+    finally:
+        cup_lib.cup_set_winograd(0, 2048)
+        cup_lib.cup_set_form("auto")
