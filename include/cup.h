@@ -159,21 +159,28 @@ int cup_inverse_inplace_i8(int64_t n, int8_t *A, int64_t lda, int64_t p, int64_t
 /*
  * Batched CUP of independent matrices, each with its own prime
  * (Algorithm 6 per matrix; a multi-modular workload).  One GPU workgroup
- * factors one matrix, largest matrices first (batches of up to 32768 are
- * ordered by m n min(m,n)); each result is the one cup_factor gives.
+ * factors one matrix; one persistent kernel per width class (n <= 128,
+ * n <= 256, n <= 512) keeps as many workgroups as fit on the GPU, each
+ * taking the class's matrices largest first (batches of up to 32768 are
+ * ordered by m n min(m, n)) from a work counter; each result is the one
+ * cup_factor gives.  Matrices with n > 512 are factored afterwards, one by
+ * one, by the recursive single-matrix path on the same stream.
  *   batch          : number of matrices (>= 0)
- *   m, n, lda, p   : device int64 arrays of length batch; n[i] <= 512
+ *   m, n, lda, p   : device int64 arrays of length batch
  *   A              : device array of batch device pointers (int64 matrices)
  *   rank           : device int64 array of length batch
  *   P, Q           : device arrays of batch device pointers (each P[i] of
  *                    length n[i], Q[i] of length m[i]); P or Q may be NULL
  *   info           : device int32 array; info[i] receives matrix i's status
- *                    with the argument codes of cup_factor (-1 m, -2 n or
- *                    n > 512, -3 A, -4 lda, -5 p); rank[i] is 0 on error
+ *                    with the argument codes of cup_factor (-1 m, -2 n,
+ *                    -3 A, -4 lda, -5 p); rank[i] is 0 on error
  * Returns 0 when the batch was queued (per-matrix status in info), or a
  * negative code for an invalid batch-level argument (-1 batch, -2 m, -3 n,
  * -4 A, -5 lda, -6 p, -7 rank, -10 info; -2000 workspace allocation).  The
- * call is asynchronous on the stream: outputs are on the device only.
+ * column counts are copied to the host on the stream ahead of the kernels
+ * (the call waits for that copy): without a matrix wider than 512 the call
+ * is asynchronous on the stream (outputs on the device only); with one, it
+ * returns after those matrices are factored.
  */
 int cup_factor_batched(int64_t batch, const int64_t *m, const int64_t *n, int64_t *const *A,
                        const int64_t *lda, const int64_t *p, int64_t *rank, int64_t *const *P,
@@ -269,11 +276,15 @@ int cup_inplace_mm(int64_t m, int64_t n, int64_t *A, int64_t lda, int64_t *B, in
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
  * same arguments, launches and results as cup_factor_batched, but the
  * library's scratch (the processing order of the batch, 4 bytes per matrix)
- * lives in a static device array of CUP_NOALLOC_BATCH_MAX entries (128 KiB,
- * held on each GPU the library runs on until the process ends), so the call
+ * lives in a static device array of CUP_NOALLOC_BATCH_MAX + 64 entries
+ * (128 KiB and 256 bytes, held on each GPU the library runs on until the
+ * process ends, with the kernels' work counters), so the call
  * allocates nothing: no hipMalloc, hipFree or allocating library routine.
  * The caller passes every input and output.  A batch above
  * CUP_NOALLOC_BATCH_MAX returns CUP_ERR_NOALLOC_LIMIT before any work.
+ * Nothing is read back and nothing synchronises, so the call can be
+ * captured in a HIP graph; matrices with n > 512 are not routed to the
+ * single-matrix path here (that needs the host): they get info -2.
  * Every call on one GPU shares that GPU's array: calls that overlap on one
  * GPU (on different streams, or from different threads without ordering)
  * race on it.  Asynchronous on the stream, like cup_factor_batched.
@@ -335,7 +346,7 @@ int cup_profile_read(double *stats);
  *   + 4 * max(k, 1024)                        row rank profile (reduced forms)
  *   + 2 * (m + n + 256) * (k + 64)            INT8 forms only: packed limb
  *                                             operands of one product
- *   + 4 * max(batch, 4096)                    batched order (batch <= 32768)
+ *   + 4 * max(batch + 64, 4096)               batched work counters and order
  * The two block caches are the library's departure from Definition 1
  * (Section 3.1: O(1) extra field elements outside matrix multiplication):
  * O(k) blocks of 64 x 64, i.e. 64 k field elements against the m n of A.

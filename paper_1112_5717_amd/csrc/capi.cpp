@@ -31,8 +31,10 @@ struct Global {
     unsigned mail_seq = 0;
     int* d_list = nullptr;
     size_t list_cap = 0;  // ints
-    int* d_order = nullptr;  // processing order of the batched entry point
+    int* d_order = nullptr;  // work counters and processing order of the batched entry point
     size_t order_cap = 0;    // ints
+    int64_t* h_bn = nullptr;  // pinned copy of a batch's column counts
+    size_t bn_cap = 0;        // entries
     size_t bytes = 0;
     Profiler prof;
     Workspace ws;
@@ -40,14 +42,15 @@ struct Global {
 
 constexpr int64_t kOrderMax = 32768;  // largest batch that is sorted by cost
 
-// Scratch of the allocation-free batched entry point: the processing order
-// of up to CUP_NOALLOC_BATCH_MAX matrices, one copy per GPU in the device
-// image of this file (128 KiB), held until the process ends.  Host code never
+// Scratch of the allocation-free batched entry point: the work counters of
+// the batched kernels and the processing order of up to
+// CUP_NOALLOC_BATCH_MAX matrices, one copy per GPU in the device image of
+// this file (128 KiB and 256 bytes), held until the process ends.  Host code never
 // passes the array's name to a kernel (in host code it is a host-side
 // stand-in); it passes the device address that hipGetSymbolAddress returns
 // for the current device, resolved once per device.
 static_assert(CUP_NOALLOC_BATCH_MAX <= kOrderMax, "the batched order covers the no-alloc limit");
-static __device__ __align__(256) int scratch[CUP_NOALLOC_BATCH_MAX];
+static __device__ __align__(256) int scratch[kBatchCounters + CUP_NOALLOC_BATCH_MAX];
 
 constexpr int kMaxDevices = 64;
 void* g_scratch_ptr[kMaxDevices] = {};
@@ -567,6 +570,84 @@ int inplace_mm_impl(int64_t m, int64_t n, int64_t* A, int64_t lda, int64_t* B, i
     });
 }
 
+// Batched entry point, wide matrices: the column counts are copied to pinned
+// host memory on the stream ahead of the batched kernels (the host waits for
+// that copy only, not for the kernels); matrices wider than the kernels take
+// (n > batched_max_n(), reported by them with info -2 and left untouched)
+// are then factored one by one by the recursive single-matrix path
+// (Algorithm 6) on the same stream, after the kernels, and their rank, P, Q
+// and info are written.  Without such matrices the call stays asynchronous.
+struct WideCheck {
+    hipEvent_t ev = nullptr;
+    const int64_t* hn = nullptr;
+};
+
+WideCheck queue_wide_check(Global& g, int64_t batch, const int64_t* n)
+{
+    if ((size_t)batch > g.bn_cap) {
+        if (g.h_bn) {
+            CUP_HIP(hipStreamSynchronize(g.stream));
+            (void)hipHostFree(g.h_bn);
+            g.h_bn = nullptr;
+            g.bn_cap = 0;
+        }
+        if (host_malloc((void**)&g.h_bn, sizeof(int64_t) * (size_t)batch, hipHostMallocDefault) != hipSuccess) {
+            g.h_bn = nullptr;
+            throw CupError{CUP_ERR_ALLOC};
+        }
+        g.bn_cap = (size_t)batch;
+    }
+    static hipEvent_t ev = nullptr;
+    if (!ev) CUP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    CUP_HIP(hipMemcpyAsync(g.h_bn, n, sizeof(int64_t) * (size_t)batch, hipMemcpyDeviceToHost, g.stream));
+    CUP_HIP(hipEventRecord(ev, g.stream));
+    return WideCheck{ev, g.h_bn};
+}
+
+template <typename V>
+std::vector<V> fetch_vec(Global& g, const V* d, int64_t count)
+{
+    std::vector<V> h((size_t)count);
+    CUP_HIP(hipMemcpyAsync(h.data(), d, sizeof(V) * (size_t)count, hipMemcpyDeviceToHost, g.stream));
+    CUP_HIP(hipStreamSynchronize(g.stream));
+    return h;
+}
+
+void route_wide(Global& g, const WideCheck& wc, int64_t batch, const int64_t* m, const int64_t* n,
+                int64_t* const* A, const int64_t* lda, const int64_t* p, int64_t* rank, int64_t* const* P,
+                int64_t* const* Q, int32_t* info)
+{
+    CUP_HIP(hipEventSynchronize(wc.ev));
+    std::vector<int64_t> wide;
+    for (int64_t i = 0; i < batch; ++i)
+        if (wc.hn[i] > batched_max_n()) wide.push_back(i);
+    if (wide.empty()) return;
+    (void)n;
+    const std::vector<int64_t> hm = fetch_vec(g, m, batch), hl = fetch_vec(g, lda, batch),
+                               hp = fetch_vec(g, p, batch);
+    const std::vector<int64_t*> hA = fetch_vec(g, A, batch);
+    const std::vector<int64_t*> hP = P ? fetch_vec(g, P, batch) : std::vector<int64_t*>((size_t)batch, nullptr);
+    const std::vector<int64_t*> hQ = Q ? fetch_vec(g, Q, batch) : std::vector<int64_t*>((size_t)batch, nullptr);
+    for (int64_t i : wide) {
+        const int64_t mi = hm[(size_t)i], ni = wc.hn[i];
+        int64_t r = 0;
+        int32_t code = validate<int64_t>(mi, ni, hA[(size_t)i], hl[(size_t)i], hp[(size_t)i], &r);
+        if (code == -6) code = 0;  // (no rank pointer in the single-matrix sense)
+        int form = code ? 0 : resolve_form(g.form, hp[(size_t)i], false);
+        if (!code && form < 0) code = -5;
+        if (!code) {
+            Ctx c = make_ctx(g, hp[(size_t)i], form);
+            std::vector<int64_t> Pl, Ql;
+            r = run_cup<int64_t>(c, hA[(size_t)i], hl[(size_t)i], (int)mi, (int)ni, Pl, Ql);
+            write_perm(c, hP[(size_t)i], Pl, ni);
+            write_perm(c, hQ[(size_t)i], Ql, mi);
+        }
+        CUP_HIP(hipMemcpyAsync(rank + i, &r, sizeof(int64_t), hipMemcpyHostToDevice, g.stream));
+        CUP_HIP(hipMemcpyAsync(info + i, &code, sizeof(int32_t), hipMemcpyHostToDevice, g.stream));
+        CUP_HIP(hipStreamSynchronize(g.stream));
+    }
+}
+
 }  // namespace
 }  // namespace cup
 
@@ -680,31 +761,32 @@ int cup_factor_batched(int64_t batch, const int64_t* m, const int64_t* n, int64_
     Global& g = G();
     std::lock_guard<std::mutex> lk(g.mu);
     try {
-        // Largest matrices first (a counting sort on the device, quadratic in
-        // the batch, so only up to kOrderMax matrices); then one workgroup
-        // per matrix.  Nothing is read back: the call stays asynchronous.
-        int* order = nullptr;
-        if (batch <= kOrderMax) {
-            if ((size_t)batch > g.order_cap) {
-                if (g.d_order) {
-                    CUP_HIP(hipDeviceSynchronize());
-                    (void)hipFree(g.d_order);
-                    g.bytes -= sizeof(int) * g.order_cap;
-                    g.d_order = nullptr;
-                    g.order_cap = 0;
-                }
-                size_t cap = std::max<size_t>((size_t)batch, 4096);
-                if (dev_malloc((void**)&g.d_order, sizeof(int) * cap) != hipSuccess)
-                    throw CupError{CUP_ERR_ALLOC};
-                g.order_cap = cap;
-                g.bytes += sizeof(int) * cap;
+        // Largest matrices first within each width class (a counting sort on
+        // the device, quadratic in the batch, so only up to kOrderMax
+        // matrices); then one persistent kernel per width class.
+        const bool ordered = batch <= kOrderMax;
+        const size_t need = batched_scratch_ints((int)batch, ordered);
+        if (need > g.order_cap) {
+            if (g.d_order) {
+                CUP_HIP(hipDeviceSynchronize());
+                (void)hipFree(g.d_order);
+                g.bytes -= sizeof(int) * g.order_cap;
+                g.d_order = nullptr;
+                g.order_cap = 0;
             }
-            order = g.d_order;
+            size_t cap = std::max<size_t>(need, 4096);
+            if (dev_malloc((void**)&g.d_order, sizeof(int) * cap) != hipSuccess) throw CupError{CUP_ERR_ALLOC};
+            g.order_cap = cap;
+            g.bytes += sizeof(int) * cap;
         }
-        launch_batched_cup(g.stream, (int)batch, m, n, A, lda, p, rank, P, Q, info, order);
+        const WideCheck wc = queue_wide_check(g, batch, n);
+        launch_batched_cup(g.stream, (int)batch, m, n, A, lda, p, rank, P, Q, info, g.d_order, ordered);
+        route_wide(g, wc, batch, m, n, A, lda, p, rank, P, Q, info);
         return CUP_OK;
     } catch (const CupError& e) {
         return e.code;
+    } catch (const std::bad_alloc&) {
+        return CUP_ERR_ALLOC;
     }
 }
 
@@ -764,10 +846,11 @@ int cup_factor_batched_noalloc(int64_t batch, const int64_t* m, const int64_t* n
     Global& g = G();
     std::lock_guard<std::mutex> lk(g.mu);
     try {
-        // the same launches as cup_factor_batched, with the processing order
-        // in this device's static scratch array instead of library memory
-        int* order = static_cast<int*>(noalloc_scratch());
-        launch_batched_cup(g.stream, (int)batch, m, n, A, lda, p, rank, P, Q, info, order);
+        // the same launches as cup_factor_batched, with the work counters and
+        // the processing order in this device's static scratch array instead
+        // of library memory (the order kernel clears the counters)
+        int* sc = static_cast<int*>(noalloc_scratch());
+        launch_batched_cup(g.stream, (int)batch, m, n, A, lda, p, rank, P, Q, info, sc, true);
         return CUP_OK;
     } catch (const CupError& e) {
         return e.code;
@@ -851,6 +934,9 @@ int cup_finalize(void)
     if (g.h_small) (void)hipHostFree(g.h_small);
     if (g.d_list) (void)hipFree(g.d_list);
     if (g.d_order) (void)hipFree(g.d_order);
+    if (g.h_bn) (void)hipHostFree(g.h_bn);
+    g.h_bn = nullptr;
+    g.bn_cap = 0;
     if (g.ws.tri) (void)hipFree(g.ws.tri);
     if (g.ws.uc) (void)hipFree(g.ws.uc);
     if (g.ws.pk) (void)hipFree(g.ws.pk);

@@ -275,11 +275,16 @@ void launch_copy2d(hipStream_t s, const T* src, int64_t lds, T* dst, int64_t ldd
                    int cols);
 
 // Batched CUP (one workgroup per matrix, n <= batched_max_n()), all
-// descriptors on the device; `order` (batch ints) receives the processing
-// order, or is null to process the matrices in index order.
+// descriptors on the device.  `scratch` holds batched_scratch_ints(batch,
+// ordered) ints: the classes' work counters, then (when `ordered`) the
+// processing order (largest first within each width class).  The launches
+// read and write nothing else of the library's, allocate nothing and never
+// synchronise, so the sequence can be captured in a graph.
+constexpr int kBatchCounters = 64;
 int batched_max_n();
+size_t batched_scratch_ints(int batch, bool ordered);
 void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_t* n,
                         int64_t* const* A, const int64_t* lda, const int64_t* p, int64_t* rank,
-                        int64_t* const* P, int64_t* const* Q, int32_t* info, int* order);
+                        int64_t* const* P, int64_t* const* Q, int32_t* info, int* scratch, bool ordered);
 
 }  // namespace cup

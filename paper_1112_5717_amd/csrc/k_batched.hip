@@ -41,6 +41,7 @@
 // loops run over every register of the width without per-register or
 // per-row branches: positions past n and rows past m hold zeros, which the
 // updates leave zero.
+#include <algorithm>
 #include <type_traits>
 
 #include "modarith.h"
@@ -114,35 +115,48 @@ struct BatchDesc {
     const int* order;  // processing order (largest first), or null
 };
 
-// BQ position registers per lane (n <= 64 BQ).  The kernel takes the
-// matrices with nlo < n <= nhi and leaves the others to its siblings.
+// The workgroup's shared state for one matrix (BQ position registers per
+// lane: n <= 64 BQ).
 template <int BQ>
-__global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch, int64_t nlo,
-                                                         int64_t nhi)
+struct BatchShared {
+    static constexpr int NP = 64 * BQ;
+    int perm[NP];               // position -> original column
+    double urow[2][NP];         // published U rows (zeros up to the pivot)
+    int s_j[2];
+    int s_rowt[BR];             // pivots found before each block row
+    int s_rowpiv[BR];           // 1 if the block row holds a pivot
+    int s_composite;
+    int s_nz[BR];               // block row has a nonzero residual
+    double ush[2][CH][NP];      // staged U rows (zeros up to the diagonal)
+    int ublk[BR][NP];           // U rows found in the current block
+    int s_tj[BR];               // their transpositions t <-> s_tj
+    int s_ti[BR];               // and their rows (entries of Q)
+};
+
+// CUP of matrix idx by the whole workgroup (every thread calls it with the
+// same idx; it returns on every thread together).
+template <int BQ>
+__device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchShared<BQ>& sh)
 {
     constexpr int NP = 64 * BQ;        // positions
     constexpr int SPT = CH * NP / BT;  // staged values per thread
     static_assert(BT % NP == 0 && CH % (BT / NP) == 0, "threads tile the staged chunk");
-    __shared__ int perm[NP];               // position -> original column
-    __shared__ double urow[2][NP];         // published U rows (zeros up to the pivot)
-    __shared__ int s_j[2];
-    __shared__ int s_rowt[BR];             // pivots found before each block row
-    __shared__ int s_rowpiv[BR];           // 1 if the block row holds a pivot
-    __shared__ int s_composite;
-    __shared__ int s_nz[BR];               // block row has a nonzero residual
-    __shared__ double ush[2][CH][NP];      // staged U rows (zeros up to the diagonal)
-    __shared__ int ublk[BR][NP];           // U rows found in the current block
-    __shared__ int s_tj[BR];               // their transpositions t <-> s_tj
-    __shared__ int s_ti[BR];               // and their rows (entries of Q)
+    auto& perm = sh.perm;
+    auto& urow = sh.urow;
+    auto& s_j = sh.s_j;
+    auto& s_rowt = sh.s_rowt;
+    auto& s_rowpiv = sh.s_rowpiv;
+    auto& s_composite = sh.s_composite;
+    auto& s_nz = sh.s_nz;
+    auto& ush = sh.ush;
+    auto& ublk = sh.ublk;
+    auto& s_tj = sh.s_tj;
+    auto& s_ti = sh.s_ti;
 
-    const int b = blockIdx.x;
-    if (b >= batch) return;
-    const int idx = g.order ? g.order[b] : b;
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     const int64_t N64 = g.n[idx];
-    if (N64 <= nlo || N64 > nhi) return;
     const int64_t M64 = g.m[idx], ld = g.lda[idx], p64 = g.p[idx];
     int64_t* const A = g.A[idx];
     int64_t* const Pv = g.P ? g.P[idx] : nullptr;
@@ -468,58 +482,142 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch,
     }
 }
 
-// order[k] = index of the matrix with the k-th largest cost m n min(m, n)
-// (ties by index), by counting: thread i counts the matrices that precede it.
+// Width class of a matrix with n columns: 0 (n <= 128), 1 (n <= 256), 2 (the
+// rest, including n > 512 and invalid n, which its kernel reports).
+__device__ __forceinline__ int width_class(int64_t n) { return n <= 128 ? 0 : (n <= 256 ? 1 : 2); }
+
+__device__ __forceinline__ double batch_cost(const int64_t* m, const int64_t* n, int e)
+{
+    const double a = (double)m[e], c = (double)n[e];
+    return (a > 0.0 && c > 0.0) ? a * c * (a < c ? a : c) : 0.0;
+}
+
+// order[k]: the matrices by width class, and within a class by decreasing
+// cost m n min(m, n) (ties by index), by counting: thread i counts the
+// matrices that precede it.  Also zeroes the classes' work counters (the
+// persistent kernels that read them run after this kernel).
 __global__ __launch_bounds__(256) void batched_order_kernel(const int64_t* m, const int64_t* n,
-                                                            int batch, int* order)
+                                                            int batch, int* order, int* counters)
 {
     __shared__ double cost[256];
+    __shared__ int cls[256];
     const int i = blockIdx.x * 256 + threadIdx.x;
-    auto cost_of = [&](int e) {
-        const double a = (double)m[e], c = (double)n[e];
-        return (a > 0.0 && c > 0.0) ? a * c * (a < c ? a : c) : 0.0;
-    };
-    const double mine = (i < batch) ? cost_of(i) : 0.0;
+    if (i == 0)
+        for (int c = 0; c < 3; ++c) counters[c] = 0;
+    const double mine = (i < batch) ? batch_cost(m, n, i) : 0.0;
+    const int mc = (i < batch) ? width_class(n[i]) : 0;
     int pos = 0;
     for (int j0 = 0; j0 < batch; j0 += 256) {
         __syncthreads();
         const int e = j0 + threadIdx.x;
-        cost[threadIdx.x] = (e < batch) ? cost_of(e) : -1.0;
+        cost[threadIdx.x] = (e < batch) ? batch_cost(m, n, e) : -1.0;
+        cls[threadIdx.x] = (e < batch) ? width_class(n[e]) : 3;
         __syncthreads();
         const int lim = min(256, batch - j0);
         for (int jj = 0; jj < lim; ++jj) {
             const double o = cost[jj];
-            pos += (o > mine) || (o == mine && j0 + jj < i);
+            const int oc = cls[jj];
+            pos += (oc < mc) || (oc == mc && ((o > mine) || (o == mine && j0 + jj < i)));
         }
     }
     if (i < batch) order[pos] = i;
+}
+
+__global__ void batched_reset_kernel(int* counters)
+{
+    if (threadIdx.x < 3) counters[threadIdx.x] = 0;
+}
+
+// One persistent kernel per width class: each workgroup finds its class's
+// range of the order (or, without an order, walks every index), then takes
+// matrices one at a time from the class's counter until the class is done.
+template <int BQ>
+__global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch, int cls, int* counters)
+{
+    __shared__ BatchShared<BQ> sh;
+    __shared__ int s_base, s_count, s_next;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_base = 0;
+        s_count = 0;
+    }
+    __syncthreads();
+    if (g.order) {
+        int below = 0, mine = 0;
+        for (int e = tid; e < batch; e += BT) {
+            const int c = width_class(g.n[e]);
+            below += c < cls;
+            mine += c == cls;
+        }
+        atomicAdd(&s_base, below);
+        atomicAdd(&s_count, mine);
+    }
+    for (;;) {
+        __syncthreads();  // the previous matrix is done with the shared state
+        if (tid == 0) s_next = atomicAdd(counters + cls, 1);
+        __syncthreads();
+        const int k = s_next;
+        int idx;
+        if (g.order) {
+            if (k >= s_count) break;
+            idx = g.order[s_base + k];
+        } else {
+            if (k >= batch) break;
+            idx = k;
+            if (width_class(g.n[idx]) != cls) continue;
+        }
+        factor_one<BQ>(g, idx, sh);
+    }
+}
+
+// Workgroups of each class's persistent kernel: the number that fit on the
+// GPU at once (CUs x resident workgroups per CU).
+int persistent_grid(int bq)
+{
+    static int grid[3] = {0, 0, 0};
+    const int c = bq == 2 ? 0 : (bq == 4 ? 1 : 2);
+    if (!grid[c]) {
+        int dev = 0, cus = 0, per = 0;
+        CUP_HIP(hipGetDevice(&dev));
+        CUP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        if (bq == 2)
+            CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cup_kernel<2>, BT, 0));
+        else if (bq == 4)
+            CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cup_kernel<4>, BT, 0));
+        else
+            CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cup_kernel<BQMAX>, BT, 0));
+        grid[c] = std::max(1, cus) * std::max(1, per);
+    }
+    return grid[c];
 }
 
 }  // namespace
 
 int batched_max_n() { return BQMAX * 64; }
 
+size_t batched_scratch_ints(int batch, bool ordered) { return kBatchCounters + (ordered ? (size_t)batch : 0); }
+
 void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_t* n,
                         int64_t* const* A, const int64_t* lda, const int64_t* p, int64_t* rank,
-                        int64_t* const* P, int64_t* const* Q, int32_t* info, int* order)
+                        int64_t* const* P, int64_t* const* Q, int32_t* info, int* scratch, bool ordered)
 {
     if (batch <= 0) return;
-    if (order) {
-        hipLaunchKernelGGL(batched_order_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, m, n,
-                           batch, order);
-        CUP_HIP(hipGetLastError());
-    }
-    // three widths: n <= 128, n <= 256, and the rest (n <= 512; wider or
-    // invalid descriptors are rejected there)
+    int* counters = scratch;
+    int* order = ordered ? scratch + kBatchCounters : nullptr;
+    if (order)
+        hipLaunchKernelGGL(batched_order_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, m, n, batch,
+                           order, counters);
+    else
+        hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, s, counters);
+    CUP_HIP(hipGetLastError());
+    // widest class first, so that the largest matrices start first
     BatchDesc g{m, n, A, lda, p, rank, P, Q, info, order};
-    hipLaunchKernelGGL(batched_cup_kernel<2>, dim3(batch), dim3(BT), 0, s, g, batch, INT64_MIN,
-                       (int64_t)128);
+    hipLaunchKernelGGL(batched_cup_kernel<BQMAX>, dim3(persistent_grid(BQMAX)), dim3(BT), 0, s, g, batch, 2,
+                       counters);
     CUP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(batched_cup_kernel<4>, dim3(batch), dim3(BT), 0, s, g, batch, (int64_t)128,
-                       (int64_t)256);
+    hipLaunchKernelGGL(batched_cup_kernel<4>, dim3(persistent_grid(4)), dim3(BT), 0, s, g, batch, 1, counters);
     CUP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(batched_cup_kernel<BQMAX>, dim3(batch), dim3(BT), 0, s, g, batch,
-                       (int64_t)256, INT64_MAX);
+    hipLaunchKernelGGL(batched_cup_kernel<2>, dim3(persistent_grid(2)), dim3(BT), 0, s, g, batch, 0, counters);
     CUP_HIP(hipGetLastError());
 }
 

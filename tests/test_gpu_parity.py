@@ -322,20 +322,77 @@ def test_batched_strided_and_no_pq(cup_lib):
 
 
 def test_batched_argument_errors(cup_lib):
-    """Per-matrix codes: n > 512 -> -2, composite or out-of-range p -> -5;
+    """Per-matrix codes: composite or out-of-range p -> -5; n > 512 is
+    routed to the single-matrix path by cup_factor_batched (a zero 3 x 513
+    matrix: rank 0) and refused with -2 by the allocation-free variant;
     empty matrices give rank 0 and identity P, Q; the others still run."""
     A_ok = inputs.low_rank(40, 30, 20, 65521, seed=31)
-    mats = [dev(A_ok), dev(np.zeros((3, 513), np.int64)), dev(A_ok), dev(A_ok),
-            dev(np.zeros((0, 5), np.int64)), dev(np.zeros((4, 0), np.int64))]
-    ps = [65521, 65521, 65519 * 3, 1 << 26, 65521, 65521]
-    rank, info, Ps, Qs = cup_lib.cup_factor_batched(mats, ps)
-    info, rank = host(info), host(rank)
-    assert info.tolist() == [0, -2, -5, -5, 0, 0]
-    ref = oracle.cup(A_ok, 65521)
-    assert rank[0] == ref[1] and np.array_equal(host(mats[0]), ref[0])
-    assert rank[4] == 0 and rank[5] == 0
-    assert np.array_equal(host(Ps[4]), np.arange(5)) and np.array_equal(host(Qs[5]), np.arange(4))
-    assert np.array_equal(host(mats[2]), A_ok) and np.array_equal(host(mats[3]), A_ok)
+    for name, wide_code in (("cup_factor_batched", 0), ("cup_factor_batched_noalloc", -2)):
+        mats = [dev(A_ok), dev(np.zeros((3, 513), np.int64)), dev(A_ok), dev(A_ok),
+                dev(np.zeros((0, 5), np.int64)), dev(np.zeros((4, 0), np.int64))]
+        ps = [65521, 65521, 65519 * 3, 1 << 26, 65521, 65521]
+        rank, info, Ps, Qs = cup_lib.cup_factor_batched(mats, ps, name=name)
+        torch.cuda.synchronize()
+        info, rank = host(info), host(rank)
+        assert info.tolist() == [0, wide_code, -5, -5, 0, 0], name
+        assert rank[1] == 0
+        if wide_code == 0:
+            assert np.array_equal(host(Ps[1]), np.arange(513)) and np.array_equal(host(Qs[1]), np.arange(3))
+        ref = oracle.cup(A_ok, 65521)
+        assert rank[0] == ref[1] and np.array_equal(host(mats[0]), ref[0])
+        assert rank[4] == 0 and rank[5] == 0
+        assert np.array_equal(host(Ps[4]), np.arange(5)) and np.array_equal(host(Qs[5]), np.arange(4))
+        assert np.array_equal(host(mats[2]), A_ok) and np.array_equal(host(mats[3]), A_ok)
+
+
+def test_batched_wide_matrices_routed(cup_lib):
+    """Matrices wider than the batched kernels (n > 512) among ordinary ones:
+    cup_factor_batched factors them by the recursive path; every result
+    equals the oracle's."""
+    primes = inputs.largest_primes_below(2 ** 23, 32)
+    cases = [(700, 600, 500, 65521), (100, 90, 60, primes[0]), (64, 1000, 64, primes[1]),
+             (300, 513, 300, 8388593), (40, 30, 20, primes[2]), (513, 900, 400, 101)]
+    hosts = [inputs.low_rank(mm, nn, rr, p, seed=mm + nn) for mm, nn, rr, p in cases]
+    _check_batched(cup_lib, hosts, [c[3] for c in cases])
+
+
+def test_batched_graph_replay(cup_lib):
+    """The allocation-free batched call captured in a HIP graph (through
+    torch's graph capture) and replayed three times, with eager library work
+    between the replays: every replay equals the eager result."""
+    primes = inputs.largest_primes_below(2 ** 23, 32)
+    m, n, r = inputs.batch_specs(60, 16, 512, seed=77)
+    ps = [primes[i % 32] for i in range(60)]
+    fb = cup_lib.FlatBatch(m, n, ps)
+    src = torch.empty(fb.size, dtype=torch.int64, device="cuda")
+    for i in range(60):
+        A = inputs.batch_matrix(i, m[i], n[i], r[i], ps[i], seed=77)
+        o = int(fb.offsets[i])
+        src[o:o + A.size].copy_(torch.from_numpy(A.reshape(-1)))
+    work = src.clone()
+    ptrs = fb.pointers(work)
+    fb.factor(ptrs, name="cup_factor_batched_noalloc")  # eager reference (and first-use set-up)
+    torch.cuda.synchronize()
+    ref = (work.clone(), fb.rank.clone(), fb.P.clone(), fb.Q.clone(), fb.info.clone())
+    assert not ref[4].any()
+    graph = torch.cuda.CUDAGraph()
+    work.copy_(src)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        fb.factor(ptrs, name="cup_factor_batched_noalloc")
+    other = torch.from_numpy(inputs.uniform((200, 150), 65521, seed=5)).cuda()
+    for rep in range(3):
+        work.copy_(src)
+        fb.rank.zero_()
+        fb.P.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(work, ref[0]), f"replay {rep}: matrices differ"
+        assert torch.equal(fb.rank, ref[1]) and torch.equal(fb.P, ref[2]) and torch.equal(fb.Q, ref[3])
+        assert not fb.info.any()
+        cup_lib.cup_factor(other.clone(), 65521)  # eager work between replays
+        torch.cuda.synchronize()
 
 
 # --------------------------------------------------------------- INT8 forms
