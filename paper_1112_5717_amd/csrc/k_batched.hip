@@ -42,7 +42,11 @@
 // per-row branches: positions past n and rows past m hold zeros, which the
 // updates leave zero.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
+
+#include "batched_tune.h"
 
 #include "modarith.h"
 
@@ -570,25 +574,69 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch,
     }
 }
 
-// Workgroups of each class's persistent kernel: the number that fit on the
-// GPU at once (CUs x resident workgroups per CU).
-int persistent_grid(int bq)
+// Workgroups of each class's persistent kernel: CUs x workgroups per CU,
+// the latter from the tuning table (tune_batched.py measures every choice
+// up to the resident maximum on the multi-modular workload and writes
+// batched_tune.h), capped by what the occupancy calculator allows.  The
+// environment variable CUP_BATCHED_TUNE="w0,w1,w2,concurrent" overrides the
+// table (the tuner's measurements use it).
+struct BatchTune {
+    int per_cu[3];
+    int concurrent;
+};
+
+BatchTune batch_tune()
 {
-    static int grid[3] = {0, 0, 0};
-    const int c = bq == 2 ? 0 : (bq == 4 ? 1 : 2);
-    if (!grid[c]) {
-        int dev = 0, cus = 0, per = 0;
+    BatchTune t{{kTuneWgPerCu[0], kTuneWgPerCu[1], kTuneWgPerCu[2]}, kTuneConcurrent};
+    if (const char* v = std::getenv("CUP_BATCHED_TUNE")) {
+        int a = 0, b = 0, c = 0, d = 0;
+        if (std::sscanf(v, "%d,%d,%d,%d", &a, &b, &c, &d) == 4) t = BatchTune{{a, b, c}, d};
+    }
+    return t;
+}
+
+int persistent_grid(int cls, const BatchTune& t)
+{
+    static int cus = 0, maxper[3] = {0, 0, 0};
+    if (!cus) {
+        int dev = 0;
         CUP_HIP(hipGetDevice(&dev));
         CUP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        if (bq == 2)
-            CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cup_kernel<2>, BT, 0));
-        else if (bq == 4)
-            CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cup_kernel<4>, BT, 0));
-        else
-            CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cup_kernel<BQMAX>, BT, 0));
-        grid[c] = std::max(1, cus) * std::max(1, per);
+        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[0], batched_cup_kernel<2>, BT, 0));
+        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[1], batched_cup_kernel<4>, BT, 0));
+        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[2], batched_cup_kernel<BQMAX>, BT, 0));
+        cus = std::max(1, cus);
     }
-    return grid[c];
+    const int per = std::max(1, std::min(t.per_cu[cls], std::max(1, maxper[cls])));
+    return cus * per;
+}
+
+// Side streams and events of the concurrent class launches (default
+// priority), created on first use and kept.
+struct ClassStreams {
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+};
+
+ClassStreams& class_streams()
+{
+    static ClassStreams cs;
+    if (!cs.fork) {
+        for (int k = 0; k < 2; ++k) {
+            CUP_HIP(hipStreamCreateWithFlags(&cs.side[k], hipStreamNonBlocking));
+            CUP_HIP(hipEventCreateWithFlags(&cs.join[k], hipEventDisableTiming));
+        }
+        CUP_HIP(hipEventCreateWithFlags(&cs.fork, hipEventDisableTiming));
+    }
+    return cs;
+}
+
+template <int BQ>
+void launch_class(hipStream_t s, const BatchDesc& g, int batch, int cls, int* counters, const BatchTune& t)
+{
+    hipLaunchKernelGGL(batched_cup_kernel<BQ>, dim3(persistent_grid(cls, t)), dim3(BT), 0, s, g, batch, cls,
+                       counters);
+    CUP_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -610,15 +658,28 @@ void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_
     else
         hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, s, counters);
     CUP_HIP(hipGetLastError());
-    // widest class first, so that the largest matrices start first
+    // widest class first, so that the largest matrices start first; with
+    // concurrent launches the narrower classes run on two side streams that
+    // join the stream again, and take the CUs the wide class leaves idle
     BatchDesc g{m, n, A, lda, p, rank, P, Q, info, order};
-    hipLaunchKernelGGL(batched_cup_kernel<BQMAX>, dim3(persistent_grid(BQMAX)), dim3(BT), 0, s, g, batch, 2,
-                       counters);
-    CUP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(batched_cup_kernel<4>, dim3(persistent_grid(4)), dim3(BT), 0, s, g, batch, 1, counters);
-    CUP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(batched_cup_kernel<2>, dim3(persistent_grid(2)), dim3(BT), 0, s, g, batch, 0, counters);
-    CUP_HIP(hipGetLastError());
+    const BatchTune t = batch_tune();
+    if (!t.concurrent) {
+        launch_class<BQMAX>(s, g, batch, 2, counters, t);
+        launch_class<4>(s, g, batch, 1, counters, t);
+        launch_class<2>(s, g, batch, 0, counters, t);
+        return;
+    }
+    ClassStreams& cs = class_streams();
+    CUP_HIP(hipEventRecord(cs.fork, s));
+    CUP_HIP(hipStreamWaitEvent(cs.side[0], cs.fork, 0));
+    CUP_HIP(hipStreamWaitEvent(cs.side[1], cs.fork, 0));
+    launch_class<BQMAX>(s, g, batch, 2, counters, t);
+    launch_class<4>(cs.side[0], g, batch, 1, counters, t);
+    launch_class<2>(cs.side[1], g, batch, 0, counters, t);
+    for (int k = 0; k < 2; ++k) {
+        CUP_HIP(hipEventRecord(cs.join[k], cs.side[k]));
+        CUP_HIP(hipStreamWaitEvent(s, cs.join[k], 0));
+    }
 }
 
 }  // namespace cup
