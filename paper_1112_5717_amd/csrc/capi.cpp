@@ -23,6 +23,7 @@ struct Global {
     int wino_min = 2048;     // smallest dimension split by it
     int* d_small = nullptr;
     int* h_small = nullptr;
+    bool sparse_ready = false;  // the sparse leaf kernel's barrier words in d_small are valid
     // Result words of the window kernel in mapped, coherent host memory (kept
     // until the process ends: GPU writes to it may still be in flight when a
     // call fails), their device address, and the last sequence number used.
@@ -110,6 +111,7 @@ void ensure_small(Global& g)
             g.d_small = nullptr;
             throw CupError{CUP_ERR_ALLOC};
         }
+        g.sparse_ready = false;
         g.bytes += sizeof(int) * kSmallInts;
     }
     if (!g.h_small) {
@@ -214,6 +216,7 @@ Ctx make_ctx(Global& g, int64_t p, int form)
     c.mail_h = g.h_mail;
     c.mail_d = g.d_mail;
     c.mail_seq = &g.mail_seq;
+    c.sparse_ready = &g.sparse_ready;
     c.log = env_flag("CUP_LOG") ? 1 : 0;
     if (const char* v = std::getenv("CUP_I8_MIN_WORK")) c.i8_min_work = std::atof(v);
     c.prof = &g.prof;

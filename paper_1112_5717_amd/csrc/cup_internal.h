@@ -167,6 +167,23 @@ void launch_row_scan(hipStream_t s, const T* A, int64_t lda, int i0, int b, int 
 constexpr int kMailScan = 2 + kLeafRows;
 constexpr int kMailWords = kMailScan + kLeafRows;
 
+// The rest of a rank-deficient leaf (see k_sparse.hip): rows [i0, b) from
+// position t0, one cooperative launch; ws holds sparse_ws_ints() device ints
+// and receives the pivot count at ws[kSparseCount], the pivot rows at
+// ws[kSparseRows + k] and positions at ws[kSparseCols + k], and posts them
+// to the host mailbox, tagged with seq: the count in mail[0], 0 in mail[1],
+// the positions in mail[2 + k] and the rows in mail[kMailScan + k] (nothing
+// is posted when a grid barrier has waited longer than spin_max polls; ws[2]
+// is then set).  The column exchanges t0 + k <-> position k are left to the
+// caller (applied in that order to the leaf's rows [0, b)).  The grid
+// barrier's words in ws carry over from launch to launch: `reset` zeroes
+// them (first use, or after a failure).
+constexpr int kSparseCount = 4, kSparseRows = 200, kSparseCols = 264;
+int sparse_ws_ints();
+template <typename T>
+int launch_sparse_leaf(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, ModP mp, int* ws,
+                       int spin_max, bool reset, unsigned long long* mail, unsigned seq);
+
 // Swap columns c0 and c1 of rows [0,rows).
 template <typename T>
 void launch_colswap(hipStream_t s, T* A, int64_t lda, int rows, int c0, int c1);

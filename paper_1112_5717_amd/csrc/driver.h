@@ -143,6 +143,10 @@ struct Ctx {
     // the node's G and Schur update.
     void* pair_below = nullptr;
     bool pair_done = false;
+    // A leaf with few pivots sends the next one straight to the sparse path;
+    // whether the sparse kernel's barrier words are in a known state.
+    bool sparse_next = false;
+    bool* sparse_ready = nullptr;
     // A full leaf's solve of its columns right of its pivots, held back so
     // that the parent's slab launch can carry it (it touches neither the
     // parent's U block nor the rows below); launched by itself before
@@ -223,6 +227,22 @@ inline void ctx_set_prime(Ctx& c, int64_t p)
     c.kred = (int64_t)std::min(terms, 1.0e12);
     if (c.kred_steps < 1) c.kred_steps = 1;
     if (c.kred < 1) c.kred = 1;
+}
+
+// The sparse leaf kernel's words in the small result buffer, the window
+// pivot count below which a leaf stopped by a zero row finishes there, and
+// the bound on its grid barriers' polls.
+constexpr int kSparseWs = 1024;
+constexpr int kSparseAfter = 16;
+constexpr int kSparseSpin = 1 << 22;
+
+// Device -> host copy of `count` small results from word `at`, then wait.
+inline const int* fetch_small_at(Ctx& c, int at, int count)
+{
+    CUP_HIP(hipMemcpyAsync(c.h_small + at, c.d_small + at, sizeof(int) * (size_t)count,
+                           hipMemcpyDeviceToHost, c.s));
+    CUP_HIP(hipStreamSynchronize(c.s));
+    return c.h_small + at;
 }
 
 // Device -> host copy of the first `count` small results, then wait.
@@ -810,6 +830,40 @@ int64_t leaf_followup(Ctx& c, T* A, int64_t lda, int b, int N, int i, int t, int
 // residual vanishes on the window is decided by a full-width scan.  Pivot
 // rows stay in place until the end, then the U rows are compacted upwards
 // in increasing order (the row move of Algorithm 6).
+// The rest of a rank-deficient leaf from row i and position t, every
+// remaining row in order, in one launch that takes the pivots full width
+// (no window, no host round trip per pivot); then the column exchanges it
+// left virtual, as one composed gather over the leaf's rows.  Appends the
+// pivots to P, Q and `rows`; returns their number.
+template <typename T>
+int sparse_rest(Ctx& c, T* A, int64_t lda, int b, int N, int i, int t, std::vector<int64_t>& P,
+                std::vector<int64_t>& Q, std::vector<int>& rows)
+{
+    flush_defer(c);
+    int* ws = c.d_small + kSparseWs;
+    const bool prof = c.prof && c.prof->want(1);
+    if (prof) c.prof->begin(c.s, 1, 0.0, 2.0 * (b - i) * (N - t) * sizeof(T));
+    const unsigned seq = next_seq(c);
+    const bool reset = !*c.sparse_ready;
+    *c.sparse_ready = false;  // (until this launch is known to have completed)
+    launch_sparse_leaf<T>(c.s, A, lda, b, N, i, t, c.mp, ws, kSparseSpin, reset, c.mail_d, seq);
+    if (prof) c.prof->end(c.s);
+    const int cnt = await_word(c, seq, 0);
+    if (await_word(c, seq, 1)) throw CupError{-3000};
+    *c.sparse_ready = true;
+    std::vector<int64_t> piv((size_t)(t + cnt));
+    for (int x = 0; x < t; ++x) piv[(size_t)x] = x;
+    for (int a = 0; a < cnt; ++a) {
+        const int col = await_word(c, seq, 2 + a), row = await_word(c, seq, kMailScan + a);
+        piv[(size_t)(t + a)] = col;
+        P.push_back(col);
+        Q.push_back(row);
+        rows.push_back(row);
+    }
+    apply_transpositions(c, A, lda, b, piv.data(), t + cnt);
+    return cnt;
+}
+
 template <typename T>
 int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
              std::vector<int64_t>& Q)
@@ -819,6 +873,12 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
     std::vector<int> piv_rows;
     T* below = static_cast<T*>(c.pair_below);
     c.pair_below = nullptr;
+    if (c.sparse_next) {
+        // the previous leaf had few pivots: this one starts on the sparse path
+        t = sparse_rest(c, A, lda, b, N, 0, 0, P, Q, piv_rows);
+        c.sparse_next = t < kSparseAfter;
+        i = b;
+    }
     while (i < b && t < N) {
         const int wc = std::min(kWin, N - t);
         flush_defer(c);  // (outside the window's timing)
@@ -900,6 +960,11 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
             if (g >= 0) c.uc_ok[(size_t)(g / kTriNB)] = 1;
             i += d;
             t += d;
+        }
+        if (stop == STOP_ZERO_ROW && i < b && t < N && d < kSparseAfter) {
+            t += sparse_rest(c, A, lda, b, N, i, t, P, Q, piv_rows);
+            c.sparse_next = t < kSparseAfter;
+            break;
         }
         if (stop == STOP_ZERO_ROW && i < b && t < N) {
             // the rows' results in order, as they arrive, up to the first

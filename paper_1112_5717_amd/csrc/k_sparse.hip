@@ -1,0 +1,311 @@
+// The rest of a rank-deficient CUP leaf in one launch.
+//
+// Algorithm 6's base case takes the rows in order; for each, the pivot is
+// the leftmost nonzero of its residual at positions >= t (the current
+// column order), the columns t and j exchange, the row is scaled into U and
+// the rows below are eliminated.  When most rows of a leaf have a zero
+// residual (a rank-deficient matrix: a row that is a combination of earlier
+// rows vanishes once those are eliminated), deciding each row by a 64-column
+// window and a separate full-width scan costs several launches and host
+// round trips per pivot.  This kernel instead runs the row loop on the
+// device for all remaining rows of the leaf, full width, with a grid of
+// co-resident workgroups (a cooperative launch) that own chunks of 64
+// columns and meet at grid barriers:
+//
+//   scan   each row's leftmost nonzero at positions >= t in the workgroup's
+//          columns -> atomicMin into that row's word;
+//   decide every workgroup finds the same first row p with a nonzero (the
+//          rows before it are zero rows: no pivot, nothing to do) and its
+//          pivot position j;
+//   read   the multipliers (the rows below p at the pivot's column) and the
+//          pivot;
+//   update row p scaled by the pivot's inverse into U; rows below p lose
+//          their multiplier times U (their multiplier stays, as their C
+//          entry, at position t after the exchange of t and j); then the
+//          next scan of the rows below p, from position t + 1.
+//
+// One grid barrier per pivot, none per zero row.  Residues are carried as doubles: a product of two stays below
+// 2^52 (p < 2^26), so every update is exact before its reduction.
+#include <algorithm>
+
+#include "modarith.h"
+
+namespace cup {
+
+namespace {
+
+constexpr int SPT = 256;  // threads per workgroup (one column each per pass)
+
+// Residues travel as doubles (exact below 2^53; a product of two residues is
+// below 2^52): reductions by the rounded reciprocal, inverses by Fermat.
+__device__ __forceinline__ double sub_mul(double x, double m, double u, double P, double PI)
+{
+    return mod_red(fma(-m, u, x), P, PI);
+}
+
+// One result word for the host (a 64-bit store tagged with the launch's
+// sequence number, at system scope).
+__device__ __forceinline__ void post_word(unsigned long long* w, unsigned seq, int v)
+{
+    __hip_atomic_store(w, ((unsigned long long)seq << 32) | (unsigned)v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Grid barrier over `nblk` co-resident workgroups: arrival counter bar[0]
+// and generation bar[1] (both zero at launch).  The wait is bounded; on
+// timeout the flag bar[2] is raised and every later barrier returns at
+// once, so that each workgroup leaves the kernel.
+__device__ bool grid_barrier(unsigned* bar, int nblk, unsigned& gen, int spin_max)
+{
+    __syncthreads();
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        const unsigned arrived = atomicAdd(&bar[0], 1u);
+        if (arrived == (unsigned)nblk - 1) {
+            atomicExch(&bar[0], 0u);
+            __threadfence();
+            atomicExch(&bar[1], gen + 1);
+        } else {
+            int it = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++it > spin_max) {
+                    atomicExch(&bar[2], 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        s_ok = ok && !__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    ++gen;
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ws layout (ints): [0..3) barrier, [4] pivot count, [8..8+3*64) the rows'
+// scan words (three rounds in rotation), [kSparseRows..+64) pivot rows,
+// [kSparseCols..+64) pivot columns (positions).
+constexpr int WS_BAR = 0, WS_CNT = kSparseCount, WS_MIN = 8, WS_PR = kSparseRows, WS_PC = kSparseCols;
+static_assert(WS_MIN + 3 * kLeafRows <= WS_PR, "scan words fit");
+constexpr int kMaxChunks = 64;  // 64-column chunks per workgroup at most
+
+// The column exchanges of the leaf are kept virtual until the end: a
+// workgroup owns the same physical columns throughout and records the
+// position of each (s_pos); position x is held by the physical column found
+// by undoing the exchanges so far (phys).  So a pivot's column, which holds
+// the rows' C entries from then on, is never written again in the leaf, and
+// the only data one workgroup reads from another's columns in a round (the
+// pivot and the multipliers, in that column) is final when the round
+// starts: one grid barrier per pivot.  The exchanges are applied to the
+// leaf's rows afterwards (by the host, as one composed gather).
+template <typename T>
+__global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int64_t lda, int b, int N,
+                                                          int i0, int t0, ModP mp, int* __restrict__ ws,
+                                                          int spin_max, unsigned long long* __restrict__ mail,
+                                                          unsigned seq)
+{
+    __shared__ int s_min[kLeafRows];
+    __shared__ double s_m[kLeafRows];
+    __shared__ int s_p, s_j, s_pc;
+    __shared__ double s_iv;
+    __shared__ int s_ht[kLeafRows], s_hj[kLeafRows];  // exchanges so far (positions)
+    __shared__ int s_pos[kMaxChunks * 64];             // position of each own column
+    const double P = mp.p, PI = mp.pinv;
+    unsigned* bar = reinterpret_cast<unsigned*>(ws + WS_BAR);
+    const int tid = threadIdx.x, nblk = gridDim.x;
+    // the barrier's generation continues from the previous launch (its last
+    // barrier left the arrival count at zero), so nothing is reset per launch
+    unsigned gen = 0;
+    if (tid == 0) gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int lane = tid & 63, rg = tid >> 6;
+    constexpr int RPT = kLeafRows / 4;  // rows per thread at most
+    const int cstride = nblk * 64;
+    const int nchunk = (N - t0 + cstride - 1) / cstride;  // own chunks (<= kMaxChunks)
+    auto col_of = [&](int ch) { return t0 + blockIdx.x * 64 + ch * cstride + lane; };
+    auto rmin = [&](int k) { return ws + WS_MIN + (k % 3) * kLeafRows; };
+
+    for (int ch = rg; ch < nchunk; ch += 4) s_pos[ch * 64 + lane] = col_of(ch);
+    for (int r = tid; r < kLeafRows; r += SPT) s_min[r] = N;
+    if (blockIdx.x == 0)
+        for (int r = tid; r < 3 * kLeafRows; r += SPT) ws[WS_MIN + r] = N;
+    if (!grid_barrier(bar, nblk, gen, spin_max)) return;
+    // first scan: every row's leftmost nonzero position >= t0
+    {
+        int best[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) best[k] = N;
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const int c = col_of(ch);
+            T x[RPT];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                const int r = i0 + rg + 4 * k;
+                x[k] = (c < N && r < b) ? A[(int64_t)r * lda + c] : (T)0;
+            }
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+                if (x[k] != 0) best[k] = min(best[k], c);
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int r = i0 + rg + 4 * k;
+            if (r < b && best[k] < N) atomicMin(&s_min[r], best[k]);
+        }
+        __syncthreads();
+        for (int r = i0 + tid; r < b; r += SPT)
+            if (s_min[r] < N) atomicMin(&rmin(0)[r], s_min[r]);
+    }
+
+    int i = i0, t = t0, count = 0;
+    while (i < b && t < N) {
+        if (!grid_barrier(bar, nblk, gen, spin_max)) return;
+        // decide: the first row from i with a nonzero residual, its pivot
+        // position, and the physical column that holds it
+        if (tid == 0) {
+            int pr = -1, jc = N;
+            for (int r = i; r < b; ++r) {
+                const int v = __hip_atomic_load(&rmin(count)[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v < N) {
+                    pr = r;
+                    jc = v;
+                    break;
+                }
+            }
+            int pc = jc;
+            for (int k = count - 1; k >= 0; --k) pc = (pc == s_ht[k]) ? s_hj[k] : ((pc == s_hj[k]) ? s_ht[k] : pc);
+            s_p = pr;
+            s_j = jc;
+            s_pc = pc;
+            if (pr >= 0) {
+                s_iv = mod_inv(ld_res(A + (int64_t)pr * lda + pc), P, PI);
+                s_ht[count] = t;
+                s_hj[count] = jc;
+            }
+        }
+        __syncthreads();
+        const int pr = s_p, j = s_j, pc = s_pc;
+        if (pr < 0) break;  // every remaining row is zero
+        const double iv = s_iv;
+        // the multipliers: the rows' entries at the pivot's column (final:
+        // that column is never written again in the leaf)
+        for (int r = tid; r < kLeafRows; r += SPT) {
+            s_m[r] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + pc) : 0.0;
+            s_min[r] = N;
+        }
+        // positions t and j exchange among own columns; the scan words two
+        // rounds ahead start empty (last read before this round's barrier)
+        const int ptc = [&] {
+            int x = t;
+            for (int k = count - 1; k >= 0; --k) x = (x == s_ht[k]) ? s_hj[k] : ((x == s_hj[k]) ? s_ht[k] : x);
+            return x;
+        }();  // physical column at position t before the exchange
+        if (blockIdx.x == 0) {
+            for (int r = tid; r < kLeafRows; r += SPT) rmin(count + 2)[r] = N;
+            if (tid == 0) {
+                ws[WS_PR + count] = pr;
+                ws[WS_PC + count] = j;
+            }
+        }
+        __syncthreads();
+        for (int ch = rg; ch < nchunk; ch += 4) {
+            const int c = col_of(ch);
+            if (c == pc && pc != ptc) s_pos[ch * 64 + lane] = t;
+            else if (c == ptc && pc != ptc) s_pos[ch * 64 + lane] = j;
+        }
+        __syncthreads();
+
+        // update the rows below p in every own column at a position > t (the
+        // pivot's column keeps their C entries), and scan them
+        int best[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) best[k] = N;
+        T* prow = A + (int64_t)pr * lda;
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const int c = col_of(ch);
+            const int pos = (c < N) ? s_pos[ch * 64 + lane] : 0;
+            if (c >= N || pos <= t) continue;
+            const double u = mod_mul(ld_res(prow + c), iv, P, PI);
+            double x[RPT];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                const int r = rg + 4 * k;
+                x[k] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + c) : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                const int r = rg + 4 * k;
+                if (r > pr && r < b) {
+                    const double y = sub_mul(x[k], s_m[r], u, P, PI);
+                    st_res(A + (int64_t)r * lda + c, y);
+                    if (y != 0.0) best[k] = min(best[k], pos);
+                }
+            }
+        }
+        __syncthreads();  // every read of row p is done before it is rescaled
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const int c = col_of(ch);
+            if (rg == 0 && c < N && s_pos[ch * 64 + lane] > t) st_res(prow + c, mod_mul(ld_res(prow + c), iv, P, PI));
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int r = rg + 4 * k;
+            if (r > pr && r < b && best[k] < N) atomicMin(&s_min[r], best[k]);
+        }
+        __syncthreads();
+        for (int r = pr + 1 + tid; r < b; r += SPT)
+            if (s_min[r] < N) atomicMin(&rmin(count + 1)[r], s_min[r]);
+        i = pr + 1;
+        ++t;
+        ++count;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        ws[WS_CNT] = count;
+        // the result for the host, in mapped memory: the pivot count, no
+        // failure, then each pivot's position and row
+        for (int a = 0; a < count; ++a) {
+            post_word(mail + 2 + a, seq, ws[WS_PC + a]);
+            post_word(mail + kMailScan + a, seq, ws[WS_PR + a]);
+        }
+        post_word(mail + 1, seq, 0);
+        post_word(mail, seq, count);
+    }
+}
+
+}  // namespace
+
+int sparse_ws_ints() { return WS_PC + kLeafRows; }
+
+template <typename T>
+int launch_sparse_leaf(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, ModP mp, int* ws,
+                       int spin_max, bool reset, unsigned long long* mail, unsigned seq)
+{
+    if (b <= i0 || N <= t0) return 0;
+    static int max_grid = 0;
+    if (!max_grid) {
+        int dev = 0, cus = 0, per = 0;
+        CUP_HIP(hipGetDevice(&dev));
+        CUP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, sparse_leaf_kernel<T>, SPT, 0));
+        max_grid = std::max(1, cus * std::max(1, per));
+    }
+    const int cols = N - t0;
+    const int grid = std::max(1, std::min(max_grid, (cols + 63) / 64));
+    if ((cols + grid * 64 - 1) / (grid * 64) > kMaxChunks) throw CupError{-3000};  // (N > 1M columns)
+    if (reset) CUP_HIP(hipMemsetAsync(ws, 0, sizeof(int) * 8, s));
+    void* args[] = {&A, &lda, &b, &N, &i0, &t0, &mp, &ws, &spin_max, &mail, &seq};
+    CUP_HIP(hipLaunchCooperativeKernel((const void*)sparse_leaf_kernel<T>, dim3(grid), dim3(SPT), args, 0, s));
+    return grid;
+}
+
+#define CUP_INST(T)                                                                                   \
+    template int launch_sparse_leaf<T>(hipStream_t, T*, int64_t, int, int, int, int, ModP, int*, int, bool, \
+                                       unsigned long long*, unsigned);
+CUP_INST(int64_t)
+CUP_INST(int8_t)
+#undef CUP_INST
+
+}  // namespace cup
