@@ -18,12 +18,15 @@ with every class timed, since the window and packing classes add event
 records to the stream and would slow the timed steps.
 
 Besides the headline form, the same steps run in the plain FP64-carrier
-form, once on the rank-6000 variant X(8192x6000) Y(6000x8192) mod p
-(seed 20), on the multi-modular batch (4096 matrices of up to 512 x 512,
-one prime below 2^23 each, one batched call per step), and on the other
-full-size workloads (GF(127) in int8 storage: CUP of 16384 x 16384 of rank
-12000 and the inverse of 8192 x 8192; GF(65521): CUP and reduced echelon
-form of a 32768 x 8192 staircase of rank 2048).  Every timed result is checked against the CPU oracle's SHA-256
+form; the rank-6000 variant X(8192x6000) Y(6000x8192) mod p (seed 20) runs
+in both forms; the multi-modular batch (4096 matrices of up to 512 x 512,
+one prime below 2^23 each) runs as one batched call per step and as the
+replay of a captured HIP graph; and the other full-size workloads run once
+each: GF(127) in int8 storage (CUP of 16384 x 16384 of rank 12000, the
+inverse of 8192 x 8192), GF(65521) (CUP and reduced echelon form of a
+32768 x 8192 staircase of rank 2048 in both forms, PLE of the headline
+matrix, CUP of the 512 x 384 rank-300 case in the FP64 form), and the
+8192^3 modular product classical against Strassen-Winograd.  Every timed result is checked against the CPU oracle's SHA-256
 digest when tests/golden/full_size_hashes.json has it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -65,7 +68,10 @@ def rref_ops(m: int, n: int, r: int) -> float:
     return r * r * (n - r) + (m - r) * r * r + 4.0 * r ** 3 / 3.0
 
 
-def config_variants(cup, torch, inputs, gold, steps):
+VARIANTS = ("cup16384", "inverse", "staircase", "ple", "small")
+
+
+def config_variants(cup, torch, inputs, gold, steps, which=VARIANTS):
     """The other full-size workloads, each restored from a pristine device
     copy before every call (outside the timed interval), median of `steps`
     calls after one warm-up, checked against the oracle's digest:
@@ -93,15 +99,31 @@ def config_variants(cup, torch, inputs, gold, steps):
 
     res = {}
     p = 127
-    A = inputs.low_rank(16384, 16384, 12000, p, seed=3, device="cuda")
-    d0 = torch.from_numpy(A.astype(np.int8)).cuda()
-    del A
-    t, (r, P, Q), work = timed(lambda x: cup.cup_factor_i8(x, p), d0)
-    res["cup_16384_rank12000_p127_int8"] = {
-        "ms": t * 1e3, "rank": r, "field_ops_per_s": field_ops(16384, 16384, r) / t,
-        "parity": check("cup_16384_rank12000_p127_seed3",
-                        digest(work.cpu().numpy().astype(np.int64), r, P.cpu().numpy(), Q.cpu().numpy()))}
-    del d0, work
+    if "cup16384" in which:
+        A = inputs.low_rank(16384, 16384, 12000, p, seed=3, device="cuda")
+        d0 = torch.from_numpy(A.astype(np.int8)).cuda()
+        del A
+        t, (r, P, Q), work = timed(lambda x: cup.cup_factor_i8(x, p), d0)
+        res["cup_16384_rank12000_p127_int8"] = {
+            "ms": t * 1e3, "rank": r, "field_ops_per_s": field_ops(16384, 16384, r) / t,
+            "parity": check("cup_16384_rank12000_p127_seed3",
+                            digest(work.cpu().numpy().astype(np.int64), r, P.cpu().numpy(), Q.cpu().numpy()))}
+        del d0, work
+    if "inverse" in which:
+        res.update(inverse_variant(cup, torch, inputs, gold, timed, check))
+    if "staircase" in which:
+        res.update(staircase_variant(cup, torch, inputs, timed, check))
+    if "ple" in which:
+        res.update(ple_variant(cup, torch, inputs, timed, check))
+    if "small" in which:
+        res.update(small_variant(cup, torch, inputs, check))
+    return res
+
+
+def inverse_variant(cup, torch, inputs, gold, timed, check):
+    import numpy as np
+    res = {}
+    p = 127
     g = gold.get("inverse_8192_p127_seed30", {"seed": 30})
     d0 = torch.from_numpy(inputs.uniform((8192, 8192), p, seed=g["seed"]).astype(np.int8)).cuda()
     t, (ok, r), work = timed(lambda x: cup.cup_inverse_inplace_i8(x, p), d0)
@@ -110,22 +132,110 @@ def config_variants(cup, torch, inputs, gold, steps):
         "ms": t * 1e3, "rank": r, "field_ops_per_s": 2.0 * 8192 ** 3 / t,
         "parity": check("inverse_8192_p127_seed30", dg) if ok else "singular"}
     del d0, work
+    return res
+
+
+def staircase_variant(cup, torch, inputs, timed, check):
+    res = {}
     p = P16
     A, _ = inputs.staircase(32768, 8192, 2048, p, seed=5, device="cuda")
     d0 = torch.from_numpy(A).cuda()
     del A
-    t, (r, P, Q), work = timed(lambda x: cup.cup_factor(x, p), d0)
-    res["cup_32768x8192_staircase2048_p65521"] = {
-        "ms": t * 1e3, "rank": r, "field_ops_per_s": field_ops(32768, 8192, r) / t,
-        "parity": check("cup_32768x8192_staircase2048_p65521_seed5",
-                        digest(work.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()))}
-    t, (r, P, Q), work = timed(lambda x: cup.cup_rref_inplace(x, p), d0)
-    res["rref_32768x8192_staircase2048_p65521"] = {
-        "ms": t * 1e3, "rank": r,
-        "field_ops_per_s": (field_ops(32768, 8192, r) + rref_ops(32768, 8192, r)) / t,
-        "parity": check("rref_32768x8192_staircase2048_p65521_seed5",
+    for form, sfx in (("i8limb", ""), ("fp64", "_fp64")):
+        cup.cup_set_form(form)
+        t, (r, P, Q), work = timed(lambda x: cup.cup_factor(x, p), d0)
+        res["cup_32768x8192_staircase2048_p65521" + sfx] = {
+            "ms": t * 1e3, "rank": r, "form": form, "field_ops_per_s": field_ops(32768, 8192, r) / t,
+            "parity": check("cup_32768x8192_staircase2048_p65521_seed5",
+                            digest(work.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()))}
+        t, (r, P, Q), work = timed(lambda x: cup.cup_rref_inplace(x, p), d0)
+        res["rref_32768x8192_staircase2048_p65521" + sfx] = {
+            "ms": t * 1e3, "rank": r, "form": form,
+            "field_ops_per_s": (field_ops(32768, 8192, r) + rref_ops(32768, 8192, r)) / t,
+            "parity": check("rref_32768x8192_staircase2048_p65521_seed5",
+                            digest(work.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()))}
+    cup.cup_set_form("auto")
+    del d0, work
+    return res
+
+
+def ple_variant(cup, torch, inputs, timed, check):
+    res = {}
+    p = P16
+    # PLE (Section 5) of the headline matrix, I8LIMB form
+    d0 = torch.from_numpy(inputs.uniform((8192, 8192), p, seed=2)).cuda()
+    t, (r, P, Q), work = timed(lambda x: cup.cup_ple(x, p), d0)
+    res["ple_8192_uniform_p65521"] = {
+        "ms": t * 1e3, "rank": r, "field_ops_per_s": field_ops(8192, 8192, r) / t,
+        "parity": check("ple_8192_uniform_p65521_seed2",
                         digest(work.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()))}
     del d0, work
+    return res
+
+
+def small_variant(cup, torch, inputs, check):
+    res = {}
+    p = P16
+    # the small case: 512 x 384 of rank 300 in the plain FP64-carrier form,
+    # median of 20 calls
+    cup.cup_set_form("fp64")
+    d0 = torch.from_numpy(inputs.low_rank(512, 384, 300, p, seed=1)).cuda()
+    times, out, work = [], None, None
+    for i in range(21):
+        work = d0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = cup.cup_factor(work, p)
+        torch.cuda.synchronize()
+        if i:
+            times.append(time.perf_counter() - t0)
+    t = sorted(times)[len(times) // 2]
+    r, P, Q = out
+    res["cup_512x384_rank300_p65521_fp64"] = {
+        "ms": t * 1e3, "rank": r, "form": "fp64", "field_ops_per_s": field_ops(512, 384, r) / t,
+        "parity": check("cup_512x384_rank300_p65521_seed1",
+                        digest(work.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()))}
+    cup.cup_set_form("auto")
+    return res
+
+
+def winograd_variant(cup, torch, steps):
+    """The modular product C - A B of 8192 x 8192 uniform residues mod 65521
+    in the FP64-carrier form, classical against one level of Strassen-Winograd
+    (Table 1's exponent log2 7): median of `steps` calls each, and whether the
+    two results are identical (their parity against the oracle is a test)."""
+    import numpy as np
+    p, n = P16, 8192
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    A = torch.randint(0, p, (n, n), dtype=torch.int64, device="cuda", generator=g)
+    B = torch.randint(0, p, (n, n), dtype=torch.int64, device="cuda", generator=g)
+    C0 = torch.randint(0, p, (n, n), dtype=torch.int64, device="cuda", generator=g)
+    cup.cup_set_form("fp64")
+    out = {}
+    res = {}
+    for levels in (0, 1):
+        cup.cup_set_winograd(levels, 4096)
+        times = []
+        C = None
+        for k in range(steps + 1):
+            C = C0.clone()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            cup.cup_ffgemm(C, A, B, p, -1)
+            e1.record()
+            torch.cuda.synchronize()
+            if k:
+                times.append(e0.elapsed_time(e1))
+        out[levels] = C
+        ms = float(np.median(times))
+        res["classical" if levels == 0 else "winograd_1_level"] = {
+            "ms": ms, "field_ops_per_s": 2.0 * n ** 3 / (ms * 1e-3)}
+    cup.cup_set_winograd(0, 2048)
+    cup.cup_set_form("auto")
+    res["identical"] = bool(torch.equal(out[0], out[1]))
+    res["shape"] = "8192 x 8192 x 8192 over GF(65521), FP64 carrier, C - A B"
     return res
 
 
@@ -211,6 +321,27 @@ def batched_variant(cup, torch, inputs, steps, warmup, gold):
         if k >= warmup:
             times.append(e0.elapsed_time(e1))
     ms = float(np.median(times))
+    # the allocation-free call captured once in a HIP graph, replayed
+    gwork = src.clone()
+    gptrs = fb.pointers(gwork)
+    fb.factor(gptrs, name="cup_factor_batched_noalloc")  # first use: set-up outside the capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fb.factor(gptrs, name="cup_factor_batched_noalloc")
+    gtimes = []
+    for k in range(warmup + steps):
+        gwork.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= warmup:
+            gtimes.append(e0.elapsed_time(e1))
+    graph_same = bool(torch.equal(gwork, work))
+    del graph, gwork
     ranks = fb.rank.cpu().numpy()
     info = fb.info.cpu().numpy()
     F = float(sum(field_ops(int(a), int(b), int(c)) for a, b, c in zip(m, n, ranks)))
@@ -228,6 +359,8 @@ def batched_variant(cup, torch, inputs, steps, warmup, gold):
         parity = "oracle digest match" if gold[key]["digest"] == h.hexdigest() else "ORACLE DIGEST MISMATCH"
     return {"matrices": count, "shapes": "m, n ~ U[16,512], r ~ U[1,min(m,n)], 32 primes < 2^23, seed 4",
             "ms_per_batch": ms, "field_ops": F, "field_ops_per_s": F / (ms * 1e-3),
+            "graph_replay_ms_per_batch": float(np.median(gtimes)),
+            "graph_replay_identical": graph_same,
             "errors": int((info != 0).sum()), "parity": parity, "timing": "HIP events, median"}
 
 
@@ -265,7 +398,8 @@ def roofline_of(stats, form, steps, traffic=None):
     achieved = (mult * st["flops"] / (st["ms"] * 1e-3) / 1e12) if st["ms"] > 0 else 0.0
     return {
         "bound": "mfma",
-        "kernel": "ffgemm_f64_kernel" if form == "fp64" else "ffgemm_i8_kernel",
+        "kernel": ("ffgemm_f64 product kernels (ffgemm_f64_kernel, ffgemm_f64_deep_kernel, "
+                   "ffgemm_f64_k64_kernel)") if form == "fp64" else "ffgemm_i8_kernel",
         "achieved": round(achieved, 3), "peak": peak, "unit": unit,
         "frac": round(achieved / peak, 4), "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -292,6 +426,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--only", choices=VARIANTS + ("batched", "winograd"), default=None,
+                    help="run only this extra workload and print its figures (for profiling)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -308,6 +444,15 @@ def main():
     cup.load()
     n = args.n
     gold = golden()
+    if args.only:
+        if args.only == "batched":
+            out = batched_variant(cup, torch, inputs, max(1, args.steps), args.warmup, gold)
+        elif args.only == "winograd":
+            out = winograd_variant(cup, torch, max(1, args.steps))
+        else:
+            out = config_variants(cup, torch, inputs, gold, max(1, args.steps), which=(args.only,))
+        print(json.dumps({"only": args.only, **out}))
+        return
     print(f"[bench] generating {n}x{n} uniform residues mod {P16} (seed 2)", file=sys.stderr, flush=True)
     A_host = inputs.uniform((n, n), P16, seed=2)
     A0 = torch.from_numpy(A_host).cuda()
@@ -349,19 +494,23 @@ def main():
     if not args.no_variants:
         print("[bench] rank-6000 variant (seed 20)", file=sys.stderr, flush=True)
         B0 = torch.from_numpy(inputs.low_rank(n, n, min(6000, n), P16, seed=20, device="cuda")).cuda()
-        rv = run_form(cup, torch, B0, P16, form, max(1, args.steps // 2), 1, profile=False)
-        extra["rank6000"] = {
-            "rank": rv["rank"], "form": form, "ms_per_step": rv["seconds"] * 1e3,
-            "field_ops_per_s": field_ops(n, n, rv["rank"]) / rv["seconds"],
-            "parity": parity_of(rv, f"cup_{n}_rank6000_p{P16}_seed20"),
-        }
+        extra["rank6000"] = {}
+        for fm in (form, "fp64") if form != "fp64" else (form,):
+            rv = run_form(cup, torch, B0, P16, fm, max(1, args.steps // 2), 1, profile=False)
+            extra["rank6000"][fm] = {
+                "rank": rv["rank"], "ms_per_step": rv["seconds"] * 1e3,
+                "field_ops_per_s": field_ops(n, n, rv["rank"]) / rv["seconds"],
+                "parity": parity_of(rv, f"cup_{n}_rank6000_p{P16}_seed20"),
+            }
         del B0
     cup.cup_set_form("auto")
     if not args.no_variants:
         print("[bench] multi-modular batch (4096 matrices)", file=sys.stderr, flush=True)
         extra["batched"] = batched_variant(cup, torch, inputs, max(1, args.steps), 1, gold)
-        print("[bench] int8 GF(127) and staircase workloads", file=sys.stderr, flush=True)
+        print("[bench] int8 GF(127), staircase, PLE and small workloads", file=sys.stderr, flush=True)
         extra["other_workloads"] = config_variants(cup, torch, inputs, gold, 3)
+        print("[bench] Strassen-Winograd against the classical product", file=sys.stderr, flush=True)
+        extra["winograd_ffgemm"] = winograd_variant(cup, torch, 3)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -6,8 +6,8 @@ parity tests and the benchmark compare against.  Run from the repo root:
 
     python tests/golden/make_full_size_hashes.py [name ...]
 
-Digest of a CUP result: sha256(packed int64 bytes | P int64 | Q int64 |
-rank int64); of an inverse: sha256(inverse int64 bytes); of a batch:
+Digest of a CUP (or PLE) result: sha256(packed int64 bytes | P int64 |
+Q int64 | rank int64); of an inverse: sha256(inverse int64 bytes); of a batch:
 sha256 over the concatenated binary digests of its matrices, in order.
 """
 from __future__ import annotations
@@ -62,6 +62,8 @@ def workloads():
         "cup_16384_rank12000_p127_seed3": lambda: ("cup", inputs.low_rank(16384, 16384, 12000, 127, seed=3), 127),
         "inverse_8192_p127_seed30": lambda: ("inverse", None, 127),
         "batched_4096_m16to512_p2e23_seed4": lambda: ("batched", None, None),
+        "cup_512x384_rank300_p65521_seed1": lambda: ("cup", inputs.low_rank(512, 384, 300, p16, seed=1), p16),
+        "ple_8192_uniform_p65521_seed2": lambda: ("ple", inputs.uniform((8192, 8192), p16, seed=2), p16),
     }
 
 
@@ -87,6 +89,9 @@ def main(names):
         t0 = time.time()
         if kind == "cup":
             packed, r, P, Q = oracle.cup(A, p)
+            entry = {"digest": cup_digest(packed, r, P, Q), "rank": r}
+        elif kind == "ple":
+            packed, r, P, Q = oracle.ple(A, p)
             entry = {"digest": cup_digest(packed, r, P, Q), "rank": r}
         elif kind == "rref":
             O, r, P, Q = oracle.rref_packed(A, p)

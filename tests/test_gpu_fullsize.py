@@ -135,3 +135,29 @@ def test_batched_multimodular_4096(cup_lib):
         h.update(bytes.fromhex(cup_digest(X[o:o + mm * nn].reshape(mm, nn), int(ranks[i]),
                                           P[po:po + nn], Q[qo:qo + mm])))
     assert h.hexdigest() == g["digest"]
+
+
+def test_ple_8192(cup_lib):
+    """PLE (Section 5) of the 8192 x 8192 uniform matrix over GF(65521), seed 2."""
+    p = 65521
+    d = torch.from_numpy(inputs.uniform((8192, 8192), p, seed=2)).cuda()
+    r, P, Q = cup_lib.cup_ple(d, p)
+    g = GOLD["ple_8192_uniform_p65521_seed2"]
+    assert r == g["rank"] == 8192
+    assert cup_digest(d.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()) == g["digest"]
+
+
+@pytest.mark.parametrize("form", ["i8limb", "fp64"])
+def test_config5_staircase_forms(cup_lib, form):
+    """The 32768 x 8192 rank-2048 staircase in both product forms."""
+    p = 65521
+    A, _ = inputs.staircase(32768, 8192, 2048, p, seed=5, device="cuda")
+    d = torch.from_numpy(A).cuda()
+    cup_lib.cup_set_form(form)
+    try:
+        r, P, Q = cup_lib.cup_factor(d, p)
+    finally:
+        cup_lib.cup_set_form("auto")
+    g = GOLD["cup_32768x8192_staircase2048_p65521_seed5"]
+    assert r == g["rank"] == 2048
+    assert cup_digest(d.cpu().numpy(), r, P.cpu().numpy(), Q.cpu().numpy()) == g["digest"]
