@@ -160,18 +160,51 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ S,
     }
 }
 
+// Algorithm 8's row exchanges: for j ascending, rows j and q[j] (q[j] >= j,
+// increasing) exchange their columns 0..j.  Column c takes the exchanges with
+// j >= c, in order; columns are independent, so one wave owns a tile of 64
+// columns and walks the exchanges in chunks of 64: the (at most 128) rows a
+// chunk touches are loaded into LDS (rows j of the chunk at their offset,
+// the other rows q[j] after them), each lane applies the chunk's exchanges
+// that reach its column in LDS, and the rows are written back.  Chunks whose
+// exchanges are all trivial are skipped.
 template <typename T>
-__global__ void rowswap_lower_kernel(T* __restrict__ A, int64_t lda, int r, const int* __restrict__ q)
+__global__ __launch_bounds__(64) void rowswap_lower_kernel(T* __restrict__ A, int64_t lda, int r,
+                                                           const int* __restrict__ q)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= r) return;
-    for (int j = c; j < r; ++j) {
-        int qj = q[j];
-        if (qj != j) {
-            T t = A[(int64_t)j * lda + c];
-            A[(int64_t)j * lda + c] = A[(int64_t)qj * lda + c];
-            A[(int64_t)qj * lda + c] = t;
+    __shared__ T buf[2 * 64][64];
+    __shared__ int slot_q[64];
+    const int lane = threadIdx.x, c0 = blockIdx.x * 64, c = c0 + lane;
+    for (int j0 = (c0 / 64) * 64; j0 < r; j0 += 64) {
+        const int jn = min(64, r - j0);
+        const int qj = (lane < jn) ? q[j0 + lane] : j0 + lane;
+        if (__ballot(lane < jn && qj != j0 + lane) == 0ull) continue;
+        // slot of row q[j]: its own offset when it is a row of the chunk
+        slot_q[lane] = (qj - j0 < jn) ? qj - j0 : 64 + lane;
+        __syncthreads();
+        for (int k = 0; k < jn; ++k) {
+            const int row = j0 + k, rq = __shfl(qj, k, 64);
+            if (c < r) {
+                buf[k][lane] = A[(int64_t)row * lda + c];
+                if (rq - j0 >= jn) buf[64 + k][lane] = A[(int64_t)rq * lda + c];
+            }
         }
+        if (c < r) {
+            for (int k = max(0, c - j0); k < jn; ++k) {
+                const int sq = slot_q[k];
+                if (sq != k) {
+                    const T x = buf[k][lane];
+                    buf[k][lane] = buf[sq][lane];
+                    buf[sq][lane] = x;
+                }
+            }
+            for (int k = 0; k < jn; ++k) {
+                const int row = j0 + k, rq = __shfl(qj, k, 64);
+                A[(int64_t)row * lda + c] = buf[k][lane];
+                if (rq - j0 >= jn) A[(int64_t)rq * lda + c] = buf[64 + k][lane];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -258,7 +291,7 @@ template <typename T>
 void launch_rowswap_lower(hipStream_t s, T* A, int64_t lda, int r, const int* q)
 {
     if (r <= 0) return;
-    hipLaunchKernelGGL(rowswap_lower_kernel<T>, dim3((r + 255) / 256), dim3(256), 0, s, A, lda, r, q);
+    hipLaunchKernelGGL(rowswap_lower_kernel<T>, dim3((r + 63) / 64), dim3(64), 0, s, A, lda, r, q);
     CUP_HIP(hipGetLastError());
 }
 

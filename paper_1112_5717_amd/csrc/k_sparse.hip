@@ -163,27 +163,29 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
     int i = i0, t = t0, count = 0;
     while (i < b && t < N) {
         if (!grid_barrier(bar, nblk, gen, spin_max)) return;
-        // decide: the first row from i with a nonzero residual, its pivot
-        // position, and the physical column that holds it
-        if (tid == 0) {
-            int pr = -1, jc = N;
-            for (int r = i; r < b; ++r) {
-                const int v = __hip_atomic_load(&rmin(count)[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (v < N) {
-                    pr = r;
-                    jc = v;
-                    break;
+        // decide: the first row from i with a nonzero residual (wave 0, one
+        // row per lane, all the scan words read at once), its pivot position,
+        // and the physical column that holds it
+        if (tid < 64) {
+            const int r = tid;
+            const int v = (r >= i && r < b)
+                              ? __hip_atomic_load(&rmin(count)[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : N;
+            const unsigned long long nz = __ballot(v < N);
+            const int pr = nz ? __ffsll((long long)nz) - 1 : -1;
+            const int jc = nz ? __shfl(v, pr, 64) : N;
+            if (tid == 0) {
+                int pc = jc;
+                for (int k = count - 1; k >= 0; --k)
+                    pc = (pc == s_ht[k]) ? s_hj[k] : ((pc == s_hj[k]) ? s_ht[k] : pc);
+                s_p = pr;
+                s_j = jc;
+                s_pc = pc;
+                if (pr >= 0) {
+                    s_iv = mod_inv(ld_res(A + (int64_t)pr * lda + pc), P, PI);
+                    s_ht[count] = t;
+                    s_hj[count] = jc;
                 }
-            }
-            int pc = jc;
-            for (int k = count - 1; k >= 0; --k) pc = (pc == s_ht[k]) ? s_hj[k] : ((pc == s_hj[k]) ? s_ht[k] : pc);
-            s_p = pr;
-            s_j = jc;
-            s_pc = pc;
-            if (pr >= 0) {
-                s_iv = mod_inv(ld_res(A + (int64_t)pr * lda + pc), P, PI);
-                s_ht[count] = t;
-                s_hj[count] = jc;
             }
         }
         __syncthreads();
