@@ -60,19 +60,26 @@ __device__ __forceinline__ double pick(const double (&v)[WQ][KPW], int k, int q)
     return x;
 }
 
+// Lanes l with lo <= l < hi, as a wave-uniform 64-bit mask.
+__device__ __forceinline__ unsigned long long lane_span(int lo, int hi)
+{
+    const unsigned long long from = (lo <= 0) ? ~0ull : ((lo >= 64) ? 0ull : (~0ull << lo));
+    const unsigned long long below = (hi >= 64) ? ~0ull : ((hi <= 0) ? 0ull : ((1ull << hi) - 1));
+    return from & below;
+}
+
 // Leftmost position >= a (and < wc) of a nonzero entry of the row held one
-// column per lane in u, or -1: one ballot per 64 columns.
+// column per lane in u, or -1: one compare per 64 columns, the position
+// limits applied to the ballot on the scalar unit.
 template <int WQ>
 __device__ __forceinline__ int leftmost(const double (&u)[WQ], int a, int wc)
 {
-    int j = -1;
 #pragma unroll
-    for (int q = WQ - 1; q >= 0; --q) {
-        const int c = (int)(threadIdx.x & 63) + 64 * q;
-        const unsigned long long mq = __ballot(c >= a && c < wc && u[q] != 0.0);
-        if (mq) j = 64 * q + __ffsll((long long)mq) - 1;
+    for (int q = 0; q < WQ; ++q) {
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(u[q] != 0.0) & lane_span(a - 64 * q, wc - 64 * q);
+        if (m) return 64 * q + __builtin_ctzll(m);
     }
-    return j;
+    return -1;
 }
 
 // u[q] for a wave-uniform q
@@ -172,29 +179,42 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     __syncthreads();
 
     const int own0 = KPW * w;
-    // columns a and j (> a) exchange in every own row
+    // columns a and j (> a) exchange in every own row: the two entries are
+    // read out to scalars and written back by lane selects, so the exchange
+    // uses no LDS traffic (and no wait on it) on the chain
     auto swap_cols = [&](int a, int j) {
         const int qa = a >> 6, la = a & 63, qj = j >> 6, lj = j & 63;
+        const bool at_a = lane == la, at_j = lane == lj;
 #pragma unroll
         for (int k = 0; k < KPW; ++k) {
-            const double from_j = __shfl(pick(v, k, qj), lj, 64);
-            const double from_a = __shfl(pick(v, k, qa), la, 64);
+            const double xa = readlane_d(pick(v, k, qa), la);
+            const double xj = readlane_d(pick(v, k, qj), lj);
 #pragma unroll
             for (int q = 0; q < WQ; ++q) {
-                if (lane == la && q == qa) v[q][k] = from_j;
-                if (lane == lj && q == qj) v[q][k] = from_a;
+                v[q][k] = (at_a && q == qa) ? xj : v[q][k];
+                v[q][k] = (at_j && q == qj) ? xa : v[q][k];
             }
         }
     };
-    // fraction-free update of own row k by pivot row u of step a (the
-    // multiplier is kept first; it is not on the update's dependency chain)
-    auto update = [&](int k, int a, double piv, const double (&u)[WQ]) {
-        const double m = readlane_d(pick(v, k, a >> 6), a & 63);
+    // fraction-free update of own row k by pivot row u of step a, with the
+    // row's multiplier m (its entry at position a) read out beforehand; the
+    // multiplier is also kept at lane a
+    auto update = [&](int k, int a, double piv, double m, const double (&u)[WQ]) {
 #pragma unroll
         for (int q = 0; q < WQ; ++q) {
             cm[q][k] = (lane + 64 * q == a) ? v[q][k] : cm[q][k];
             v[q][k] = red_c(fma(piv, v[q][k], -m * u[q]), P, PI);
         }
+    };
+    // The pivot entry and the multipliers are read out (lane to scalar) as
+    // soon as the pivot row is there, on the guess that the pivot is at
+    // position a, which holds unless the entry there is zero; the leftmost
+    // test runs beside them and only a failed guess reads them again.  Each
+    // read-out costs the latency of a vector-to-scalar transfer, so the
+    // guess takes it off the pivot search's path.
+    auto multipliers = [&](int a, int kfrom, double (&m)[KPW]) {
+#pragma unroll
+        for (int k = 0; k < KPW; ++k) m[k] = (k >= kfrom) ? readlane_d(pick(v, k, a >> 6), a & 63) : 0.0;
     };
 
     // Steps of the waves above: follow them in order (rows past the block
@@ -230,16 +250,18 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             stopped = true;
             break;
         }
+        double piv = readlane_d(pick1(u, a >> 6), a & 63);
+        double m[KPW];
+        multipliers(a, 0, m);
         const int j = leftmost(u, a, wc);
         if (j < 0) {
             stopped = true;
             break;
         }
-        double piv;
         if (j != a) {
             // the exchange of positions a and j, in the pivot row and in
             // every own row
-            const double ua = readlane_d(pick1(u, a >> 6), a & 63);
+            const double ua = piv;
             piv = readlane_d(pick1(u, j >> 6), j & 63);
 #pragma unroll
             for (int q = 0; q < WQ; ++q) {
@@ -247,11 +269,10 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 u[q] = (c == a) ? piv : ((c == j) ? ua : u[q]);
             }
             swap_cols(a, j);
-        } else {
-            piv = readlane_d(pick1(u, a >> 6), a & 63);
+            multipliers(a, 0, m);
         }
 #pragma unroll
-        for (int k = 0; k < KPW; ++k) update(k, a, piv, u);
+        for (int k = 0; k < KPW; ++k) update(k, a, piv, m[k], u);
     }
     // Own steps, at the highest issue priority: they are the chain, and the
     // waves below share the SIMDs with updates that can wait.  Pivot
@@ -271,6 +292,9 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 u[q] = v[q][k];
                 rowslot[a][lane + 64 * q] = u[q];  // published before the exchange
             }
+            double piv = readlane_d(pick1(u, a >> 6), a & 63);
+            double m[KPW];
+            multipliers(a, k + 1, m);
             const int j = leftmost(u, a, wc);
             if (j < 0) {  // zero residual on the window: the phase ends at a
                 if (lane == 0) s_d = a;
@@ -280,13 +304,14 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 swap_cols(a, j);
 #pragma unroll
                 for (int q = 0; q < WQ; ++q) u[q] = v[q][k];
+                piv = readlane_d(pick1(u, a >> 6), a & 63);
+                multipliers(a, k + 1, m);
             }
-            const double piv = readlane_d(pick1(u, a >> 6), a & 63);
             own_j[k] = j;
             own_piv[k] = piv;
             nown = k + 1;
 #pragma unroll
-            for (int k2 = k + 1; k2 < KPW; ++k2) update(k2, a, piv, u);
+            for (int k2 = k + 1; k2 < KPW; ++k2) update(k2, a, piv, m[k2], u);
         }
     }
     if (lane == 0) {
