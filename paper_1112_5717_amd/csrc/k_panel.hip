@@ -153,6 +153,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     __shared__ double s_ipiv[kLeafRows];
     __shared__ double s_dl[kLeafRows];  // inverses of the diagonal of C
     __shared__ int s_nswap;
+    __shared__ int s_b[kLeafRows][kLeafRows + 1];  // the block under the leaf (two-leaf node)
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
@@ -177,6 +178,12 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         s_d = aend;
     }
     __syncthreads();
+    // The block under the leaf, read for G = B U^{-1} at the end, is fetched
+    // now by the second half of the waves (whose first own step is the
+    // furthest away), so that its memory latency is off the end phase.
+    if (WQ == 1 && below != nullptr && tid >= WT / 2)
+        for (int x = tid - WT / 2; x < kLeafRows * kLeafRows; x += WT / 2)
+            s_b[x >> 6][x & 63] = (int)ld_res(below + (int64_t)(x >> 6) * lda + (x & 63));
 
     const int own0 = KPW * w;
     // columns a and j (> a) exchange in every own row: the two entries are
@@ -365,28 +372,30 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         }
     }
 
-    // Sigma_{s+1} = prod_{s' <= s} piv_{s'}: inclusive scan in wave 0.
+    // Sigma_{s+1} = prod_{s' <= s} piv_{s'}: inclusive scan in wave 0, and the
+    // inverses from it, every value kept in (-p, p) (short roundings on this
+    // serial stretch; the stores below make the results canonical).
     if (w == 0) {
-        double x = (lane < d) ? mod_red(s_piv[lane], P, PI) : 1.0;
+        double x = (lane < d) ? s_piv[lane] : 1.0;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             double o = __shfl_up(x, off, 64);
-            if (lane >= off) x = mod_mul(x, o, P, PI);
+            if (lane >= off) x = red_near(x * o, P, PI);
         }
         double sig_prev = __shfl_up(x, 1, 64);  // Sigma_lane
         if (lane == 0) sig_prev = 1.0;
         if (lane < d) {
-            double isig_next = mod_inv(x, P, PI);  // 1 / Sigma_{lane+1}
+            double isig_next = inv_near(x, P, PI);  // 1 / Sigma_{lane+1}
             s_isig[lane + 1] = isig_next;
-            const double ipiv = mod_mul(sig_prev, isig_next, P, PI);  // 1 / piv_lane
+            const double ipiv = red_near(sig_prev * isig_next, P, PI);  // 1 / piv_lane
             s_ipiv[lane] = ipiv;
-            s_dl[lane] = mod_mul(sig_prev, ipiv, P, PI);  // 1 / C[lane][lane]
+            s_dl[lane] = red_near(sig_prev * ipiv, P, PI);  // 1 / C[lane][lane]
         } else {
             s_dl[lane] = 1.0;  // identity padding of the inverse below
         }
         if (lane == 0) s_isig[0] = 1.0;
     }
-    __syncthreads();
+    lds_barrier();
 
     // The pivot block's triangles are inverted here as well (padded with the
     // identity to 64 x 64): L^{-1} for any pivot count when `winv` is given,
@@ -406,7 +415,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
                 const bool low = c < r && c < d;
                 const double x = low ? cm[q][k] : v[q][k];
                 const double f = (c <= r && c < d) ? s_isig[c] : ((r < d) ? s_ipiv[r] : s_isig[d]);
-                const double y = mod_mul(x, f, P, PI);
+                const double y = canon(red_near(x * f, P, PI), P);
                 st_res(A + (int64_t)(i0 + r) * lda + t0 + c, y);
             }
         }
@@ -419,14 +428,16 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         for (int k = 0; k < KPW; ++k) {
             const int r = KPW * w + k;
             const bool in = r < d && c < d;
-            wbuf[0][r][c] = (in && c > r) ? mod_mul(v[0][k], s_ipiv[r], P, PI) : 0.0;
-            wbuf[1][c][r] = (in && c < r) ? mod_mul(cm[0][k], s_ipiv[c], P, PI) : 0.0;
+            wbuf[0][r][c] = (in && c > r) ? red_near(v[0][k] * s_ipiv[r], P, PI) : 0.0;
+            wbuf[1][c][r] = (in && c < r) ? red_near(cm[0][k] * s_ipiv[c], P, PI) : 0.0;
         }
         // waves 0-3 invert U, waves 4-7 the scaled L^T; then
         // U^{-1} as is, and L^{-1}[i][s] = (L^T scaled)^{-1}[s][i] / C[i][i]
-        __syncthreads();
+        // (the barriers order LDS only: the stores of the block above are
+        // left in flight)
+        lds_barrier();
         const bool second = w >= 4;
-        unit_upper_inverse<(WT >= 1024 ? 1 : 3)>(wbuf[second ? 1 : 0], wbuf[second ? 3 : 2], P, PI, second ? 4 : 0);
+        unit_upper_inverse<3>(wbuf[second ? 1 : 0], wbuf[second ? 3 : 2], P, PI, second ? 4 : 0);
         for (int idx = tid; idx < kLeafRows * kLeafRows; idx += WT) {
             const int i = idx >> 6, s = idx & 63;
             if (uinv && full) uinv[idx] = canon(wbuf[2][i][s], P);
@@ -434,19 +445,22 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         }
         if (below != nullptr && full && s_nswap == 0) {
             // G = B U^{-1} for the block under the leaf (Algorithm 6's G
-            // for a two-leaf node), one 16 x 16 tile per wave, in place
-            const int hi = lane >> 4, lo = lane & 15, tr = w >> 2, tc = w & 3;
-            double bv[16];
+            // for a two-leaf node), 16 x 16 tiles spread over the waves, in
+            // place (B comes from LDS, so no wave waits for another's reads)
+            const int hi = lane >> 4, lo = lane & 15;
+            for (int tile = w; tile < 16; tile += NWV) {
+                const int tr = tile >> 2, tc = tile & 3;
+                double bv[16];
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks) bv[ks] = ld_res(below + (int64_t)(16 * tr + lo) * lda + 4 * ks + hi);
-            v4d acc = {0.0, 0.0, 0.0, 0.0};
+                for (int ks = 0; ks < 16; ++ks) bv[ks] = (double)s_b[16 * tr + lo][4 * ks + hi];
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[ks], wbuf[2][4 * ks + hi][16 * tc + lo], acc, 0, 0, 0);
-            __syncthreads();  // every wave has read its rows of B before any is overwritten
+                for (int ks = 0; ks < 16; ++ks)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[ks], wbuf[2][4 * ks + hi][16 * tc + lo], acc, 0, 0, 0);
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                st_res(below + (int64_t)(16 * tr + hi + 4 * e) * lda + 16 * tc + lo, mod_red(acc[e], P, PI));
+                for (int e = 0; e < 4; ++e)
+                    st_res(below + (int64_t)(16 * tr + hi + 4 * e) * lda + 16 * tc + lo, mod_red(acc[e], P, PI));
+            }
         }
     }
     // the same column swaps on the leaf rows above the window block

@@ -22,6 +22,29 @@ __device__ __forceinline__ double red_near(double x, double p, double pinv)
 
 __device__ __forceinline__ double canon(double x, double p) { return (x < 0.0) ? x + p : x; }
 
+// a^(p-2), the inverse of a nonzero residue (Fermat), by square and multiply
+// with every intermediate in (-p, p): one short rounding per product, and
+// every product below p^2 < 2^52.
+__device__ inline double inv_near(double a, double p, double pinv)
+{
+    double r = 1.0, b = a;
+    for (int64_t e = (int64_t)p - 2; e > 0; e >>= 1) {
+        if (e & 1) r = red_near(r * b, p, pinv);
+        b = red_near(b * b, p, pinv);
+    }
+    return r;
+}
+
+// Workgroup barrier that orders LDS accesses only: global stores still in
+// flight are not waited for (the usual barrier waits for every memory
+// operation of every wave).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Inverse of a unit upper triangle U (64 x 64; its strict upper part in M),
 // into X, by 16 x 16 blocks.  The four diagonal blocks are inverted
 // column-parallel by the first wave of the group (lane 16a + j solves for
@@ -73,7 +96,7 @@ __device__ __forceinline__ void unit_upper_inverse(const double (*M)[kTriNB + 1]
             const int i = idx >> 6, s = idx & 63;
             if ((s >> 4) < (i >> 4)) X[i][s] = 0.0;
         }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int d = 1; d < 4; ++d) {
         if (w >= 0 && w + d < 4) {
@@ -105,7 +128,7 @@ __device__ __forceinline__ void unit_upper_inverse(const double (*M)[kTriNB + 1]
 #pragma unroll
             for (int e = 0; e < 4; ++e) X[16 * a + hi + 4 * e][16 * b + lo] = -red_near(xacc[e], P, PI);
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
