@@ -38,6 +38,7 @@ namespace {
 constexpr int WT = 1024;            // threads of the window kernel (16 waves)
 constexpr int NWV = WT / 64;        // waves
 constexpr int KPW = kLeafRows / NWV; // tile rows per wave
+static_assert(NWV >= 10, "the end phase inverts the two triangles on waves 0-3 and 6-9");
 
 // Residue in (-p, p): x - round(x / p) p, exact for |x| < 2^53.  Zero iff
 // x = 0 mod p.  The rounding adds and subtracts 1.5 * 2^52, which rounds any
@@ -179,10 +180,10 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
     }
     __syncthreads();
     // The block under the leaf, read for G = B U^{-1} at the end, is fetched
-    // now by the second half of the waves (whose first own step is the
+    // now by the last quarter of the waves (whose first own step is the
     // furthest away), so that its memory latency is off the end phase.
-    if (WQ == 1 && below != nullptr && tid >= WT / 2)
-        for (int x = tid - WT / 2; x < kLeafRows * kLeafRows; x += WT / 2)
+    if (WQ == 1 && below != nullptr && tid >= 3 * WT / 4)
+        for (int x = tid - 3 * WT / 4; x < kLeafRows * kLeafRows; x += WT / 4)
             s_b[x >> 6][x & 63] = (int)ld_res(below + (int64_t)(x >> 6) * lda + (x & 63));
 
     const int own0 = KPW * w;
@@ -431,13 +432,15 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
             wbuf[0][r][c] = (in && c > r) ? red_near(v[0][k] * s_ipiv[r], P, PI) : 0.0;
             wbuf[1][c][r] = (in && c < r) ? red_near(cm[0][k] * s_ipiv[c], P, PI) : 0.0;
         }
-        // waves 0-3 invert U, waves 4-7 the scaled L^T; then
+        // waves 0-3 invert U, waves 6-9 the scaled L^T (so that, with waves
+        // placed on the four SIMDs in turn, the two groups' matrix-core
+        // products of the later rounds fall on different SIMDs); then
         // U^{-1} as is, and L^{-1}[i][s] = (L^T scaled)^{-1}[s][i] / C[i][i]
         // (the barriers order LDS only: the stores of the block above are
         // left in flight)
         lds_barrier();
-        const bool second = w >= 4;
-        unit_upper_inverse<3>(wbuf[second ? 1 : 0], wbuf[second ? 3 : 2], P, PI, second ? 4 : 0);
+        const bool second = w >= 6 && w < 10;
+        unit_upper_inverse<3>(wbuf[second ? 1 : 0], wbuf[second ? 3 : 2], P, PI, second ? 6 : 0);
         for (int idx = tid; idx < kLeafRows * kLeafRows; idx += WT) {
             const int i = idx >> 6, s = idx & 63;
             if (uinv && full) uinv[idx] = canon(wbuf[2][i][s], P);
