@@ -29,6 +29,7 @@
 #include <algorithm>
 
 #include "modarith.h"
+#include "tri64.h"
 
 namespace cup {
 
@@ -68,14 +69,17 @@ __device__ bool grid_barrier(unsigned* bar, int nblk, unsigned& gen, int spin_ma
             __threadfence();
             atomicExch(&bar[1], gen + 1);
         } else {
+            // one memory round trip per poll; the failure flag is read on
+            // every 16th poll only
             int it = 0;
             while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++it > spin_max) {
+                if (++it > spin_max ||
+                    ((it & 15) == 0 && __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
                     atomicExch(&bar[2], 1u);
                     ok = 0;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
             }
         }
         __threadfence();
@@ -86,11 +90,37 @@ __device__ bool grid_barrier(unsigned* bar, int nblk, unsigned& gen, int spin_ma
     return s_ok != 0;
 }
 
-// ws layout (ints): [0..3) barrier, [4] pivot count, [8..8+3*64) the rows'
-// scan words (three rounds in rotation), [kSparseRows..+64) pivot rows,
-// [kSparseCols..+64) pivot columns (positions).
-constexpr int WS_BAR = 0, WS_CNT = kSparseCount, WS_MIN = 8, WS_PR = kSparseRows, WS_PC = kSparseCols;
-static_assert(WS_MIN + 3 * kLeafRows <= WS_PR, "scan words fit");
+// ws layout (ints): [0..3) barrier, [4] pivot count, [8..14) the scan words
+// (three 64-bit words, one per round in rotation), [kSparseRows..+64) pivot
+// rows, [kSparseCols..+64) pivot columns (positions).
+constexpr int WS_BAR = 0, WS_CNT = kSparseCount, WS_KEY = 8, WS_PR = kSparseRows, WS_PC = kSparseCols;
+static_assert(WS_KEY % 2 == 0 && WS_KEY + 6 <= WS_PR, "scan words fit, 8-byte aligned");
+
+// A scan result: the first row (leaf-relative) with a nonzero residual at the
+// positions scanned, and its leftmost such position, as one ordered key
+// (row above position), so that the minimum over the workgroups' keys is the
+// next pivot.  No key: no nonzero left.
+constexpr unsigned long long kNoKey = ~0ull;
+__device__ __forceinline__ unsigned long long scan_key(int r, int pos)
+{
+    return ((unsigned long long)(unsigned)r << 32) | (unsigned)pos;
+}
+
+// Minimum of the workgroup's keys, folded into *word by one atomic (thread 0).
+__device__ void fold_key(unsigned long long key, unsigned long long* s_keys, unsigned long long* word)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        key = o < key ? o : key;
+    }
+    if ((threadIdx.x & 63) == 0) s_keys[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long k = s_keys[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) k = s_keys[w] < k ? s_keys[w] : k;
+        if (k != kNoKey) atomicMin(word, k);
+    }
+}
 constexpr int kMaxChunks = 64;  // 64-column chunks per workgroup at most
 
 // The column exchanges of the leaf are kept virtual until the end: a
@@ -108,7 +138,7 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
                                                           int spin_max, unsigned long long* __restrict__ mail,
                                                           unsigned seq)
 {
-    __shared__ int s_min[kLeafRows];
+    __shared__ unsigned long long s_keys[SPT / 64];
     __shared__ double s_m[kLeafRows];
     __shared__ int s_p, s_j, s_pc;
     __shared__ double s_iv;
@@ -126,12 +156,10 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
     const int cstride = nblk * 64;
     const int nchunk = (N - t0 + cstride - 1) / cstride;  // own chunks (<= kMaxChunks)
     auto col_of = [&](int ch) { return t0 + blockIdx.x * 64 + ch * cstride + lane; };
-    auto rmin = [&](int k) { return ws + WS_MIN + (k % 3) * kLeafRows; };
+    auto kword = [&](int k) { return reinterpret_cast<unsigned long long*>(ws + WS_KEY) + (k % 3); };
 
     for (int ch = rg; ch < nchunk; ch += 4) s_pos[ch * 64 + lane] = col_of(ch);
-    for (int r = tid; r < kLeafRows; r += SPT) s_min[r] = N;
-    if (blockIdx.x == 0)
-        for (int r = tid; r < 3 * kLeafRows; r += SPT) ws[WS_MIN + r] = N;
+    if (blockIdx.x == 0 && tid < 3) *kword(tid) = kNoKey;
     if (!grid_barrier(bar, nblk, gen, spin_max)) return;
     // first scan: every row's leftmost nonzero position >= t0
     {
@@ -150,42 +178,35 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
             for (int k = 0; k < RPT; ++k)
                 if (x[k] != 0) best[k] = min(best[k], c);
         }
+        unsigned long long key = kNoKey;
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
             const int r = i0 + rg + 4 * k;
-            if (r < b && best[k] < N) atomicMin(&s_min[r], best[k]);
+            if (r < b && best[k] < N) key = min(key, scan_key(r, best[k]));
         }
-        __syncthreads();
-        for (int r = i0 + tid; r < b; r += SPT)
-            if (s_min[r] < N) atomicMin(&rmin(0)[r], s_min[r]);
+        fold_key(key, s_keys, kword(0));
     }
 
     int i = i0, t = t0, count = 0;
     while (i < b && t < N) {
         if (!grid_barrier(bar, nblk, gen, spin_max)) return;
-        // decide: the first row from i with a nonzero residual (wave 0, one
-        // row per lane, all the scan words read at once), its pivot position,
-        // and the physical column that holds it
-        if (tid < 64) {
-            const int r = tid;
-            const int v = (r >= i && r < b)
-                              ? __hip_atomic_load(&rmin(count)[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                              : N;
-            const unsigned long long nz = __ballot(v < N);
-            const int pr = nz ? __ffsll((long long)nz) - 1 : -1;
-            const int jc = nz ? __shfl(v, pr, 64) : N;
-            if (tid == 0) {
-                int pc = jc;
-                for (int k = count - 1; k >= 0; --k)
-                    pc = (pc == s_ht[k]) ? s_hj[k] : ((pc == s_hj[k]) ? s_ht[k] : pc);
-                s_p = pr;
-                s_j = jc;
-                s_pc = pc;
-                if (pr >= 0) {
-                    s_iv = mod_inv(ld_res(A + (int64_t)pr * lda + pc), P, PI);
-                    s_ht[count] = t;
-                    s_hj[count] = jc;
-                }
+        // decide: the round's scan word is the first row from i with a
+        // nonzero residual and its pivot position; then the physical column
+        // that holds it, and the pivot's inverse
+        if (tid == 0) {
+            const unsigned long long key = __hip_atomic_load(kword(count), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int pr = (key == kNoKey) ? -1 : (int)(key >> 32);
+            const int jc = (key == kNoKey) ? N : (int)(key & 0xffffffffu);
+            int pc = jc;
+            for (int k = count - 1; k >= 0; --k)
+                pc = (pc == s_ht[k]) ? s_hj[k] : ((pc == s_hj[k]) ? s_ht[k] : pc);
+            s_p = pr;
+            s_j = jc;
+            s_pc = pc;
+            if (pr >= 0) {
+                s_iv = canon(inv_near(ld_res(A + (int64_t)pr * lda + pc), P, PI), P);
+                s_ht[count] = t;
+                s_hj[count] = jc;
             }
         }
         __syncthreads();
@@ -194,10 +215,7 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
         const double iv = s_iv;
         // the multipliers: the rows' entries at the pivot's column (final:
         // that column is never written again in the leaf)
-        for (int r = tid; r < kLeafRows; r += SPT) {
-            s_m[r] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + pc) : 0.0;
-            s_min[r] = N;
-        }
+        for (int r = tid; r < kLeafRows; r += SPT) s_m[r] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + pc) : 0.0;
         // positions t and j exchange among own columns; the scan words two
         // rounds ahead start empty (last read before this round's barrier)
         const int ptc = [&] {
@@ -205,12 +223,10 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
             for (int k = count - 1; k >= 0; --k) x = (x == s_ht[k]) ? s_hj[k] : ((x == s_hj[k]) ? s_ht[k] : x);
             return x;
         }();  // physical column at position t before the exchange
-        if (blockIdx.x == 0) {
-            for (int r = tid; r < kLeafRows; r += SPT) rmin(count + 2)[r] = N;
-            if (tid == 0) {
-                ws[WS_PR + count] = pr;
-                ws[WS_PC + count] = j;
-            }
+        if (blockIdx.x == 0 && tid == 0) {
+            *kword(count + 2) = kNoKey;
+            ws[WS_PR + count] = pr;
+            ws[WS_PC + count] = j;
         }
         __syncthreads();
         for (int ch = rg; ch < nchunk; ch += 4) {
@@ -252,14 +268,13 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
             const int c = col_of(ch);
             if (rg == 0 && c < N && s_pos[ch * 64 + lane] > t) st_res(prow + c, mod_mul(ld_res(prow + c), iv, P, PI));
         }
+        unsigned long long key = kNoKey;
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
             const int r = rg + 4 * k;
-            if (r > pr && r < b && best[k] < N) atomicMin(&s_min[r], best[k]);
+            if (r > pr && r < b && best[k] < N) key = min(key, scan_key(r, best[k]));
         }
-        __syncthreads();
-        for (int r = pr + 1 + tid; r < b; r += SPT)
-            if (s_min[r] < N) atomicMin(&rmin(count + 1)[r], s_min[r]);
+        fold_key(key, s_keys, kword(count + 1));
         i = pr + 1;
         ++t;
         ++count;
