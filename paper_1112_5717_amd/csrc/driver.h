@@ -229,9 +229,10 @@ inline void ctx_set_prime(Ctx& c, int64_t p)
     if (c.kred < 1) c.kred = 1;
 }
 
-// The sparse leaf kernel's words in the small result buffer, the window
-// pivot count below which a leaf stopped by a zero row finishes there, and
-// the bound on its grid barriers' polls.
+// The sparse leaf kernel's words in the small result buffer (sparse_ws_ints()
+// = 768 ints from here, within kSmallInts), the window pivot count below
+// which a leaf stopped by a zero row finishes there, and the bound on its
+// grid barriers' polls.
 constexpr int kSparseWs = 1024;
 constexpr int kSparseAfter = 16;
 constexpr int kSparseSpin = 1 << 22;
@@ -841,6 +842,7 @@ int sparse_rest(Ctx& c, T* A, int64_t lda, int b, int N, int i, int t, std::vect
 {
     flush_defer(c);
     int* ws = c.d_small + kSparseWs;
+    if (kSparseWs + sparse_ws_ints() > kSmallInts) throw CupError{-3000};
     const bool prof = c.prof && c.prof->want(1);
     if (prof) c.prof->begin(c.s, 1, 0.0, 2.0 * (b - i) * (N - t) * sizeof(T));
     const unsigned seq = next_seq(c);

@@ -52,40 +52,43 @@ __device__ __forceinline__ void post_word(unsigned long long* w, unsigned seq, i
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Grid barrier over `nblk` co-resident workgroups: arrival counter bar[0]
-// and generation bar[1] (both zero at launch).  The wait is bounded; on
-// timeout the flag bar[2] is raised and every later barrier returns at
-// once, so that each workgroup leaves the kernel.
-__device__ bool grid_barrier(unsigned* bar, int nblk, unsigned& gen, int spin_max)
+// Grid barrier over `nblk` co-resident workgroups, with no central counter:
+// each workgroup stores the generation it has reached into its own word of
+// `flags` and then reads every other workgroup's word (one wave, one word
+// per lane) until all have reached it; a workgroup already at the next
+// barrier counts as arrived.  One store and one round of loads per barrier,
+// and no atomic that 128 workgroups contend for.  Generations grow across
+// launches (the last is kept in bar[1]); the wait is bounded, and on timeout
+// the flag bar[2] is raised and every later barrier returns at once, so that
+// each workgroup leaves the kernel.
+__device__ bool grid_barrier(unsigned* bar, unsigned* flags, int nblk, unsigned& gen, int spin_max)
 {
     __syncthreads();
     __shared__ int s_ok;
+    const unsigned next = gen + 1;
     if (threadIdx.x == 0) {
-        int ok = 1;
         __threadfence();
-        const unsigned arrived = atomicAdd(&bar[0], 1u);
-        if (arrived == (unsigned)nblk - 1) {
-            atomicExch(&bar[0], 0u);
-            __threadfence();
-            atomicExch(&bar[1], gen + 1);
-        } else {
-            // one memory round trip per poll; the failure flag is read on
-            // every 16th poll only
-            int it = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (++it > spin_max ||
-                    ((it & 15) == 0 && __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                    atomicExch(&bar[2], 1u);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
+        __hip_atomic_store(&flags[blockIdx.x], next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x < 64) {
+        int ok = 1;
+        for (int it = 0;; ++it) {
+            bool arrived = true;
+            for (int b = (int)threadIdx.x; b < nblk; b += 64)
+                arrived &= (int)(__hip_atomic_load(&flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - next) >= 0;
+            if (__ballot(!arrived) == 0) break;
+            if (it > spin_max ||
+                ((it & 15) == 15 && __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                if (threadIdx.x == 0) atomicExch(&bar[2], 1u);
+                ok = 0;
+                break;
             }
+            __builtin_amdgcn_s_sleep(1);
         }
         __threadfence();
-        s_ok = ok && !__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) s_ok = ok && !__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    ++gen;
+    gen = next;
     __syncthreads();
     return s_ok != 0;
 }
@@ -95,6 +98,9 @@ __device__ bool grid_barrier(unsigned* bar, int nblk, unsigned& gen, int spin_ma
 // rows, [kSparseCols..+64) pivot columns (positions).
 constexpr int WS_BAR = 0, WS_CNT = kSparseCount, WS_KEY = 8, WS_PR = kSparseRows, WS_PC = kSparseCols;
 static_assert(WS_KEY % 2 == 0 && WS_KEY + 6 <= WS_PR, "scan words fit, 8-byte aligned");
+constexpr int kMaxGrid = 256;                      // workgroups of one launch at most
+constexpr int WS_FLAGS = 512;                      // [512..512+kMaxGrid): barrier words
+static_assert(WS_PC + kLeafRows <= WS_FLAGS, "pivot columns before the barrier words");
 
 // A scan result: the first row (leaf-relative) with a nonzero residual at the
 // positions scanned, and its leftmost such position, as one ordered key
@@ -146,11 +152,12 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
     __shared__ int s_pos[kMaxChunks * 64];             // position of each own column
     const double P = mp.p, PI = mp.pinv;
     unsigned* bar = reinterpret_cast<unsigned*>(ws + WS_BAR);
+    unsigned* flags = reinterpret_cast<unsigned*>(ws + WS_FLAGS);
     const int tid = threadIdx.x, nblk = gridDim.x;
-    // the barrier's generation continues from the previous launch (its last
-    // barrier left the arrival count at zero), so nothing is reset per launch
-    unsigned gen = 0;
-    if (tid == 0) gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the barrier's generation continues from the previous launch (kept in
+    // bar[1]), so nothing is reset per launch
+    const unsigned gen0 = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned gen = gen0;
     const int lane = tid & 63, rg = tid >> 6;
     constexpr int RPT = kLeafRows / 4;  // rows per thread at most
     const int cstride = nblk * 64;
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
 
     for (int ch = rg; ch < nchunk; ch += 4) s_pos[ch * 64 + lane] = col_of(ch);
     if (blockIdx.x == 0 && tid < 3) *kword(tid) = kNoKey;
-    if (!grid_barrier(bar, nblk, gen, spin_max)) return;
+    if (!grid_barrier(bar, flags, nblk, gen, spin_max)) return;
     // first scan: every row's leftmost nonzero position >= t0
     {
         int best[RPT];
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
 
     int i = i0, t = t0, count = 0;
     while (i < b && t < N) {
-        if (!grid_barrier(bar, nblk, gen, spin_max)) return;
+        if (!grid_barrier(bar, flags, nblk, gen, spin_max)) return;
         // decide: the round's scan word is the first row from i with a
         // nonzero residual and its pivot position; then the physical column
         // that holds it, and the pivot's inverse
@@ -280,6 +287,9 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
         ++count;
     }
     if (blockIdx.x == 0 && tid == 0) {
+        // the generation reached, for the next launch (every workgroup has
+        // read bar[1] at its start, before the first barrier)
+        __hip_atomic_store(&bar[1], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ws[WS_CNT] = count;
         // the result for the host, in mapped memory: the pivot count, no
         // failure, then each pivot's position and row
@@ -294,7 +304,7 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
 
 }  // namespace
 
-int sparse_ws_ints() { return WS_PC + kLeafRows; }
+int sparse_ws_ints() { return WS_FLAGS + kMaxGrid; }
 
 template <typename T>
 int launch_sparse_leaf(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, ModP mp, int* ws,
@@ -310,9 +320,9 @@ int launch_sparse_leaf(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, i
         max_grid = std::max(1, cus * std::max(1, per));
     }
     const int cols = N - t0;
-    const int grid = std::max(1, std::min(max_grid, (cols + 63) / 64));
+    const int grid = std::max(1, std::min(std::min(max_grid, kMaxGrid), (cols + 63) / 64));
     if ((cols + grid * 64 - 1) / (grid * 64) > kMaxChunks) throw CupError{-3000};  // (N > 1M columns)
-    if (reset) CUP_HIP(hipMemsetAsync(ws, 0, sizeof(int) * 8, s));
+    if (reset) CUP_HIP(hipMemsetAsync(ws, 0, sizeof(int) * (WS_FLAGS + kMaxGrid), s));
     void* args[] = {&A, &lda, &b, &N, &i0, &t0, &mp, &ws, &spin_max, &mail, &seq};
     CUP_HIP(hipLaunchCooperativeKernel((const void*)sparse_leaf_kernel<T>, dim3(grid), dim3(SPT), args, 0, s));
     return grid;
