@@ -63,11 +63,17 @@ constexpr int kTriNB = 64;      // order of a triangular leaf block
 // Stop reasons of the window elimination.
 enum WindowStop { STOP_ROWS = 0, STOP_WINDOW = 1, STOP_ZERO_ROW = 2, STOP_FAIL = 3 };
 
+// Rows of the largest block the rank-deficient (sparse) path takes at once:
+// a node of two leaves.  (Nodes of four leaves were measured slower: each
+// pivot's update then sweeps up to 255 rows below it, where two-leaf nodes
+// leave most of that work to the batched Schur products of their parents.)
+constexpr int kSparseNodeRows = 128;
+
 // Rows passed by value to the row-move kernel.
 struct MoveList {
     int n;
-    int dst[kLeafRows];
-    int src[kLeafRows];
+    int dst[kSparseNodeRows];
+    int src[kSparseNodeRows];
 };
 
 // A composed permutation of at most kGatherMax positions (columns) or
@@ -162,13 +168,15 @@ template <typename T>
 void launch_row_scan(hipStream_t s, const T* A, int64_t lda, int i0, int b, int t0, int N,
                      int* out, unsigned long long* mail = nullptr, unsigned seq = 0);
 
-// Words of the host mailbox: the window's result (2 + kLeafRows), then the
-// row scan's (kLeafRows).
-constexpr int kMailScan = 2 + kLeafRows;
-constexpr int kMailWords = kMailScan + kLeafRows;
+// Words of the host mailbox: a result count and status, then one word per
+// pivot (the window's columns, at most kLeafRows; the sparse path's
+// positions, at most kSparseNodeRows), then one word per row (the row scan's
+// results, the sparse path's pivot rows).
+constexpr int kMailScan = 2 + kSparseNodeRows;
+constexpr int kMailWords = kMailScan + kSparseNodeRows;
 
-// The rest of a rank-deficient leaf (see k_sparse.hip): rows [i0, b) from
-// position t0, one cooperative launch; ws holds sparse_ws_ints() device ints
+// The rest of a rank-deficient leaf or node of b <= kSparseNodeRows rows (see
+// k_sparse.hip): rows [i0, b) from position t0, one cooperative launch; ws holds sparse_ws_ints() device ints
 // and receives the pivot count at ws[kSparseCount], the pivot rows at
 // ws[kSparseRows + k] and positions at ws[kSparseCols + k], and posts them
 // to the host mailbox, tagged with seq: the count in mail[0], 0 in mail[1],
@@ -178,7 +186,7 @@ constexpr int kMailWords = kMailScan + kLeafRows;
 // caller (applied in that order to the leaf's rows [0, b)).  The grid
 // barrier's words in ws carry over from launch to launch: `reset` zeroes
 // them (first use, or after a failure).
-constexpr int kSparseCount = 4, kSparseRows = 200, kSparseCols = 264;
+constexpr int kSparseCount = 4, kSparseRows = 16, kSparseCols = 16 + kSparseNodeRows;
 int sparse_ws_ints();
 template <typename T>
 int launch_sparse_leaf(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, ModP mp, int* ws,

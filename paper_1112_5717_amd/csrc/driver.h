@@ -866,6 +866,40 @@ int sparse_rest(Ctx& c, T* A, int64_t lda, int b, int N, int i, int t, std::vect
     return cnt;
 }
 
+// U rows up: for the pivots in order, the pivot row's part right of its
+// position moves to the row of that index (Algorithm 6's row move).
+template <typename T>
+void compact_u_rows(Ctx& c, T* A, int64_t lda, int N, const std::vector<int>& piv_rows)
+{
+    MoveList ml;
+    ml.n = 0;
+    for (int s = 0; s < (int)piv_rows.size(); ++s)
+        if (piv_rows[s] != s) {
+            ml.dst[ml.n] = s;
+            ml.src[ml.n] = piv_rows[s];
+            ++ml.n;
+        }
+    launch_rowmove_list<T>(c.s, A, lda, N, ml);
+}
+
+// A node of up to kSparseNodeRows rows after a leaf with few pivots: every
+// row in order on the sparse path (one launch, whatever the node's depth),
+// then one row move.  The decisions, and so the results, are those of the
+// node's recursion (Algorithm 6's pivots are those of a row-by-row
+// elimination, and its row moves at every level together bring the U rows
+// up in pivot order).  The next node stays on this path while the pivots
+// are fewer than 16 per 64 rows.
+template <typename T>
+int sparse_node(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& P,
+                std::vector<int64_t>& Q)
+{
+    std::vector<int> rows;
+    const int r = sparse_rest(c, A, lda, m, n, 0, 0, P, Q, rows);
+    c.sparse_next = (int64_t)r * kLeafRows < (int64_t)kSparseAfter * m;
+    compact_u_rows(c, A, lda, n, rows);
+    return r;
+}
+
 template <typename T>
 int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
              std::vector<int64_t>& Q)
@@ -990,15 +1024,7 @@ int cup_leaf(Ctx& c, T* A, int64_t lda, int b, int N, std::vector<int64_t>& P,
             }
         }
     }
-    MoveList ml;
-    ml.n = 0;
-    for (int s = 0; s < (int)piv_rows.size(); ++s)
-        if (piv_rows[s] != s) {
-            ml.dst[ml.n] = s;
-            ml.src[ml.n] = piv_rows[s];
-            ++ml.n;
-        }
-    launch_rowmove_list<T>(c.s, A, lda, N, ml);
+    compact_u_rows(c, A, lda, N, piv_rows);
     return t;
 }
 
@@ -1014,6 +1040,7 @@ int cup_rec(Ctx& c, T* A, int64_t lda, int m, int n, std::vector<int64_t>& P,
 {
     if (m <= 0 || n <= 0) return 0;
     if (m <= kLeafRows) return cup_leaf(c, A, lda, m, n, P, Q);
+    if (c.sparse_next && m <= kSparseNodeRows) return sparse_node(c, A, lda, m, n, P, Q);
     const int k = split_at(m, kLeafRows);
     const size_t p0 = P.size(), q0 = Q.size();
     if (c.log) std::fprintf(stderr, "[cup] node m=%d n=%d k=%d\n", m, n, k);

@@ -98,9 +98,9 @@ __device__ bool grid_barrier(unsigned* bar, unsigned* flags, int nblk, unsigned&
 // rows, [kSparseCols..+64) pivot columns (positions).
 constexpr int WS_BAR = 0, WS_CNT = kSparseCount, WS_KEY = 8, WS_PR = kSparseRows, WS_PC = kSparseCols;
 static_assert(WS_KEY % 2 == 0 && WS_KEY + 6 <= WS_PR, "scan words fit, 8-byte aligned");
-constexpr int kMaxGrid = 256;                      // workgroups of one launch at most
-constexpr int WS_FLAGS = 512;                      // [512..512+kMaxGrid): barrier words
-static_assert(WS_PC + kLeafRows <= WS_FLAGS, "pivot columns before the barrier words");
+static_assert(WS_PR + kSparseNodeRows <= WS_PC, "pivot rows before the pivot columns");
+constexpr int kMaxGrid = 256;                                // workgroups of one launch at most
+constexpr int WS_FLAGS = WS_PC + kSparseNodeRows;            // then the barrier words
 
 // A scan result: the first row (leaf-relative) with a nonzero residual at the
 // positions scanned, and its leftmost such position, as one ordered key
@@ -138,17 +138,17 @@ constexpr int kMaxChunks = 64;  // 64-column chunks per workgroup at most
 // pivot and the multipliers, in that column) is final when the round
 // starts: one grid barrier per pivot.  The exchanges are applied to the
 // leaf's rows afterwards (by the host, as one composed gather).
-template <typename T>
+template <typename T, int MAXR>
 __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int64_t lda, int b, int N,
                                                           int i0, int t0, ModP mp, int* __restrict__ ws,
                                                           int spin_max, unsigned long long* __restrict__ mail,
                                                           unsigned seq)
 {
     __shared__ unsigned long long s_keys[SPT / 64];
-    __shared__ double s_m[kLeafRows];
+    __shared__ double s_m[MAXR];
     __shared__ int s_p, s_j, s_pc;
     __shared__ double s_iv;
-    __shared__ int s_ht[kLeafRows], s_hj[kLeafRows];  // exchanges so far (positions)
+    __shared__ int s_ht[MAXR], s_hj[MAXR];  // exchanges so far (positions)
     __shared__ int s_pos[kMaxChunks * 64];             // position of each own column
     const double P = mp.p, PI = mp.pinv;
     unsigned* bar = reinterpret_cast<unsigned*>(ws + WS_BAR);
@@ -159,7 +159,6 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
     const unsigned gen0 = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned gen = gen0;
     const int lane = tid & 63, rg = tid >> 6;
-    constexpr int RPT = kLeafRows / 4;  // rows per thread at most
     const int cstride = nblk * 64;
     const int nchunk = (N - t0 + cstride - 1) / cstride;  // own chunks (<= kMaxChunks)
     auto col_of = [&](int ch) { return t0 + blockIdx.x * 64 + ch * cstride + lane; };
@@ -168,28 +167,29 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
     for (int ch = rg; ch < nchunk; ch += 4) s_pos[ch * 64 + lane] = col_of(ch);
     if (blockIdx.x == 0 && tid < 3) *kword(tid) = kNoKey;
     if (!grid_barrier(bar, flags, nblk, gen, spin_max)) return;
-    // first scan: every row's leftmost nonzero position >= t0
+    // first scan: the first row from i0 with a nonzero at a position >= t0,
+    // and its leftmost one, as this workgroup sees them (rows in groups of
+    // up to 128, sixteen per thread and 64-row pass)
     {
-        int best[RPT];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) best[k] = N;
+        unsigned long long key = kNoKey;
         for (int ch = 0; ch < nchunk; ++ch) {
             const int c = col_of(ch);
-            T x[RPT];
+            constexpr int GP = MAXR >= 128 ? 2 : 1;  // 64-row passes per group
+            for (int g0 = i0; g0 < b; g0 += 64 * GP) {
+                T x[GP][16];
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                const int r = i0 + rg + 4 * k;
-                x[k] = (c < N && r < b) ? A[(int64_t)r * lda + c] : (T)0;
+                for (int ps = 0; ps < GP; ++ps)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const int r = g0 + 64 * ps + rg + 4 * k;
+                        x[ps][k] = (c < N && r < b) ? A[(int64_t)r * lda + c] : (T)0;
+                    }
+#pragma unroll
+                for (int ps = 0; ps < GP; ++ps)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        if (x[ps][k] != 0) key = min(key, scan_key(g0 + 64 * ps + rg + 4 * k, c));
             }
-#pragma unroll
-            for (int k = 0; k < RPT; ++k)
-                if (x[k] != 0) best[k] = min(best[k], c);
-        }
-        unsigned long long key = kNoKey;
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int r = i0 + rg + 4 * k;
-            if (r < b && best[k] < N) key = min(key, scan_key(r, best[k]));
         }
         fold_key(key, s_keys, kword(0));
     }
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
         const double iv = s_iv;
         // the multipliers: the rows' entries at the pivot's column (final:
         // that column is never written again in the leaf)
-        for (int r = tid; r < kLeafRows; r += SPT) s_m[r] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + pc) : 0.0;
+        for (int r = tid; r < MAXR; r += SPT) s_m[r] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + pc) : 0.0;
         // positions t and j exchange among own columns; the scan words two
         // rounds ahead start empty (last read before this round's barrier)
         const int ptc = [&] {
@@ -245,41 +245,43 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
 
         // update the rows below p in every own column at a position > t (the
         // pivot's column keeps their C entries), and scan them
-        int best[RPT];
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) best[k] = N;
+        unsigned long long key = kNoKey;
         T* prow = A + (int64_t)pr * lda;
         for (int ch = 0; ch < nchunk; ++ch) {
             const int c = col_of(ch);
             const int pos = (c < N) ? s_pos[ch * 64 + lane] : 0;
             if (c >= N || pos <= t) continue;
             const double u = mod_mul(ld_res(prow + c), iv, P, PI);
-            double x[RPT];
+            // rows in groups of up to 128 (sixteen per thread and 64-row
+            // pass, the loads of a group issued together), from the group
+            // holding the first row below p
+            constexpr int GP = MAXR >= 128 ? 2 : 1;  // passes per group
+            for (int g0 = ((pr + 1) >> 6) / GP * GP * 64; g0 < b; g0 += 64 * GP) {
+                double x[GP][16];
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                const int r = rg + 4 * k;
-                x[k] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + c) : 0.0;
-            }
+                for (int ps = 0; ps < GP; ++ps)
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                const int r = rg + 4 * k;
-                if (r > pr && r < b) {
-                    const double y = sub_mul(x[k], s_m[r], u, P, PI);
-                    st_res(A + (int64_t)r * lda + c, y);
-                    if (y != 0.0) best[k] = min(best[k], pos);
-                }
+                    for (int k = 0; k < 16; ++k) {
+                        const int r = g0 + 64 * ps + rg + 4 * k;
+                        x[ps][k] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + c) : 0.0;
+                    }
+#pragma unroll
+                for (int ps = 0; ps < GP; ++ps)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const int r = g0 + 64 * ps + rg + 4 * k;
+                        if (r > pr && r < b) {
+                            const double y = sub_mul(x[ps][k], s_m[r], u, P, PI);
+                            st_res(A + (int64_t)r * lda + c, y);
+                            if (y != 0.0) key = min(key, scan_key(r, pos));
+                        }
+                    }
             }
         }
         __syncthreads();  // every read of row p is done before it is rescaled
         for (int ch = 0; ch < nchunk; ++ch) {
             const int c = col_of(ch);
             if (rg == 0 && c < N && s_pos[ch * 64 + lane] > t) st_res(prow + c, mod_mul(ld_res(prow + c), iv, P, PI));
-        }
-        unsigned long long key = kNoKey;
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int r = rg + 4 * k;
-            if (r > pr && r < b && best[k] < N) key = min(key, scan_key(r, best[k]));
         }
         fold_key(key, s_keys, kword(count + 1));
         i = pr + 1;
@@ -306,17 +308,16 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
 
 int sparse_ws_ints() { return WS_FLAGS + kMaxGrid; }
 
-template <typename T>
-int launch_sparse_leaf(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, ModP mp, int* ws,
-                       int spin_max, bool reset, unsigned long long* mail, unsigned seq)
+template <typename T, int MAXR>
+int launch_sparse(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, ModP mp, int* ws,
+                  int spin_max, bool reset, unsigned long long* mail, unsigned seq)
 {
-    if (b <= i0 || N <= t0) return 0;
     static int max_grid = 0;
     if (!max_grid) {
         int dev = 0, cus = 0, per = 0;
         CUP_HIP(hipGetDevice(&dev));
         CUP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, sparse_leaf_kernel<T>, SPT, 0));
+        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, sparse_leaf_kernel<T, MAXR>, SPT, 0));
         max_grid = std::max(1, cus * std::max(1, per));
     }
     const int cols = N - t0;
@@ -324,8 +325,19 @@ int launch_sparse_leaf(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, i
     if ((cols + grid * 64 - 1) / (grid * 64) > kMaxChunks) throw CupError{-3000};  // (N > 1M columns)
     if (reset) CUP_HIP(hipMemsetAsync(ws, 0, sizeof(int) * (WS_FLAGS + kMaxGrid), s));
     void* args[] = {&A, &lda, &b, &N, &i0, &t0, &mp, &ws, &spin_max, &mail, &seq};
-    CUP_HIP(hipLaunchCooperativeKernel((const void*)sparse_leaf_kernel<T>, dim3(grid), dim3(SPT), args, 0, s));
+    CUP_HIP(hipLaunchCooperativeKernel((const void*)sparse_leaf_kernel<T, MAXR>, dim3(grid), dim3(SPT), args, 0, s));
     return grid;
+}
+
+template <typename T>
+int launch_sparse_leaf(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, ModP mp, int* ws,
+                       int spin_max, bool reset, unsigned long long* mail, unsigned seq)
+{
+    if (b <= i0 || N <= t0) return 0;
+    if (b > kSparseNodeRows) throw CupError{-3000};
+    if (b <= kLeafRows)
+        return launch_sparse<T, kLeafRows>(s, A, lda, b, N, i0, t0, mp, ws, spin_max, reset, mail, seq);
+    return launch_sparse<T, kSparseNodeRows>(s, A, lda, b, N, i0, t0, mp, ws, spin_max, reset, mail, seq);
 }
 
 #define CUP_INST(T)                                                                                   \
