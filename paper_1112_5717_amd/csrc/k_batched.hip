@@ -49,6 +49,7 @@
 #include "batched_tune.h"
 
 #include "modarith.h"
+#include "tri64.h"
 
 namespace cup {
 
@@ -75,18 +76,22 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
-// Inverse of a nonzero residue, a^(p-2) (Fermat).  For p < 2^25 the chain
-// keeps its values in [-p, 2p) (products below 4p^2 < 2^53) and reduces
-// fully once at the end; larger p take the exact chain.
+// Inverse of a nonzero residue a in (-p, p), a^(p-2) (Fermat), for
+// p < 2^26: square and multiply over the 26 bits of p - 2, unrolled and
+// without branches (a bit of the exponent selects the product), every value
+// kept in (-p, p) by the three-operation rounding, so every product is
+// below p^2 < 2^52 and exact.  The result is in (-p, p).
 __device__ __forceinline__ double inv_pivot(double a, double p, double pinv)
 {
-    if (p >= 33554432.0) return mod_inv(a, p, pinv);
+    const unsigned e = (unsigned)p - 2u;
     double r = 1.0, b = a;
-    for (int64_t e = (int64_t)p - 2; e > 0; e >>= 1) {
-        if (e & 1) r = red_lazy(r * b, p, pinv);
-        b = red_lazy(b * b, p, pinv);
+#pragma unroll
+    for (int i = 0; i < 26; ++i) {
+        const double rb = red_near(r * b, p, pinv);
+        r = ((e >> i) & 1u) ? rb : r;
+        b = red_near(b * b, p, pinv);
     }
-    return mod_red(r, p, pinv);
+    return r;
 }
 
 // f(std::integral_constant<int, 0>), ..., f(..., Q - 1): the index reaches
@@ -242,16 +247,20 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
         int cnt = 0;
 
         // 2. left-looking elimination against U rows 0..t-1.  Thread tid
-        // stages position tid % NP of SPT consecutive rows of a chunk.
+        // stages position tid % NP of SPT consecutive rows of a chunk.  The
+        // loads read clamped (always valid) addresses and the entries that
+        // are not U entries are zeroed only when the chunk goes to LDS, so
+        // that no load waits on the one before it.
         const int nch = (t + CH - 1) / CH;
         const int spos = tid % NP, se0 = (tid / NP) * SPT;
         int stg[SPT];
         auto fetch = [&](int ch) __attribute__((always_inline)) {
 #pragma unroll
             for (int e = 0; e < SPT; ++e) {
-                const int sr = ch * CH + se0 + e;
-                const int v = (int)A[(int64_t)min(sr, t - 1) * ld + min(spos, N - 1)];
-                stg[e] = (sr < t && spos > sr && spos < N) ? v : 0;
+                const int sr = min(ch * CH + se0 + e, t - 1);
+                // a global-memory load (not a flat one, which would also
+                // hold the LDS counter that the steps below wait on)
+                stg[e] = *(const __attribute__((address_space(1))) int*)(A + (int64_t)sr * ld + min(spos, N - 1));
             }
         };
         if (nch > 0) fetch(0);
@@ -261,7 +270,10 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
             for (; ch < nch && ch * CH < 64 * (qs + 1); ++ch) {
                 const int buf = ch & 1;
 #pragma unroll
-                for (int e = 0; e < SPT; ++e) ush[buf][se0 + e][spos] = (double)stg[e];
+                for (int e = 0; e < SPT; ++e) {
+                    const int sr = ch * CH + se0 + e;
+                    ush[buf][se0 + e][spos] = (sr < t && spos > sr && spos < N) ? (double)stg[e] : 0.0;
+                }
                 __syncthreads();
                 if (ch + 1 < nch) fetch(ch + 1);
                 const int s0 = ch * CH, s1 = min(t, s0 + CH);
@@ -329,14 +341,19 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
                     double ek[BK];
 #pragma unroll
                     for (int k = 0; k < BK; ++k) ek[k] = (ka == k) ? 1.0 : 0.0;
+                    // residues in (-p, p), zero exactly where the entry is
+                    // (positions past n hold zeros)
                     double rv[BQ];
 #pragma unroll
                     for (int q = qt; q < BQ; ++q) {
                         double v = x[0][q] * ek[0];
 #pragma unroll
                         for (int k = 1; k < BK; ++k) v = fma(x[k][q], ek[k], v);
-                        rv[q] = (q < nq) ? mod_red(v, P, PI) : 0.0;
+                        rv[q] = red_near(v, P, PI);
                     }
+                    // the entry at position t, read beside the pivot search:
+                    // it is the pivot unless that entry is zero
+                    const double vt = readlane_d(rv[qt], lt);
                     int j = -1;
 #pragma unroll
                     for (int q = BQ - 1; q >= qt; --q) {
@@ -345,12 +362,17 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
                         if (mk) j = 64 * q + __ffsll((long long)mk) - 1;
                     }
                     if (j >= 0) {
-                        const int qj = j >> 6, lj = j & 63;
-                        double piv = 0.0;
+                        double piv = vt;
+                        if (j != t) {
+                            const int qj = j >> 6, lj = j & 63;
+                            double sel = rv[qt];
 #pragma unroll
-                        for (int q = qt; q < BQ; ++q) piv = (q == qj) ? readlane_d(rv[q], lj) : piv;
-                        const double vt = readlane_d(rv[qt], lt);
+                            for (int q = qt + 1; q < BQ; ++q) sel = (q == qj) ? rv[q] : sel;
+                            piv = readlane_d(sel, lj);
+                        }
                         const double ipiv = inv_pivot(piv, P, PI);
+                        // the U row in (-p, p); its copy for the matrix is made
+                        // canonical when it is written out
                         int* ub = ublk[t - t0];
 #pragma unroll
                         for (int q = 0; q < BQ; ++q) {
@@ -359,7 +381,7 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
                                 urow[par][c] = 0.0;
                             } else {
                                 const double val = (c == j) ? vt : rv[q];
-                                const double u = (c > t && c < N) ? mod_mul(val, ipiv, P, PI) : 0.0;
+                                const double u = (c > t && c < N) ? red_near(val * ipiv, P, PI) : 0.0;
                                 urow[par][c] = u;
                                 ub[c] = (int)u;
                             }
@@ -447,7 +469,10 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
         for (int d = 0; d < nd; ++d) {
             const int tt = t0 + d;
             int64_t* ur = A + (int64_t)tt * ld;
-            for (int c = tt + 1 + tid; c < N; c += BT) ur[c] = ublk[d][c];
+            for (int c = tt + 1 + tid; c < N; c += BT) {
+                const int e = ublk[d][c];
+                ur[c] = (e < 0) ? e + (int)p64 : e;
+            }
         }
         if (tid < nd) {
             if (Pv) Pv[t0 + tid] = s_tj[tid];
