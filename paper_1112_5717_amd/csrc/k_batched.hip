@@ -5,7 +5,8 @@
 // The recursion of Algorithm 6 visits rows top-down and, with the pivot rule
 // of its base case (leftmost nonzero in the current column order), the
 // decisions it takes are those of a row-by-row elimination.  The kernel
-// groups rows into blocks of 32 and, for each block:
+// groups rows into blocks of 4 BW (BW waves per workgroup) and, for each
+// block:
 //
 //  1. loads the block into registers in the current column order (the
 //     composition of every transposition so far, kept in LDS);
@@ -13,13 +14,13 @@
 //     s = 0..t-1 the block's residual at position s is its entry of C, and
 //     the block rows lose C(., s) times U row s; the U rows live in the
 //     matrix (rows 0..t-1, positions after the diagonal) and pass through
-//     LDS in double-buffered chunks of 8, the next chunk in flight while the
-//     current one is used;
+//     LDS in double-buffered chunks of BW, the next chunk in flight while
+//     the current one is used;
 //  3. runs the row-by-row base case inside the block (rows whose residual is
 //     already zero need no step: later pivots leave them zero): the owner
 //     wave reduces the next row, finds its leftmost nonzero at positions >= t
 //     with a ballot, inverts the pivot and publishes the normalised U row in
-//     LDS; every wave swaps the two positions in its rows and subtracts
+//     LDS (entries in (-p, p); the matrix gets them canonical); every wave swaps the two positions in its rows and subtracts
 //     residual(i, t) times the U row from its later rows.  A step touches no
 //     global memory: the block's U rows, transpositions and profile entries
 //     collect in LDS;
@@ -30,14 +31,16 @@
 // Updates are not reduced one by one.  A multiplier is reduced lazily, to
 // x - floor(x / p) p in [-p, 2p), and a residual absorbs
 // floor((2^53 - p) / (2p (p - 1))) products of such a multiplier with a
-// canonical U entry before the block is reduced again.  A position that has
+// U entry of magnitude below p before the block is reduced again.  A position that has
 // become an entry of C is never updated again, so the C entries are the
 // residuals themselves, reduced once when the block is written back.
 //
-// Layout: 512 threads = 8 waves; wave w owns block rows w + 8k (k < 4);
-// lane l holds positions l + 64q (q < BQ) of those rows.  Three widths are
-// compiled (BQ = 2, 4, 8: n <= 128, 256, 512) so that a narrow matrix pays
-// for its own width only and leaves room for more workgroups per CU.  Inner
+// Layout: BW waves; wave w owns block rows w + BW k (k < 4); lane l holds
+// positions l + 64q (q < BQ) of those rows.  Three widths are compiled
+// (BQ = 2, 4, 8: n <= 128, 256, 512) so that a narrow matrix pays for its
+// own width only and leaves room for more workgroups per CU; the two wider
+// ones use 4 waves (blocks of 16 rows), so that two or three of their
+// workgroups fit a CU's registers and LDS together.  Inner
 // loops run over every register of the width without per-register or
 // per-row branches: positions past n and rows past m hold zeros, which the
 // updates leave zero.
@@ -55,12 +58,14 @@ namespace cup {
 
 namespace {
 
-constexpr int BW = 8;          // waves per workgroup
-constexpr int BT = 64 * BW;    // threads per workgroup
-constexpr int BR = 32;         // rows per block
-constexpr int BK = BR / BW;    // block rows per wave
+// A workgroup of BW waves (a template parameter: 8 for the narrowest class,
+// 4 for the wider ones, whose registers allow two waves per SIMD at most, so
+// that two of their workgroups share a CU and one's pivot chain overlaps the
+// other's updates) factors blocks of BR = 4 BW rows and stages U rows in
+// chunks of CH = BW.
+constexpr int BK = 4;          // block rows per wave
 constexpr int BQMAX = 8;       // position registers per lane at most (n <= 512)
-constexpr int CH = 8;          // U rows per LDS chunk of the left-looking phase
+constexpr int kClassWaves[3] = {8, 4, 4};  // BW of the width classes (n <= 128, <= 256, <= 512)
 
 // x - floor(x / p) p, in [-p, 2p) for |x| < 2^53 (the quotient from the
 // rounded reciprocal is off by at most one; the fma is exact).
@@ -126,9 +131,11 @@ struct BatchDesc {
 
 // The workgroup's shared state for one matrix (BQ position registers per
 // lane: n <= 64 BQ).
-template <int BQ>
+template <int BQ, int BW>
 struct BatchShared {
     static constexpr int NP = 64 * BQ;
+    static constexpr int BR = BK * BW;  // rows per block
+    static constexpr int CH = BW;       // U rows per LDS chunk of the left-looking phase
     int perm[NP];               // position -> original column
     double urow[2][NP];         // published U rows (zeros up to the pivot)
     int s_j[2];
@@ -144,12 +151,15 @@ struct BatchShared {
 
 // CUP of matrix idx by the whole workgroup (every thread calls it with the
 // same idx; it returns on every thread together).
-template <int BQ>
-__device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchShared<BQ>& sh)
+template <int BQ, int BW>
+__device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchShared<BQ, BW>& sh)
 {
     constexpr int NP = 64 * BQ;        // positions
+    constexpr int BT = 64 * BW;        // threads
+    constexpr int BR = BK * BW;        // rows per block
+    constexpr int CH = BW;             // U rows per staged chunk
     constexpr int SPT = CH * NP / BT;  // staged values per thread
-    static_assert(BT % NP == 0 && CH % (BT / NP) == 0, "threads tile the staged chunk");
+    static_assert((CH * NP) % BT == 0, "threads tile the staged chunk");
     auto& perm = sh.perm;
     auto& urow = sh.urow;
     auto& s_j = sh.s_j;
@@ -247,17 +257,18 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
         int cnt = 0;
 
         // 2. left-looking elimination against U rows 0..t-1.  Thread tid
-        // stages position tid % NP of SPT consecutive rows of a chunk.  The
-        // loads read clamped (always valid) addresses and the entries that
-        // are not U entries are zeroed only when the chunk goes to LDS, so
-        // that no load waits on the one before it.
+        // stages entries tid + BT e (e < SPT) of a chunk, row-major (row
+        // (tid + BT e) / NP, position (tid + BT e) % NP).  The loads read
+        // clamped (always valid) addresses and the entries that are not U
+        // entries are zeroed only when the chunk goes to LDS, so that no load
+        // waits on the one before it.
         const int nch = (t + CH - 1) / CH;
-        const int spos = tid % NP, se0 = (tid / NP) * SPT;
         int stg[SPT];
         auto fetch = [&](int ch) __attribute__((always_inline)) {
 #pragma unroll
             for (int e = 0; e < SPT; ++e) {
-                const int sr = min(ch * CH + se0 + e, t - 1);
+                const int v = tid + BT * e, spos = v % NP;
+                const int sr = min(ch * CH + v / NP, t - 1);
                 // a global-memory load (not a flat one, which would also
                 // hold the LDS counter that the steps below wait on)
                 stg[e] = *(const __attribute__((address_space(1))) int*)(A + (int64_t)sr * ld + min(spos, N - 1));
@@ -271,8 +282,9 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
                 const int buf = ch & 1;
 #pragma unroll
                 for (int e = 0; e < SPT; ++e) {
-                    const int sr = ch * CH + se0 + e;
-                    ush[buf][se0 + e][spos] = (sr < t && spos > sr && spos < N) ? (double)stg[e] : 0.0;
+                    const int v = tid + BT * e, spos = v % NP;
+                    const int sr = ch * CH + v / NP;
+                    ush[buf][v / NP][spos] = (sr < t && spos > sr && spos < N) ? (double)stg[e] : 0.0;
                 }
                 __syncthreads();
                 if (ch + 1 < nch) fetch(ch + 1);
@@ -560,10 +572,11 @@ __global__ void batched_reset_kernel(int* counters)
 // One persistent kernel per width class: each workgroup finds its class's
 // range of the order (or, without an order, walks every index), then takes
 // matrices one at a time from the class's counter until the class is done.
-template <int BQ>
-__global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch, int cls, int* counters)
+template <int BQ, int BW>
+__global__ __launch_bounds__(64 * BW) void batched_cup_kernel(BatchDesc g, int batch, int cls, int* counters)
 {
-    __shared__ BatchShared<BQ> sh;
+    constexpr int BT = 64 * BW;
+    __shared__ BatchShared<BQ, BW> sh;
     __shared__ int s_base, s_count, s_next;
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -595,7 +608,7 @@ __global__ __launch_bounds__(BT) void batched_cup_kernel(BatchDesc g, int batch,
             idx = k;
             if (width_class(g.n[idx]) != cls) continue;
         }
-        factor_one<BQ>(g, idx, sh);
+        factor_one<BQ, BW>(g, idx, sh);
     }
 }
 
@@ -627,9 +640,12 @@ int persistent_grid(int cls, const BatchTune& t)
         int dev = 0;
         CUP_HIP(hipGetDevice(&dev));
         CUP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[0], batched_cup_kernel<2>, BT, 0));
-        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[1], batched_cup_kernel<4>, BT, 0));
-        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[2], batched_cup_kernel<BQMAX>, BT, 0));
+        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[0], batched_cup_kernel<2, kClassWaves[0]>,
+                                                             64 * kClassWaves[0], 0));
+        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[1], batched_cup_kernel<4, kClassWaves[1]>,
+                                                             64 * kClassWaves[1], 0));
+        CUP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&maxper[2], batched_cup_kernel<BQMAX, kClassWaves[2]>,
+                                                             64 * kClassWaves[2], 0));
         cus = std::max(1, cus);
     }
     const int per = std::max(1, std::min(t.per_cu[cls], std::max(1, maxper[cls])));
@@ -656,11 +672,11 @@ ClassStreams& class_streams()
     return cs;
 }
 
-template <int BQ>
+template <int BQ, int BW>
 void launch_class(hipStream_t s, const BatchDesc& g, int batch, int cls, int* counters, const BatchTune& t)
 {
-    hipLaunchKernelGGL(batched_cup_kernel<BQ>, dim3(persistent_grid(cls, t)), dim3(BT), 0, s, g, batch, cls,
-                       counters);
+    hipLaunchKernelGGL((batched_cup_kernel<BQ, BW>), dim3(persistent_grid(cls, t)), dim3(64 * BW), 0, s, g, batch,
+                       cls, counters);
     CUP_HIP(hipGetLastError());
 }
 
@@ -689,18 +705,18 @@ void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_
     BatchDesc g{m, n, A, lda, p, rank, P, Q, info, order};
     const BatchTune t = batch_tune();
     if (!t.concurrent) {
-        launch_class<BQMAX>(s, g, batch, 2, counters, t);
-        launch_class<4>(s, g, batch, 1, counters, t);
-        launch_class<2>(s, g, batch, 0, counters, t);
+        launch_class<BQMAX, kClassWaves[2]>(s, g, batch, 2, counters, t);
+        launch_class<4, kClassWaves[1]>(s, g, batch, 1, counters, t);
+        launch_class<2, kClassWaves[0]>(s, g, batch, 0, counters, t);
         return;
     }
     ClassStreams& cs = class_streams();
     CUP_HIP(hipEventRecord(cs.fork, s));
     CUP_HIP(hipStreamWaitEvent(cs.side[0], cs.fork, 0));
     CUP_HIP(hipStreamWaitEvent(cs.side[1], cs.fork, 0));
-    launch_class<BQMAX>(s, g, batch, 2, counters, t);
-    launch_class<4>(cs.side[0], g, batch, 1, counters, t);
-    launch_class<2>(cs.side[1], g, batch, 0, counters, t);
+    launch_class<BQMAX, kClassWaves[2]>(s, g, batch, 2, counters, t);
+    launch_class<4, kClassWaves[1]>(cs.side[0], g, batch, 1, counters, t);
+    launch_class<2, kClassWaves[0]>(cs.side[1], g, batch, 0, counters, t);
     for (int k = 0; k < 2; ++k) {
         CUP_HIP(hipEventRecord(cs.join[k], cs.side[k]));
         CUP_HIP(hipStreamWaitEvent(s, cs.join[k], 0));

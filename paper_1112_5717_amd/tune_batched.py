@@ -29,7 +29,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--report", default=None)
-    ap.add_argument("--max-per-cu", type=int, nargs=3, default=[4, 2, 1])
+    ap.add_argument("--max-per-cu", type=int, nargs=3, default=[4, 3, 2])
     args = ap.parse_args()
 
     import numpy as np
