@@ -534,16 +534,21 @@ __device__ __forceinline__ double batch_cost(const int64_t* m, const int64_t* n,
 }
 
 // order[k]: the matrices by width class, and within a class by decreasing
-// cost m n min(m, n) (ties by index), by counting: thread i counts the
-// matrices that precede it.  Also zeroes the classes' work counters (the
-// persistent kernels that read them run after this kernel).
+// cost m n min(m, n) (ties by index), by counting: the position of matrix i
+// is the number of matrices that precede it.  Each matrix is counted by 16
+// threads (those of a 16-lane group, each over every 16th matrix of the
+// staged tiles), whose counts add up by shuffles.  Also zeroes the classes'
+// work counters (the persistent kernels that read them run after this
+// kernel).
+constexpr int kOrderSplit = 16;  // threads per counted matrix
 __global__ __launch_bounds__(256) void batched_order_kernel(const int64_t* m, const int64_t* n,
                                                             int batch, int* order, int* counters)
 {
     __shared__ double cost[256];
     __shared__ int cls[256];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i == 0)
+    const int sub = threadIdx.x % kOrderSplit;
+    const int i = blockIdx.x * (256 / kOrderSplit) + threadIdx.x / kOrderSplit;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int c = 0; c < 3; ++c) counters[c] = 0;
     const double mine = (i < batch) ? batch_cost(m, n, i) : 0.0;
     const int mc = (i < batch) ? width_class(n[i]) : 0;
@@ -555,13 +560,15 @@ __global__ __launch_bounds__(256) void batched_order_kernel(const int64_t* m, co
         cls[threadIdx.x] = (e < batch) ? width_class(n[e]) : 3;
         __syncthreads();
         const int lim = min(256, batch - j0);
-        for (int jj = 0; jj < lim; ++jj) {
+        for (int jj = sub; jj < lim; jj += kOrderSplit) {
             const double o = cost[jj];
             const int oc = cls[jj];
             pos += (oc < mc) || (oc == mc && ((o > mine) || (o == mine && j0 + jj < i)));
         }
     }
-    if (i < batch) order[pos] = i;
+#pragma unroll
+    for (int off = kOrderSplit / 2; off > 0; off >>= 1) pos += __shfl_xor(pos, off, kOrderSplit);
+    if (i < batch && sub == 0) order[pos] = i;
 }
 
 __global__ void batched_reset_kernel(int* counters)
@@ -694,8 +701,8 @@ void launch_batched_cup(hipStream_t s, int batch, const int64_t* m, const int64_
     int* counters = scratch;
     int* order = ordered ? scratch + kBatchCounters : nullptr;
     if (order)
-        hipLaunchKernelGGL(batched_order_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, m, n, batch,
-                           order, counters);
+        hipLaunchKernelGGL(batched_order_kernel, dim3((batch + 256 / kOrderSplit - 1) / (256 / kOrderSplit)),
+                           dim3(256), 0, s, m, n, batch, order, counters);
     else
         hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(64), 0, s, counters);
     CUP_HIP(hipGetLastError());
