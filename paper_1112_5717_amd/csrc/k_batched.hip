@@ -147,6 +147,10 @@ struct BatchShared {
     int ublk[BR][NP];           // U rows found in the current block
     int s_tj[BR];               // their transpositions t <-> s_tj
     int s_ti[BR];               // and their rows (entries of Q)
+    double s_pv[2];             // published pivot (as stored: scaled)
+    double s_piv[BR];           // the block's stored pivots
+    double s_isg[BR];           // 1 / Sigma_d (C entries of the block's columns)
+    double s_ipv[BR];           // 1 / stored pivot (U rows)
 };
 
 // CUP of matrix idx by the whole workgroup (every thread calls it with the
@@ -171,6 +175,10 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
     auto& ublk = sh.ublk;
     auto& s_tj = sh.s_tj;
     auto& s_ti = sh.s_ti;
+    auto& s_pv = sh.s_pv;
+    auto& s_piv = sh.s_piv;
+    auto& s_isg = sh.s_isg;
+    auto& s_ipv = sh.s_ipv;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -382,9 +390,9 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
                             for (int q = qt + 1; q < BQ; ++q) sel = (q == qj) ? rv[q] : sel;
                             piv = readlane_d(sel, lj);
                         }
-                        const double ipiv = inv_pivot(piv, P, PI);
-                        // the U row in (-p, p); its copy for the matrix is made
-                        // canonical when it is written out
+                        // the pivot row as it stands (scaled, in (-p, p)),
+                        // after the exchange, positions after t; it is
+                        // normalised when the block is written out
                         int* ub = ublk[t - t0];
 #pragma unroll
                         for (int q = 0; q < BQ; ++q) {
@@ -393,10 +401,14 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
                                 urow[par][c] = 0.0;
                             } else {
                                 const double val = (c == j) ? vt : rv[q];
-                                const double u = (c > t && c < N) ? red_near(val * ipiv, P, PI) : 0.0;
+                                const double u = (c > t && c < N) ? val : 0.0;
                                 urow[par][c] = u;
                                 ub[c] = (int)u;
                             }
+                        }
+                        if (lane == 0) {
+                            s_pv[par] = piv;
+                            s_piv[t - t0] = piv;
                         }
                     }
                     if (lane == 0) s_j[par] = j;
@@ -422,16 +434,23 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
                             for (int q = qt; q < BQ; ++q) x[k][q] = (q == qj && lane == lj) ? vt : x[k][q];
                         }
                     }
+                    // fraction free: a later row becomes piv row - m (pivot
+                    // row) at positions after t (m: its entry at t, kept
+                    // there as its C entry); every value stays in (-p, p)
+                    // and every product below p^2, so the fma is exact
+                    const double piv = s_pv[par];
                     double u[BQ];
 #pragma unroll
                     for (int q = qt; q < BQ; ++q) u[q] = urow[par][lane + 64 * q];
 #pragma unroll
                     for (int k = 0; k < BK; ++k) {
                         const int row = w + BW * k;
-                        {
-                            const double mk = (row > a && row < rows) ? red_lazy(readlane_d(x[k][qt], lt), P, PI) : 0.0;
+                        const bool later = row > a && row < rows;
+                        const double mk = readlane_d(x[k][qt], lt);
 #pragma unroll
-                            for (int q = qt; q < BQ; ++q) x[k][q] = fma(-mk, u[q], x[k][q]);
+                        for (int q = qt; q < BQ; ++q) {
+                            const double y = red_near(fma(piv, x[k][q], -(mk * u[q])), P, PI);
+                            x[k][q] = (later && (q > qt || lane > lt)) ? y : x[k][q];
                         }
                     }
                     if (j != t) {
@@ -464,9 +483,36 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
         }
         __syncthreads();
 
+        // The block's steps scaled its rows: after step t0 + d a row stands
+        // at Sigma_{d+1} = prod_{d' <= d} (stored pivot d') times its true
+        // value.  Wave 0 forms Sigma by a scan and the inverses in parallel
+        // lanes: 1 / Sigma_d for the C entries of column t0 + d, and
+        // 1 / (stored pivot d) for U row t0 + d.
+        const int nd = t - t0;
+        if (w == 0 && nd > 0) {
+            double sg = (lane < nd) ? s_piv[min(lane, BR - 1)] : 1.0;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const double o = __shfl_up(sg, off, 64);
+                if (lane >= off) sg = red_near(sg * o, P, PI);
+            }
+            // lane d: Sigma_{d+1}
+            const double isg_next = inv_pivot(sg, P, PI);
+            double isg = __shfl_up(isg_next, 1, 64);  // 1 / Sigma_d
+            double sg_prev = __shfl_up(sg, 1, 64);    // Sigma_d
+            if (lane == 0) {
+                isg = 1.0;
+                sg_prev = 1.0;
+            }
+            if (lane < nd) {
+                s_isg[lane] = isg;
+                s_ipv[lane] = red_near(sg_prev * isg_next, P, PI);
+            }
+        }
+        __syncthreads();
+
         // 4. the block's transpositions on the U rows of earlier blocks (one
         // thread per row, in order), its U rows, and its entries of P and Q
-        const int nd = t - t0;
         for (int sr = tid; sr < t0; sr += BT) {
             int64_t* ur = A + (int64_t)sr * ld;
             for (int d = 0; d < nd; ++d) {
@@ -481,10 +527,8 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
         for (int d = 0; d < nd; ++d) {
             const int tt = t0 + d;
             int64_t* ur = A + (int64_t)tt * ld;
-            for (int c = tt + 1 + tid; c < N; c += BT) {
-                const int e = ublk[d][c];
-                ur[c] = (e < 0) ? e + (int)p64 : e;
-            }
+            const double ip = s_ipv[d];
+            for (int c = tt + 1 + tid; c < N; c += BT) ur[c] = (int64_t)(int)mod_red((double)ublk[d][c] * ip, P, PI);
         }
         if (tid < nd) {
             if (Pv) Pv[t0 + tid] = s_tj[tid];
@@ -504,7 +548,10 @@ __device__ __forceinline__ void factor_one(const BatchDesc& g, int idx, BatchSha
                     const int c = lane + 64 * q;
                     if (q < nq && c <= i && c < N) {
                         const bool cpart = (c < tr) || (pv && c == tr);
-                        dst[c] = cpart ? (int64_t)(int)x[k][q] : 0;
+                        // columns of this block's steps: true value = stored / Sigma
+                        const double y = (c >= t0 && c < t) ? mod_red(x[k][q] * s_isg[min(c - t0, BR - 1)], P, PI)
+                                                            : x[k][q];
+                        dst[c] = cpart ? (int64_t)(int)y : 0;
                     }
                 }
             }

@@ -288,12 +288,13 @@ def test_batched_recipe_full_range(cup_lib):
 
 
 def test_batched_shapes_and_primes(cup_lib):
-    """Edge shapes, structured rank profiles, primes from 2 to below 2^26."""
+    """Edge shapes, structured rank profiles, primes from 2 to the largest below 2^26."""
     cases = []
     for (mm, nn, rr, p, seed) in [(1, 1, 1, 2, 0), (1, 512, 1, 3, 1), (512, 1, 1, 65521, 2),
                                   (512, 512, 512, 8388593, 3), (64, 64, 64, 2, 4), (65, 65, 40, 3, 5),
                                   (300, 500, 7, 33554393, 6), (130, 200, 130, 65521, 7),
-                                  (200, 130, 129, 8388593, 8), (129, 511, 100, 5, 9)]:
+                                  (200, 130, 129, 8388593, 8), (129, 511, 100, 5, 9),
+                                  (260, 300, 200, 67108859, 15), (256, 256, 256, 67108859, 16)]:
         cases.append((inputs.low_rank(mm, nn, rr, p, seed=seed), p))
     cases.append((np.zeros((70, 90), np.int64), 65521))
     cases.append((inputs.staircase(300, 257, 60, 8388593, seed=11)[0], 8388593))
