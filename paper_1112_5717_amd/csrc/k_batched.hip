@@ -19,21 +19,28 @@
 //  3. runs the row-by-row base case inside the block (rows whose residual is
 //     already zero need no step: later pivots leave them zero): the owner
 //     wave reduces the next row, finds its leftmost nonzero at positions >= t
-//     with a ballot, inverts the pivot and publishes the normalised U row in
-//     LDS (entries in (-p, p); the matrix gets them canonical); every wave swaps the two positions in its rows and subtracts
-//     residual(i, t) times the U row from its later rows.  A step touches no
-//     global memory: the block's U rows, transpositions and profile entries
-//     collect in LDS;
-//  4. writes the block's C entries (and the echelon zeros) and its U rows,
-//     applies its transpositions to the U rows of earlier blocks, and
-//     appends its entries of P and Q.
+//     with a ballot and publishes the row and its pivot in LDS; every wave
+//     swaps the two positions in its rows and, fraction free, replaces each
+//     later row by piv row - residual(i, t) pivot row at the positions after
+//     t, so that no modular inverse is on the chain of steps.  A step touches
+//     no global memory: the block's pivot rows, transpositions and profile
+//     entries collect in LDS;
+//  4. recovers the true values (after step t0 + d every row of the block
+//     stands at Sigma_{d+1}, the product of the stored pivots so far, times
+//     its true value: one scan and one Fermat inverse per lane for the whole
+//     block), writes the block's C entries (and the echelon zeros) and its
+//     normalised U rows, applies its transpositions to the U rows of earlier
+//     blocks, and appends its entries of P and Q.
 //
-// Updates are not reduced one by one.  A multiplier is reduced lazily, to
-// x - floor(x / p) p in [-p, 2p), and a residual absorbs
+// Left-looking updates are not reduced one by one.  A multiplier is reduced
+// lazily, to x - floor(x / p) p in [-p, 2p), and a residual absorbs
 // floor((2^53 - p) / (2p (p - 1))) products of such a multiplier with a
-// U entry of magnitude below p before the block is reduced again.  A position that has
-// become an entry of C is never updated again, so the C entries are the
-// residuals themselves, reduced once when the block is written back.
+// canonical U entry before the block is reduced again.  The base case's
+// fraction-free updates round every value to (-p, p), so both of its
+// products stay below p^2 and their difference below 2^53 for p < 2^26.  A
+// position that has become an entry of C is never updated again, so the C
+// entries are the residuals themselves (scaled by Sigma in the block's own
+// columns), reduced once when the block is written back.
 //
 // Layout: BW waves; wave w owns block rows w + BW k (k < 4); lane l holds
 // positions l + 64q (q < BQ) of those rows.  Three widths are compiled
