@@ -230,7 +230,7 @@ inline void ctx_set_prime(Ctx& c, int64_t p)
 }
 
 // The sparse leaf kernel's words in the small result buffer (sparse_ws_ints()
-// = 768 ints from here, within kSmallInts), the window pivot count below
+// = 1296 ints from here, within kSmallInts), the window pivot count below
 // which a leaf stopped by a zero row finishes there, and the bound on its
 // grid barriers' polls.
 constexpr int kSparseWs = 1024;

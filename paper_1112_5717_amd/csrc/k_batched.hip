@@ -88,23 +88,9 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
-// Inverse of a nonzero residue a in (-p, p), a^(p-2) (Fermat), for
-// p < 2^26: square and multiply over the 26 bits of p - 2, unrolled and
-// without branches (a bit of the exponent selects the product), every value
-// kept in (-p, p) by the three-operation rounding, so every product is
-// below p^2 < 2^52 and exact.  The result is in (-p, p).
-__device__ __forceinline__ double inv_pivot(double a, double p, double pinv)
-{
-    const unsigned e = (unsigned)p - 2u;
-    double r = 1.0, b = a;
-#pragma unroll
-    for (int i = 0; i < 26; ++i) {
-        const double rb = red_near(r * b, p, pinv);
-        r = ((e >> i) & 1u) ? rb : r;
-        b = red_near(b * b, p, pinv);
-    }
-    return r;
-}
+// Inverse of a nonzero residue in (-p, p), p < 2^26: the unrolled Fermat
+// chain of tri64.h.
+__device__ __forceinline__ double inv_pivot(double a, double p, double pinv) { return inv_fermat26(a, p, pinv); }
 
 // f(std::integral_constant<int, 0>), ..., f(..., Q - 1): the index reaches
 // the body as a constant, so register arrays indexed by it stay in registers.

@@ -13,19 +13,22 @@
 // columns and meet at grid barriers:
 //
 //   scan   each row's leftmost nonzero at positions >= t in the workgroup's
-//          columns -> atomicMin into that row's word;
-//   decide every workgroup finds the same first row p with a nonzero (the
-//          rows before it are zero rows: no pivot, nothing to do) and its
-//          pivot position j;
-//   read   the multipliers (the rows below p at the pivot's column) and the
-//          pivot;
+//          columns -> the workgroup's minimum (row, position) key, which
+//          its next barrier word carries to the others;
+//   decide every workgroup takes the minimum key over the grid from the
+//          barrier: the first row p with a nonzero (the rows before it are
+//          zero rows: no pivot, nothing to do) and its pivot position j;
+//   read   the pivot, the multipliers (the rows below p at the pivot's
+//          column) and the rows, issued together;
 //   update row p scaled by the pivot's inverse into U; rows below p lose
 //          their multiplier times U (their multiplier stays, as their C
 //          entry, at position t after the exchange of t and j); then the
 //          next scan of the rows below p, from position t + 1.
 //
-// One grid barrier per pivot, none per zero row.  Residues are carried as doubles: a product of two stays below
-// 2^52 (p < 2^26), so every update is exact before its reduction.
+// One grid barrier per pivot, none per zero row, and no other round trip
+// between the workgroups.  Residues are carried as doubles: a product of two
+// stays below 2^52 (p < 2^26), so every update is exact before its
+// reduction.
 #include <algorithm>
 
 #include "modarith.h"
@@ -52,30 +55,43 @@ __device__ __forceinline__ void post_word(unsigned long long* w, unsigned seq, i
                        __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Grid barrier over `nblk` co-resident workgroups, with no central counter:
-// each workgroup stores the generation it has reached into its own word of
-// `flags` and then reads every other workgroup's word (one wave, one word
-// per lane) until all have reached it; a workgroup already at the next
-// barrier counts as arrived.  One store and one round of loads per barrier,
-// and no atomic that 128 workgroups contend for.  Generations grow across
-// launches (the last is kept in bar[1]); the wait is bounded, and on timeout
-// the flag bar[2] is raised and every later barrier returns at once, so that
-// each workgroup leaves the kernel.
-__device__ bool grid_barrier(unsigned* bar, unsigned* flags, int nblk, unsigned& gen, int spin_max)
+// Grid barrier over `nblk` co-resident workgroups, with no central counter,
+// that also takes the minimum of the workgroups' scan keys: each workgroup
+// stores the generation it reaches and its key, as one 64-bit word, into its
+// own slot of the generation's parity, and one wave reads every slot (one
+// per lane) until all hold that generation, then folds their keys.  A
+// workgroup that has passed on to the next barrier writes the other parity,
+// and cannot reach the one after before this workgroup has left this one,
+// so a slot of the awaited parity holds either the awaited generation or an
+// older one.  One store and one round of loads per barrier, and no atomic
+// that the workgroups contend for.  Generations grow across launches (the
+// last is kept in bar[1]); the wait is bounded, and on timeout the flag
+// bar[2] is raised and every later barrier returns at once, so that each
+// workgroup leaves the kernel.
+constexpr int kMaxGrid = 256;  // workgroups of one launch at most
+__device__ bool grid_barrier(unsigned* bar, unsigned long long* slots, int nblk, unsigned& gen, int spin_max,
+                             unsigned key, unsigned* s_min)
 {
     __syncthreads();
     __shared__ int s_ok;
     const unsigned next = gen + 1;
+    unsigned long long* slot = slots + (next & 1u) * kMaxGrid;
     if (threadIdx.x == 0) {
         __threadfence();
-        __hip_atomic_store(&flags[blockIdx.x], next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&slot[blockIdx.x], ((unsigned long long)next << 32) | key, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
     if (threadIdx.x < 64) {
         int ok = 1;
+        unsigned mn = ~0u;
         for (int it = 0;; ++it) {
             bool arrived = true;
-            for (int b = (int)threadIdx.x; b < nblk; b += 64)
-                arrived &= (int)(__hip_atomic_load(&flags[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - next) >= 0;
+            mn = ~0u;
+            for (int b = (int)threadIdx.x; b < nblk; b += 64) {
+                const unsigned long long w = __hip_atomic_load(&slot[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                arrived &= (unsigned)(w >> 32) == next;
+                mn = min(mn, (unsigned)w);
+            }
             if (__ballot(!arrived) == 0) break;
             if (it > spin_max ||
                 ((it & 15) == 15 && __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
@@ -85,47 +101,48 @@ __device__ bool grid_barrier(unsigned* bar, unsigned* flags, int nblk, unsigned&
             }
             __builtin_amdgcn_s_sleep(1);
         }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mn = min(mn, (unsigned)__shfl_xor((int)mn, off, 64));
         __threadfence();
-        if (threadIdx.x == 0) s_ok = ok && !__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) {
+            s_ok = ok && !__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *s_min = mn;
+        }
     }
     gen = next;
     __syncthreads();
     return s_ok != 0;
 }
 
-// ws layout (ints): [0..3) barrier, [4] pivot count, [8..14) the scan words
-// (three 64-bit words, one per round in rotation), [kSparseRows..+64) pivot
-// rows, [kSparseCols..+64) pivot columns (positions).
-constexpr int WS_BAR = 0, WS_CNT = kSparseCount, WS_KEY = 8, WS_PR = kSparseRows, WS_PC = kSparseCols;
-static_assert(WS_KEY % 2 == 0 && WS_KEY + 6 <= WS_PR, "scan words fit, 8-byte aligned");
+// ws layout (ints): [0..3) barrier, [4] pivot count, [kSparseRows..) pivot
+// rows, [kSparseCols..) pivot columns (positions), then the barrier slots
+// (two parities of kMaxGrid 64-bit words).
+constexpr int WS_BAR = 0, WS_CNT = kSparseCount, WS_PR = kSparseRows, WS_PC = kSparseCols;
 static_assert(WS_PR + kSparseNodeRows <= WS_PC, "pivot rows before the pivot columns");
-constexpr int kMaxGrid = 256;                                // workgroups of one launch at most
-constexpr int WS_FLAGS = WS_PC + kSparseNodeRows;            // then the barrier words
+constexpr int WS_FLAGS = WS_PC + kSparseNodeRows;
+static_assert(WS_FLAGS % 2 == 0, "barrier slots 8-byte aligned");
 
-// A scan result: the first row (leaf-relative) with a nonzero residual at the
-// positions scanned, and its leftmost such position, as one ordered key
-// (row above position), so that the minimum over the workgroups' keys is the
-// next pivot.  No key: no nonzero left.
-constexpr unsigned long long kNoKey = ~0ull;
-__device__ __forceinline__ unsigned long long scan_key(int r, int pos)
+// A scan result: the first row (leaf-relative, < 128) with a nonzero
+// residual at the positions scanned, and its leftmost such position
+// (relative to the launch's first position, < 2^24), as one ordered 32-bit
+// key (row above position), so that the minimum over the workgroups' keys is
+// the next pivot.  No key: no nonzero left.
+constexpr unsigned kNoKey = ~0u;
+__device__ __forceinline__ unsigned scan_key(int r, int rel_pos)
 {
-    return ((unsigned long long)(unsigned)r << 32) | (unsigned)pos;
+    return ((unsigned)r << 24) | (unsigned)rel_pos;
 }
 
-// Minimum of the workgroup's keys, folded into *word by one atomic (thread 0).
-__device__ void fold_key(unsigned long long key, unsigned long long* s_keys, unsigned long long* word)
+// Minimum of the workgroup's keys (every thread gets it).
+__device__ unsigned wg_min_key(unsigned key, unsigned* s_keys)
 {
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(key, off, 64);
-        key = o < key ? o : key;
-    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) key = min(key, (unsigned)__shfl_xor((int)key, off, 64));
     if ((threadIdx.x & 63) == 0) s_keys[threadIdx.x >> 6] = key;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long k = s_keys[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) k = s_keys[w] < k ? s_keys[w] : k;
-        if (k != kNoKey) atomicMin(word, k);
-    }
+    unsigned k = s_keys[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) k = min(k, s_keys[w]);
+    return k;
 }
 constexpr int kMaxChunks = 64;  // 64-column chunks per workgroup at most
 
@@ -144,15 +161,13 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
                                                           int spin_max, unsigned long long* __restrict__ mail,
                                                           unsigned seq)
 {
-    __shared__ unsigned long long s_keys[SPT / 64];
-    __shared__ double s_m[MAXR];
-    __shared__ int s_p, s_j, s_pc;
-    __shared__ double s_iv;
+    __shared__ unsigned s_keys[SPT / 64];
+    __shared__ unsigned s_min;
     __shared__ int s_ht[MAXR], s_hj[MAXR];  // exchanges so far (positions)
-    __shared__ int s_pos[kMaxChunks * 64];             // position of each own column
+    __shared__ int s_pos[kMaxChunks * 64];  // position of each own column
     const double P = mp.p, PI = mp.pinv;
     unsigned* bar = reinterpret_cast<unsigned*>(ws + WS_BAR);
-    unsigned* flags = reinterpret_cast<unsigned*>(ws + WS_FLAGS);
+    unsigned long long* slots = reinterpret_cast<unsigned long long*>(ws + WS_FLAGS);
     const int tid = threadIdx.x, nblk = gridDim.x;
     // the barrier's generation continues from the previous launch (kept in
     // bar[1]), so nothing is reset per launch
@@ -162,16 +177,16 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
     const int cstride = nblk * 64;
     const int nchunk = (N - t0 + cstride - 1) / cstride;  // own chunks (<= kMaxChunks)
     auto col_of = [&](int ch) { return t0 + blockIdx.x * 64 + ch * cstride + lane; };
-    auto kword = [&](int k) { return reinterpret_cast<unsigned long long*>(ws + WS_KEY) + (k % 3); };
 
     for (int ch = rg; ch < nchunk; ch += 4) s_pos[ch * 64 + lane] = col_of(ch);
-    if (blockIdx.x == 0 && tid < 3) *kword(tid) = kNoKey;
-    if (!grid_barrier(bar, flags, nblk, gen, spin_max)) return;
     // first scan: the first row from i0 with a nonzero at a position >= t0,
     // and its leftmost one, as this workgroup sees them (rows in groups of
-    // up to 128, sixteen per thread and 64-row pass)
+    // up to 128, sixteen per thread and 64-row pass); its key reaches the
+    // other workgroups with the first barrier (the matrix was written by
+    // earlier launches on the stream, so no barrier precedes the scan)
+    unsigned wgkey;
     {
-        unsigned long long key = kNoKey;
+        unsigned key = kNoKey;
         for (int ch = 0; ch < nchunk; ++ch) {
             const int c = col_of(ch);
             constexpr int GP = MAXR >= 128 ? 2 : 1;  // 64-row passes per group
@@ -188,102 +203,107 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
                 for (int ps = 0; ps < GP; ++ps)
 #pragma unroll
                     for (int k = 0; k < 16; ++k)
-                        if (x[ps][k] != 0) key = min(key, scan_key(g0 + 64 * ps + rg + 4 * k, c));
+                        if (x[ps][k] != 0) key = min(key, scan_key(g0 + 64 * ps + rg + 4 * k, c - t0));
             }
         }
-        fold_key(key, s_keys, kword(0));
+        wgkey = wg_min_key(key, s_keys);
     }
 
     int i = i0, t = t0, count = 0;
     while (i < b && t < N) {
-        if (!grid_barrier(bar, flags, nblk, gen, spin_max)) return;
-        // decide: the round's scan word is the first row from i with a
-        // nonzero residual and its pivot position; then the physical column
-        // that holds it, and the pivot's inverse
+        if (!grid_barrier(bar, slots, nblk, gen, spin_max, wgkey, &s_min)) return;
+        // decide (every thread, from the minimum key): the first row from i
+        // with a nonzero residual and its pivot position
+        const unsigned key = s_min;
+        if (key == kNoKey) break;  // every remaining row is zero
+        const int pr = (int)(key >> 24);
+        const int j = t0 + (int)(key & 0xffffffu);
+        // the physical columns holding positions j and t before this round's
+        // exchange (the exchanges so far undone, latest first)
+        int pc = j, ptc = t;
+        for (int k = count - 1; k >= 0; --k) {
+            const int ht = s_ht[k], hj = s_hj[k];
+            pc = (pc == ht) ? hj : ((pc == hj) ? ht : pc);
+            ptc = (ptc == ht) ? hj : ((ptc == hj) ? ht : ptc);
+        }
         if (tid == 0) {
-            const unsigned long long key = __hip_atomic_load(kword(count), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int pr = (key == kNoKey) ? -1 : (int)(key >> 32);
-            const int jc = (key == kNoKey) ? N : (int)(key & 0xffffffffu);
-            int pc = jc;
-            for (int k = count - 1; k >= 0; --k)
-                pc = (pc == s_ht[k]) ? s_hj[k] : ((pc == s_hj[k]) ? s_ht[k] : pc);
-            s_p = pr;
-            s_j = jc;
-            s_pc = pc;
-            if (pr >= 0) {
-                s_iv = canon(inv_near(ld_res(A + (int64_t)pr * lda + pc), P, PI), P);
-                s_ht[count] = t;
-                s_hj[count] = jc;
+            s_ht[count] = t;
+            s_hj[count] = j;
+            if (blockIdx.x == 0) {
+                ws[WS_PR + count] = pr;
+                ws[WS_PC + count] = j;
             }
         }
-        __syncthreads();
-        const int pr = s_p, j = s_j, pc = s_pc;
-        if (pr < 0) break;  // every remaining row is zero
-        const double iv = s_iv;
-        // the multipliers: the rows' entries at the pivot's column (final:
-        // that column is never written again in the leaf)
-        for (int r = tid; r < MAXR; r += SPT) s_m[r] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + pc) : 0.0;
-        // positions t and j exchange among own columns; the scan words two
-        // rounds ahead start empty (last read before this round's barrier)
-        const int ptc = [&] {
-            int x = t;
-            for (int k = count - 1; k >= 0; --k) x = (x == s_ht[k]) ? s_hj[k] : ((x == s_hj[k]) ? s_ht[k] : x);
-            return x;
-        }();  // physical column at position t before the exchange
-        if (blockIdx.x == 0 && tid == 0) {
-            *kword(count + 2) = kNoKey;
-            ws[WS_PR + count] = pr;
-            ws[WS_PC + count] = j;
-        }
-        __syncthreads();
-        for (int ch = rg; ch < nchunk; ch += 4) {
-            const int c = col_of(ch);
-            if (c == pc && pc != ptc) s_pos[ch * 64 + lane] = t;
-            else if (c == ptc && pc != ptc) s_pos[ch * 64 + lane] = j;
-        }
-        __syncthreads();
+        // the pivot, read at once; its inverse (a chain of dependent
+        // operations) is formed after the first column's loads are issued
+        T* prow = A + (int64_t)pr * lda;
+        const double pv = ld_res(prow + pc);
+        double iv = 0.0;
+        bool have_iv = false;
 
         // update the rows below p in every own column at a position > t (the
         // pivot's column keeps their C entries), and scan them
-        unsigned long long key = kNoKey;
-        T* prow = A + (int64_t)pr * lda;
+        unsigned key2 = kNoKey;
         for (int ch = 0; ch < nchunk; ++ch) {
             const int c = col_of(ch);
-            const int pos = (c < N) ? s_pos[ch * 64 + lane] : 0;
-            if (c >= N || pos <= t) continue;
-            const double u = mod_mul(ld_res(prow + c), iv, P, PI);
+            if (c >= N) continue;
+            // positions t and j exchange among own columns (the same value
+            // from each of the column's four threads)
+            int pos = s_pos[ch * 64 + lane];
+            if (pc != ptc) pos = (c == pc) ? t : ((c == ptc) ? j : pos);
+            if (rg == 0) s_pos[ch * 64 + lane] = pos;
+            if (pos <= t) continue;
+            const double pu = ld_res(prow + c);
             // rows in groups of up to 128 (sixteen per thread and 64-row
-            // pass, the loads of a group issued together), from the group
-            // holding the first row below p
+            // pass), from the group holding the first row below p; the
+            // group's rows and multipliers (their entries in the pivot's
+            // column, final: it is never written again in the leaf) are
+            // loaded together
             constexpr int GP = MAXR >= 128 ? 2 : 1;  // passes per group
             for (int g0 = ((pr + 1) >> 6) / GP * GP * 64; g0 < b; g0 += 64 * GP) {
-                double x[GP][16];
+                double x[GP][16], m[GP][16];
 #pragma unroll
                 for (int ps = 0; ps < GP; ++ps)
 #pragma unroll
                     for (int k = 0; k < 16; ++k) {
                         const int r = g0 + 64 * ps + rg + 4 * k;
-                        x[ps][k] = (r > pr && r < b) ? ld_res(A + (int64_t)r * lda + c) : 0.0;
+                        const bool below = r > pr && r < b;
+                        x[ps][k] = below ? ld_res(A + (int64_t)r * lda + c) : 0.0;
+                        m[ps][k] = below ? ld_res(A + (int64_t)r * lda + pc) : 0.0;
                     }
+                if (!have_iv) {
+                    iv = inv_fermat26(pv, P, PI);
+                    have_iv = true;
+                }
+                const double u = mod_mul(pu, iv, P, PI);
 #pragma unroll
                 for (int ps = 0; ps < GP; ++ps)
 #pragma unroll
                     for (int k = 0; k < 16; ++k) {
                         const int r = g0 + 64 * ps + rg + 4 * k;
                         if (r > pr && r < b) {
-                            const double y = sub_mul(x[ps][k], s_m[r], u, P, PI);
+                            const double y = sub_mul(x[ps][k], m[ps][k], u, P, PI);
                             st_res(A + (int64_t)r * lda + c, y);
-                            if (y != 0.0) key = min(key, scan_key(r, pos));
+                            if (y != 0.0) key2 = min(key2, scan_key(r, pos - t0));
                         }
                     }
             }
         }
-        __syncthreads();  // every read of row p is done before it is rescaled
-        for (int ch = 0; ch < nchunk; ++ch) {
-            const int c = col_of(ch);
-            if (rg == 0 && c < N && s_pos[ch * 64 + lane] > t) st_res(prow + c, mod_mul(ld_res(prow + c), iv, P, PI));
+        // the workgroup's key (its barrier also orders every read of row p
+        // before the row is rescaled)
+        wgkey = wg_min_key(key2, s_keys);
+        if (rg == 0) {
+            for (int ch = 0; ch < nchunk; ++ch) {
+                const int c = col_of(ch);
+                if (c < N && s_pos[ch * 64 + lane] > t) {
+                    if (!have_iv) {
+                        iv = inv_fermat26(pv, P, PI);
+                        have_iv = true;
+                    }
+                    st_res(prow + c, mod_mul(ld_res(prow + c), iv, P, PI));
+                }
+            }
         }
-        fold_key(key, s_keys, kword(count + 1));
         i = pr + 1;
         ++t;
         ++count;
@@ -306,7 +326,7 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
 
 }  // namespace
 
-int sparse_ws_ints() { return WS_FLAGS + kMaxGrid; }
+int sparse_ws_ints() { return WS_FLAGS + 4 * kMaxGrid; }
 
 template <typename T, int MAXR>
 int launch_sparse(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0, ModP mp, int* ws,
@@ -323,7 +343,7 @@ int launch_sparse(hipStream_t s, T* A, int64_t lda, int b, int N, int i0, int t0
     const int cols = N - t0;
     const int grid = std::max(1, std::min(std::min(max_grid, kMaxGrid), (cols + 63) / 64));
     if ((cols + grid * 64 - 1) / (grid * 64) > kMaxChunks) throw CupError{-3000};  // (N > 1M columns)
-    if (reset) CUP_HIP(hipMemsetAsync(ws, 0, sizeof(int) * (WS_FLAGS + kMaxGrid), s));
+    if (reset) CUP_HIP(hipMemsetAsync(ws, 0, sizeof(int) * (size_t)sparse_ws_ints(), s));
     void* args[] = {&A, &lda, &b, &N, &i0, &t0, &mp, &ws, &spin_max, &mail, &seq};
     CUP_HIP(hipLaunchCooperativeKernel((const void*)sparse_leaf_kernel<T, MAXR>, dim3(grid), dim3(SPT), args, 0, s));
     return grid;

@@ -22,6 +22,23 @@ __device__ __forceinline__ double red_near(double x, double p, double pinv)
 
 __device__ __forceinline__ double canon(double x, double p) { return (x < 0.0) ? x + p : x; }
 
+// Inverse of a nonzero residue a in (-p, p), p < 2^26, in (-p, p): a^(p-2)
+// by square and multiply over the 26 bits of p - 2, unrolled and without
+// branches (a bit of the exponent selects the product), every value kept in
+// (-p, p) by red_near, so every product is below p^2 < 2^52 and exact.
+__device__ __forceinline__ double inv_fermat26(double a, double p, double pinv)
+{
+    const unsigned e = (unsigned)p - 2u;
+    double r = 1.0, b = a;
+#pragma unroll
+    for (int i = 0; i < 26; ++i) {
+        const double rb = red_near(r * b, p, pinv);
+        r = ((e >> i) & 1u) ? rb : r;
+        b = red_near(b * b, p, pinv);
+    }
+    return r;
+}
+
 // a^(p-2), the inverse of a nonzero residue (Fermat), by square and multiply
 // with every intermediate in (-p, p): one short rounding per product, and
 // every product below p^2 < 2^52.
