@@ -386,7 +386,7 @@ __global__ __launch_bounds__(WT) void window_kernel(T* __restrict__ A, int64_t l
         double sig_prev = __shfl_up(x, 1, 64);  // Sigma_lane
         if (lane == 0) sig_prev = 1.0;
         if (lane < d) {
-            double isig_next = inv_near(x, P, PI);  // 1 / Sigma_{lane+1}
+            double isig_next = inv_fermat26(x, P, PI);  // 1 / Sigma_{lane+1}
             s_isig[lane + 1] = isig_next;
             const double ipiv = red_near(sig_prev * isig_next, P, PI);  // 1 / piv_lane
             s_ipiv[lane] = ipiv;

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void diag_prep_kernel(T* __restrict__ A, int64
         }
         return;
     }
-    if (tid < NB) dinv[tid] = (unit || tid >= nb) ? 1.0 : mod_inv(M[tid][tid], P, PI);
+    if (tid < NB) dinv[tid] = (unit || tid >= nb) ? 1.0 : canon(inv_fermat26(M[tid][tid], P, PI), P);
     __syncthreads();
     if constexpr (BIG) {
         if (tid < NB) inverse_column_big(M, dinv, 0, tid, X, P, PI);

@@ -29,25 +29,6 @@ __device__ __forceinline__ double mod_mul(double a, double b, double p, double p
     return mod_red(a * b, p, pinv);
 }
 
-// a^e mod p by square-and-multiply.
-__device__ inline double mod_pow(double a, int64_t e, double p, double pinv)
-{
-    double r = 1.0;
-    double b = a;
-    while (e > 0) {
-        if (e & 1) r = mod_mul(r, b, p, pinv);
-        b = mod_mul(b, b, p, pinv);
-        e >>= 1;
-    }
-    return r;
-}
-
-// Inverse of a nonzero residue (Fermat).  p = 2 gives 1 = 1^{-1}.
-__device__ inline double mod_inv(double a, double p, double pinv)
-{
-    return mod_pow(a, (int64_t)p - 2, p, pinv);
-}
-
 // Residue loads and stores: int64 storage holds values below 2^26, so its low
 // 32-bit word carries the value; int8 storage holds values below 2^7.
 __device__ __forceinline__ double ld_res(const int64_t* a) { return (double)(int)(*a); }

@@ -39,19 +39,6 @@ __device__ __forceinline__ double inv_fermat26(double a, double p, double pinv)
     return r;
 }
 
-// a^(p-2), the inverse of a nonzero residue (Fermat), by square and multiply
-// with every intermediate in (-p, p): one short rounding per product, and
-// every product below p^2 < 2^52.
-__device__ inline double inv_near(double a, double p, double pinv)
-{
-    double r = 1.0, b = a;
-    for (int64_t e = (int64_t)p - 2; e > 0; e >>= 1) {
-        if (e & 1) r = red_near(r * b, p, pinv);
-        b = red_near(b * b, p, pinv);
-    }
-    return r;
-}
-
 // Workgroup barrier that orders LDS accesses only: global stores still in
 // flight are not waited for (the usual barrier waits for every memory
 // operation of every wave).
