@@ -30,6 +30,7 @@
 // stays below 2^52 (p < 2^26), so every update is exact before its
 // reduction.
 #include <algorithm>
+#include <type_traits>
 
 #include "modarith.h"
 #include "tri64.h"
@@ -184,12 +185,34 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
     // up to 128, sixteen per thread and 64-row pass); its key reaches the
     // other workgroups with the first barrier (the matrix was written by
     // earlier launches on the stream, so no barrier precedes the scan)
+    // The rows of the first own chunk (thread: rows 64 ps + rg + 4 k of its
+    // column, every row of the node) stay in registers for the whole launch:
+    // a round reads only the multipliers and writes the updated rows back
+    // (other workgroups read them as multipliers and pivots).
+    constexpr int GP = MAXR >= 128 ? 2 : 1;  // 64-row passes per group of rows
+    double xr[GP][16];
     unsigned wgkey;
     {
         unsigned key = kNoKey;
-        for (int ch = 0; ch < nchunk; ++ch) {
+        {
+            const int c = col_of(0);
+#pragma unroll
+            for (int ps = 0; ps < GP; ++ps)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int r = 64 * ps + rg + 4 * k;
+                    xr[ps][k] = (c < N && r < b) ? ld_res(A + (int64_t)r * lda + c) : 0.0;
+                }
+#pragma unroll
+            for (int ps = 0; ps < GP; ++ps)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int r = 64 * ps + rg + 4 * k;
+                    if (r >= i0 && xr[ps][k] != 0.0) key = min(key, scan_key(r, c - t0));
+                }
+        }
+        for (int ch = 1; ch < nchunk; ++ch) {
             const int c = col_of(ch);
-            constexpr int GP = MAXR >= 128 ? 2 : 1;  // 64-row passes per group
             for (int g0 = i0; g0 < b; g0 += 64 * GP) {
                 T x[GP][16];
 #pragma unroll
@@ -244,22 +267,25 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
         // update the rows below p in every own column at a position > t (the
         // pivot's column keeps their C entries), and scan them
         unsigned key2 = kNoKey;
-        for (int ch = 0; ch < nchunk; ++ch) {
+        // one own column: the exchange of positions t and j, then (at a
+        // position after t) the update and scan of the rows below p, from
+        // the registers (first chunk) or from memory (the others)
+        auto column = [&](int ch, auto in_regs) __attribute__((always_inline)) {
+            constexpr bool R = decltype(in_regs)::value;
             const int c = col_of(ch);
-            if (c >= N) continue;
+            if (c >= N) return;
             // positions t and j exchange among own columns (the same value
             // from each of the column's four threads)
             int pos = s_pos[ch * 64 + lane];
             if (pc != ptc) pos = (c == pc) ? t : ((c == ptc) ? j : pos);
             if (rg == 0) s_pos[ch * 64 + lane] = pos;
-            if (pos <= t) continue;
+            if (pos <= t) return;
             const double pu = ld_res(prow + c);
             // rows in groups of up to 128 (sixteen per thread and 64-row
             // pass), from the group holding the first row below p; the
-            // group's rows and multipliers (their entries in the pivot's
-            // column, final: it is never written again in the leaf) are
-            // loaded together
-            constexpr int GP = MAXR >= 128 ? 2 : 1;  // passes per group
+            // group's multipliers (their entries in the pivot's column,
+            // final: it is never written again in the leaf) and, outside the
+            // registers, its rows are loaded together
             for (int g0 = ((pr + 1) >> 6) / GP * GP * 64; g0 < b; g0 += 64 * GP) {
                 double x[GP][16], m[GP][16];
 #pragma unroll
@@ -268,7 +294,10 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
                     for (int k = 0; k < 16; ++k) {
                         const int r = g0 + 64 * ps + rg + 4 * k;
                         const bool below = r > pr && r < b;
-                        x[ps][k] = below ? ld_res(A + (int64_t)r * lda + c) : 0.0;
+                        if (R)
+                            x[ps][k] = xr[ps][k];
+                        else
+                            x[ps][k] = below ? ld_res(A + (int64_t)r * lda + c) : 0.0;
                         m[ps][k] = below ? ld_res(A + (int64_t)r * lda + pc) : 0.0;
                     }
                 if (!have_iv) {
@@ -284,11 +313,14 @@ __global__ __launch_bounds__(SPT) void sparse_leaf_kernel(T* __restrict__ A, int
                         if (r > pr && r < b) {
                             const double y = sub_mul(x[ps][k], m[ps][k], u, P, PI);
                             st_res(A + (int64_t)r * lda + c, y);
+                            if (R) xr[ps][k] = y;
                             if (y != 0.0) key2 = min(key2, scan_key(r, pos - t0));
                         }
                     }
             }
-        }
+        };
+        column(0, std::true_type{});
+        for (int ch = 1; ch < nchunk; ++ch) column(ch, std::false_type{});
         // the workgroup's key (its barrier also orders every read of row p
         // before the row is rescaled)
         wgkey = wg_min_key(key2, s_keys);
