@@ -178,6 +178,17 @@ def test_cup_staircase(cup_lib):
     assert_same_cup(got, oracle.cup(A, p), "staircase")
 
 
+@pytest.mark.parametrize("m,n,r,p,seed", [(256, 17000, 40, 65521, 21), (200, 16600, 25, 3, 22)])
+def test_cup_staircase_wide(cup_lib, m, n, r, p, seed):
+    """Rank-deficient leaves wider than 256 x 64 columns: workgroups of the
+    sparse kernel own two column chunks, the second read from memory each
+    round (the first stays in registers)."""
+    A, piv = inputs.staircase(m, n, r, p, seed=seed)
+    got = run_cup(cup_lib, A, p)
+    assert got[1] == r and np.array_equal(got[3][:r], piv)
+    assert_same_cup(got, oracle.cup(A, p), f"wide staircase {m}x{n} p={p}")
+
+
 @pytest.mark.parametrize("p", [2, 3, 127])
 def test_cup_i8(cup_lib, p):
     for m, n, rank in [(70, 90, None), (300, 200, None), (256, 256, 100)]:
