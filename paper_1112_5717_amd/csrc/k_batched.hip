@@ -45,9 +45,9 @@
 // Layout: BW waves; wave w owns block rows w + BW k (k < 4); lane l holds
 // positions l + 64q (q < BQ) of those rows.  Three widths are compiled
 // (BQ = 2, 4, 8: n <= 128, 256, 512) so that a narrow matrix pays for its
-// own width only and leaves room for more workgroups per CU; the two wider
-// ones use 4 waves (blocks of 16 rows), so that two or three of their
-// workgroups fit a CU's registers and LDS together.  Inner
+// own width only and leaves room for more workgroups per CU; each uses 4
+// waves (blocks of 16 rows), so that two or more of its workgroups fit a
+// CU's registers and LDS together.  Inner
 // loops run over every register of the width without per-register or
 // per-row branches: positions past n and rows past m hold zeros, which the
 // updates leave zero.
@@ -65,14 +65,15 @@ namespace cup {
 
 namespace {
 
-// A workgroup of BW waves (a template parameter: 8 for the narrowest class,
-// 4 for the wider ones, whose registers allow two waves per SIMD at most, so
-// that two of their workgroups share a CU and one's pivot chain overlaps the
-// other's updates) factors blocks of BR = 4 BW rows and stages U rows in
-// chunks of CH = BW.
+// A workgroup of BW waves (a template parameter; 4 for every width class:
+// the wider ones' registers allow two waves per SIMD at most, and with 4
+// waves two or more workgroups share a CU, so that one's pivot chain
+// overlaps the others' updates; 8 waves measured slower for the narrow
+// classes too) factors blocks of BR = 4 BW rows and stages U rows in chunks
+// of CH = BW.
 constexpr int BK = 4;          // block rows per wave
 constexpr int BQMAX = 8;       // position registers per lane at most (n <= 512)
-constexpr int kClassWaves[3] = {8, 4, 4};  // BW of the width classes (n <= 128, <= 256, <= 512)
+constexpr int kClassWaves[3] = {4, 4, 4};  // BW of the width classes (n <= 128, <= 256, <= 512)
 
 // x - floor(x / p) p, in [-p, 2p) for |x| < 2^53 (the quotient from the
 // rounded reciprocal is off by at most one; the fma is exact).
