@@ -84,7 +84,10 @@ extern "C" {
 int cup_set_stream(void *hip_stream);
 
 /* Select the ffgemm form for later calls.  Returns -1 for an unknown form.
- * A forced form that p does not allow makes later calls return -5. */
+ * A forced form that p does not allow makes later calls return -5.  The
+ * initial form is CUP_FORM from the environment when it names one (auto,
+ * fp64, i8, i8limb, or 0..3), read once when the library is first used;
+ * otherwise CUP_FORM_AUTO. */
 int cup_set_form(int form);
 int cup_get_form(void);
 

@@ -72,9 +72,24 @@ void* noalloc_scratch()
     return g_scratch_ptr[dev];
 }
 
+// The initial form: CUP_FORM from the environment when it names one (auto,
+// fp64, i8, i8limb, or 0..3), else automatic.
+int env_form()
+{
+    const char* v = std::getenv("CUP_FORM");
+    if (!v) return FORM_AUTO;
+    static const char* const names[] = {"auto", "fp64", "i8", "i8limb"};
+    for (int f = 0; f < 4; ++f)
+        if (std::strcmp(v, names[f]) == 0) return f;
+    if (v[0] >= '0' && v[0] <= '3' && v[1] == 0) return v[0] - '0';
+    return FORM_AUTO;
+}
+
 Global& G()
 {
     static Global g;
+    static const bool form_set = (g.form = env_form(), true);  // once, before any use
+    (void)form_set;
     return g;
 }
 

@@ -93,3 +93,21 @@ def test_argument_validation_derived():
     assert lib.cup_set_winograd(9, 2048) == -1
     assert lib.cup_set_winograd(1, 64) == -2
     assert lib.cup_set_winograd(0, 2048) == 0
+
+
+def test_form_from_environment():
+    """CUP_FORM sets the initial form (names or digits); anything else leaves
+    the automatic choice.  Host-only: no GPU call is made."""
+    import subprocess
+    import sys
+    code = ("import ctypes, sys; from paper_1112_5717_amd import cup; "
+            "lib = ctypes.CDLL(cup.LIB_PATH); print(lib.cup_get_form())")
+    for value, want in (("fp64", 1), ("i8", 2), ("i8limb", 3), ("3", 3), ("auto", 0), ("bogus", 0), (None, 0)):
+        env = dict(os.environ)
+        env.pop("CUP_FORM", None)
+        if value is not None:
+            env["CUP_FORM"] = value
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                             cwd=ROOT, timeout=120)
+        assert out.returncode == 0, out.stderr[-2000:]
+        assert int(out.stdout.strip().splitlines()[-1]) == want, (value, out.stdout)
